@@ -1,0 +1,389 @@
+"""Counter-based synthetic master sets and disk images.
+
+Every byte is a pure function of (seed, stream name, counter), computed with
+int64 torch operations that never overflow, so the same call yields the same
+bytes on the CPU and on a GPU, and any sector can be regenerated alone (the
+oracle's sampled checks at full size rely on that).
+
+Data model (paper, Section 2 and Section 3.1): a sector is 512 bytes, a cluster
+is 8 consecutive sectors, master files start on a cluster boundary, and a
+deleted file's cluster may survive whole or with its first few sectors
+overwritten by a newer file.
+
+Disk image recipe (one seeded Bernoulli draw per 4 KiB cluster):
+  * master cluster: the 8 sectors of a random full cluster of a random master
+    file, copied cluster-aligned; a fraction of those get their first 1-3
+    sectors replaced by random bytes (partial overwrite);
+  * zero cluster: 4096 zero bytes;
+  * low-entropy cluster: one 4-byte pattern, drawn from a small pool, repeated;
+  * otherwise uniform random bytes (the paper's corpus was random data).
+Master files are uniform random sectors, plus duplicated sectors (the same
+bytes at the same or at another cluster position in another file) and, when
+configured, low-entropy sectors from the same pattern pool.
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Optional
+
+import torch
+
+SECTOR = 512
+WORDS_PER_SECTOR = SECTOR // 4
+CLUSTER = 8
+_M32 = 0xFFFFFFFF
+_TWO32 = 1 << 32
+
+KIND_RANDOM, KIND_MASTER, KIND_ZERO, KIND_LOW = 0, 1, 2, 3
+
+
+# --------------------------------------------------------------------------
+# counter-based word generator
+# --------------------------------------------------------------------------
+def _key(*parts) -> tuple:
+    d = hashlib.sha256(repr(parts).encode()).digest()
+    return tuple(int.from_bytes(d[4 * i:4 * i + 4], "little") for i in range(3))
+
+
+def _mix32(x: torch.Tensor) -> torch.Tensor:
+    # 32-bit integer finaliser (xorshift-multiply, multiplier 0x45d9f3b); the
+    # operand stays below 2^32 and the multiplier below 2^27, so every product
+    # fits in int64 without wrapping.
+    x = x ^ (x >> 16)
+    x = (x * 0x45D9F3B) & _M32
+    x = x ^ (x >> 16)
+    x = (x * 0x45D9F3B) & _M32
+    return x ^ (x >> 16)
+
+
+def words(key: tuple, idx: torch.Tensor) -> torch.Tensor:
+    """Pseudo-random 32-bit words (int64 values in [0, 2^32)) at counters idx >= 0."""
+    k0, k1, k2 = key
+    a = _mix32((idx & _M32) ^ k0)
+    b = _mix32((idx >> 32) ^ k1)
+    return _mix32(a ^ b ^ k2)
+
+
+def _words_to_bytes(w: torch.Tensor) -> torch.Tensor:
+    """int64 words in [0, 2^32), last dim k -> uint8 with last dim 4k (little-endian)."""
+    w32 = torch.where(w >= (1 << 31), w - _TWO32, w).to(torch.int32)
+    return w32.contiguous().view(torch.uint8)
+
+
+def _scalar_words(key: tuple, idx: int, n: int = 1) -> List[int]:
+    t = torch.arange(idx, idx + n, dtype=torch.int64)
+    return [int(v) for v in words(key, t)]
+
+
+def _threshold(p: float) -> int:
+    return int(round(p * _TWO32))
+
+
+# --------------------------------------------------------------------------
+# configurations
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class CarveConfig:
+    name: str
+    seed: int
+    n_master_sectors: int
+    n_files: int
+    equal_files: bool           # equal file sizes, else random cut points
+    n_disk_sectors: int
+    p_master_cluster: float
+    p_overwrite: float          # share of copied clusters with 1-3 sectors overwritten
+    p_zero: float
+    p_low_entropy: float
+    n_dup_same_tau: int
+    n_dup_other_tau: int
+    tail_bytes: int = 0         # bytes after the last full sector
+    low_pattern_pool: int = 4096
+    n_low_masters: int = 0      # master sectors holding a low-entropy pattern
+
+    @property
+    def image_bytes(self) -> int:
+        return self.n_disk_sectors * SECTOR + self.tail_bytes
+
+
+CONFIGS = {
+    # 8 files x 256 KiB, 64 MiB image (131072 sectors)
+    "tiny": CarveConfig("tiny", 1, 4096, 8, True, 131072, 0.05, 0.5, 0.02, 0.0, 8, 8),
+    # 1M master sectors (512 MiB), 8 GiB image (16M sectors)
+    "mid": CarveConfig("mid", 1, 1 << 20, 1000, False, 1 << 24, 0.01, 0.3, 0.05, 0.0, 524, 525),
+    # 16M master sectors (8 GiB), 64 GiB image (128M sectors)
+    "large": CarveConfig("large", 1, 1 << 24, 10000, False, 1 << 27, 0.001, 0.3, 0.0, 0.10,
+                         1024, 1024, n_low_masters=64),
+    # resident index of the served workload: 4M master sectors
+    "served": CarveConfig("served", 1, 1 << 22, 4000, False, 1 << 22, 0.02, 0.3, 0.02, 0.02,
+                          512, 512, n_low_masters=16),
+}
+
+
+def scaled(cfg: CarveConfig, n_master_sectors: int, n_disk_sectors: int, **kw) -> CarveConfig:
+    """A smaller copy of a configuration with the same recipe."""
+    n_files = kw.pop("n_files", max(1, min(cfg.n_files, n_master_sectors // 64)))
+    return replace(cfg, n_master_sectors=n_master_sectors, n_disk_sectors=n_disk_sectors,
+                   n_files=n_files, **kw)
+
+
+# --------------------------------------------------------------------------
+# master set
+# --------------------------------------------------------------------------
+@dataclass
+class MasterSet:
+    cfg: CarveConfig
+    sectors: torch.Tensor               # uint8 [M, 512]
+    file_offsets: List[int]             # CSR of sector ranges per file, len n_files+1
+    full_cluster_starts: torch.Tensor   # int64, first sector of every full master cluster
+    dup_dst: torch.Tensor               # int64, sorted; master sectors that copy another
+    dup_src: torch.Tensor               # int64, aligned with dup_dst
+    low_ids: torch.Tensor               # int64, sorted; low-entropy master sectors
+    low_pattern: torch.Tensor           # int64 pattern word per low_ids entry
+
+    @property
+    def n_files(self) -> int:
+        return len(self.file_offsets) - 1
+
+
+def _file_offsets(cfg: CarveConfig) -> List[int]:
+    m = cfg.n_master_sectors
+    if cfg.equal_files or cfg.n_files <= 1:
+        nf = max(1, cfg.n_files)
+        return [f * m // nf for f in range(nf + 1)]
+    k = _key(cfg.seed, cfg.name, "file-cuts")
+    cuts = words(k, torch.arange(cfg.n_files - 1, dtype=torch.int64)) % (m - 1) + 1
+    cuts = sorted(set(int(c) for c in cuts))
+    return [0] + cuts + [m]
+
+
+def _file_of(offsets: List[int], s: int) -> int:
+    lo, hi = 0, len(offsets) - 2
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if offsets[mid] <= s:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+def _pick_dups(cfg: CarveConfig, offsets: List[int]):
+    """Sector pairs (dst, src): dst in another file gets src's bytes."""
+    m = cfg.n_master_sectors
+    nf = len(offsets) - 1
+    dst_set, src_set, pairs = set(), set(), []
+    if nf < 2:
+        return pairs
+    for which, count in (("same", cfg.n_dup_same_tau), ("other", cfg.n_dup_other_tau)):
+        k = _key(cfg.seed, cfg.name, "dup", which)
+        ctr = 0
+        made = 0
+        while made < count and ctr < 64 * (count + 16):
+            w = _scalar_words(k, 4 * ctr, 4)
+            ctr += 1
+            src = w[0] % m
+            fs = _file_of(offsets, src)
+            tau = (src - offsets[fs]) % CLUSTER
+            if which == "other":
+                tau = (tau + 1 + w[1] % (CLUSTER - 1)) % CLUSTER
+            fd = w[2] % nf
+            if fd == fs:
+                continue
+            ln = offsets[fd + 1] - offsets[fd]
+            if ln <= tau:
+                continue
+            q = w[3] % ((ln - tau + CLUSTER - 1) // CLUSTER)
+            dst = offsets[fd] + CLUSTER * q + tau
+            if dst in dst_set or dst in src_set or src in dst_set:
+                continue
+            dst_set.add(dst)
+            src_set.add(src)
+            pairs.append((dst, src))
+            made += 1
+    return pairs
+
+
+def _pattern_pool_word(cfg: CarveConfig, p: torch.Tensor) -> torch.Tensor:
+    return words(_key(cfg.seed, cfg.name, "pattern-pool"), p)
+
+
+def master_words(ms: MasterSet, ids: torch.Tensor) -> torch.Tensor:
+    """Content words [n, 128] of master sectors ids (int64 tensor on any device)."""
+    cfg = ms.cfg
+    dev = ids.device
+    base = ids
+    if ms.dup_dst.numel():
+        dd, dsrc = ms.dup_dst.to(dev), ms.dup_src.to(dev)
+        pos = torch.searchsorted(dd, ids).clamp(max=dd.numel() - 1)
+        hit = dd[pos] == ids
+        base = torch.where(hit, dsrc[pos], ids)
+    ar = torch.arange(WORDS_PER_SECTOR, dtype=torch.int64, device=dev)
+    w = words(_key(cfg.seed, cfg.name, "master"), base[:, None] * WORDS_PER_SECTOR + ar[None, :])
+    if ms.low_ids.numel():
+        li, lp = ms.low_ids.to(dev), ms.low_pattern.to(dev)
+        pos = torch.searchsorted(li, ids).clamp(max=li.numel() - 1)
+        hit = li[pos] == ids
+        w = torch.where(hit[:, None], lp[pos][:, None], w)
+    return w
+
+
+def master_sectors(ms: MasterSet, ids: torch.Tensor) -> torch.Tensor:
+    """Bytes [n, 512] of master sectors ids."""
+    return _words_to_bytes(master_words(ms, ids))
+
+
+def master_set(cfg: CarveConfig, device="cpu", chunk: int = 1 << 18) -> MasterSet:
+    offsets = _file_offsets(cfg)
+    off = torch.tensor(offsets, dtype=torch.int64)
+    lens = off[1:] - off[:-1]
+    ncl = lens // CLUSTER
+    total = int(ncl.sum())
+    first = torch.cumsum(ncl, 0) - ncl
+    starts = (torch.repeat_interleave(off[:-1], ncl)
+              + CLUSTER * (torch.arange(total, dtype=torch.int64) - torch.repeat_interleave(first, ncl)))
+    pairs = sorted(_pick_dups(cfg, offsets))
+    dup_dst = torch.tensor([p[0] for p in pairs], dtype=torch.int64)
+    dup_src = torch.tensor([p[1] for p in pairs], dtype=torch.int64)
+    low_ids = torch.empty(0, dtype=torch.int64)
+    low_pat = torch.empty(0, dtype=torch.int64)
+    if cfg.n_low_masters:
+        k = _key(cfg.seed, cfg.name, "low-masters")
+        taken = set(int(v) for v in dup_dst) | set(int(v) for v in dup_src)
+        ids, ctr = [], 0
+        while len(ids) < cfg.n_low_masters and ctr < 64 * cfg.n_low_masters:
+            s = _scalar_words(k, ctr)[0] % cfg.n_master_sectors
+            ctr += 1
+            if s not in taken:
+                taken.add(s)
+                ids.append(s)
+        ids.sort()
+        low_ids = torch.tensor(ids, dtype=torch.int64)
+        sel = words(_key(cfg.seed, cfg.name, "low-master-pick"), low_ids) % cfg.low_pattern_pool
+        low_pat = _pattern_pool_word(cfg, sel)
+    ms = MasterSet(cfg, torch.empty(0), offsets, starts, dup_dst, dup_src, low_ids, low_pat)
+    m = cfg.n_master_sectors
+    out = torch.empty((m, SECTOR), dtype=torch.uint8, device=device)
+    for s in range(0, m, chunk):
+        e = min(m, s + chunk)
+        out[s:e] = master_sectors(ms, torch.arange(s, e, dtype=torch.int64, device=device))
+    ms.sectors = out
+    return ms
+
+
+# --------------------------------------------------------------------------
+# disk images
+# --------------------------------------------------------------------------
+@dataclass
+class DiskImage:
+    cfg: CarveConfig
+    image_id: int
+    data: torch.Tensor                  # uint8 [n_disk_sectors*512 + tail_bytes]
+    planted_clusters: torch.Tensor      # int64 disk cluster ids holding a master cluster
+    planted_src: torch.Tensor           # int64 first master sector of the copied cluster
+    planted_overwrite: torch.Tensor     # int64 number of leading sectors overwritten (0-3)
+    kind_counts: dict = field(default_factory=dict)
+
+
+def _cluster_plan(cfg: CarveConfig, ms: MasterSet, c: torch.Tensor, image_id: int):
+    """Kind, source master sector and overwrite count for disk clusters c."""
+    kk = lambda name: _key(cfg.seed, cfg.name, image_id, name)  # noqa: E731
+    u = words(kk("kind"), c)
+    t_m = _threshold(cfg.p_master_cluster)
+    t_z = t_m + _threshold(cfg.p_zero)
+    t_l = t_z + _threshold(cfg.p_low_entropy)
+    kind = torch.full_like(c, KIND_RANDOM)
+    kind = torch.where(u < t_l, torch.full_like(c, KIND_LOW), kind)
+    kind = torch.where(u < t_z, torch.full_like(c, KIND_ZERO), kind)
+    n_full = ms.full_cluster_starts.numel()
+    if n_full:
+        kind = torch.where(u < t_m, torch.full_like(c, KIND_MASTER), kind)
+    fcs = ms.full_cluster_starts.to(c.device)
+    src = fcs[words(kk("src"), c) % max(n_full, 1)] if n_full else torch.zeros_like(c)
+    ow = words(kk("overwrite"), c) < _threshold(cfg.p_overwrite)
+    r = torch.where(ow, 1 + words(kk("overwrite-count"), c) % 3, torch.zeros_like(c))
+    pat = _pattern_pool_word(cfg, words(kk("pattern"), c) % cfg.low_pattern_pool)
+    return kind, src, r, pat
+
+
+def disk_sectors(cfg: CarveConfig, ms: MasterSet, ids: torch.Tensor, image_id: int = 0) -> torch.Tensor:
+    """Bytes [n, 512] of disk sectors ids of image image_id (any device)."""
+    dev = ids.device
+    c = ids // CLUSTER
+    i = ids % CLUSTER
+    kind, src, r, pat = _cluster_plan(cfg, ms, c, image_id)
+    ar = torch.arange(WORDS_PER_SECTOR, dtype=torch.int64, device=dev)
+    w = words(_key(cfg.seed, cfg.name, image_id, "random"), ids[:, None] * WORDS_PER_SECTOR + ar[None, :])
+    w = torch.where((kind == KIND_ZERO)[:, None], torch.zeros_like(w), w)
+    w = torch.where((kind == KIND_LOW)[:, None], pat[:, None].expand_as(w), w)
+    use = (kind == KIND_MASTER) & (i >= r)
+    if bool(use.any()):
+        w[use] = master_words(ms, (src + i)[use])
+    return _words_to_bytes(w)
+
+
+def disk_image(cfg: CarveConfig, ms: MasterSet, device="cpu", image_id: int = 0,
+               chunk: int = 1 << 18, out: Optional[torch.Tensor] = None) -> DiskImage:
+    n = cfg.n_disk_sectors
+    nbytes = n * SECTOR + cfg.tail_bytes
+    if out is None:
+        out = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    assert out.numel() >= nbytes
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        ids = torch.arange(s, e, dtype=torch.int64, device=device)
+        out[s * SECTOR:e * SECTOR] = disk_sectors(cfg, ms, ids, image_id).reshape(-1)
+    if cfg.tail_bytes:
+        tw = words(_key(cfg.seed, cfg.name, image_id, "tail"),
+                   torch.arange((cfg.tail_bytes + 3) // 4, dtype=torch.int64, device=device))
+        out[n * SECTOR:nbytes] = _words_to_bytes(tw)[:cfg.tail_bytes]
+    # ground truth of the planted clusters
+    pc, ps, pr = [], [], []
+    counts = {KIND_RANDOM: 0, KIND_MASTER: 0, KIND_ZERO: 0, KIND_LOW: 0}
+    n_cl = n // CLUSTER
+    for s in range(0, n_cl, 1 << 22):
+        e = min(n_cl, s + (1 << 22))
+        c = torch.arange(s, e, dtype=torch.int64, device=device)
+        kind, src, r, _ = _cluster_plan(cfg, ms, c, image_id)
+        for kd in counts:
+            counts[kd] += int((kind == kd).sum())
+        sel = kind == KIND_MASTER
+        pc.append(c[sel].cpu())
+        ps.append(src[sel].cpu())
+        pr.append(r[sel].cpu())
+    cat = lambda xs: torch.cat(xs) if xs else torch.empty(0, dtype=torch.int64)  # noqa: E731
+    return DiskImage(cfg, image_id, out[:nbytes], cat(pc), cat(ps), cat(pr), counts)
+
+
+# --------------------------------------------------------------------------
+# batched and served workloads
+# --------------------------------------------------------------------------
+def batch_image_specs(seed: int = 1, n_images: int = 256, min_bytes: int = 1 << 20,
+                      max_bytes: int = 1 << 30, max_hit: float = 0.05):
+    """Sizes log-uniform in [min_bytes, max_bytes] rounded to 4 KiB, hit rate uniform in [0, max_hit]."""
+    k = _key(seed, "batch-specs")
+    w = words(k, torch.arange(2 * n_images, dtype=torch.int64)).double() / _TWO32
+    lo, hi = math.log(min_bytes), math.log(max_bytes)
+    specs = []
+    for i in range(n_images):
+        size = int(math.exp(lo + (hi - lo) * float(w[2 * i])))
+        size = max(4096, (size // 4096) * 4096)
+        specs.append((size // SECTOR, max_hit * float(w[2 * i + 1])))
+    return specs
+
+
+def served_job_specs(seed: int = 1, rate: float = 2000.0, duration: float = 60.0,
+                     min_bytes: int = 64 << 10, max_bytes: int = 256 << 20,
+                     any_tau_below: int = 1 << 20):
+    """Poisson arrivals: (arrival time s, size bytes (multiple of 512), tau_any flag)."""
+    n_max = int(rate * duration * 1.5) + 64
+    k = _key(seed, "served-specs")
+    w = (words(k, torch.arange(2 * n_max, dtype=torch.int64)).double() + 0.5) / _TWO32
+    gaps = -torch.log(w[0::2]) / rate
+    t = torch.cumsum(gaps, 0)
+    n = int((t < duration).sum())
+    lo, hi = math.log(min_bytes), math.log(max_bytes)
+    sizes = torch.exp(lo + (hi - lo) * w[1::2][:n])
+    sizes = (sizes / SECTOR).floor().to(torch.int64).clamp(min=1) * SECTOR
+    return [(float(t[i]), int(sizes[i]), int(sizes[i]) < any_tau_below) for i in range(n)]

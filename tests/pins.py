@@ -1,0 +1,205 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by arithmetic.
+
+Each check takes the oracle's ctypes library as an argument, so the mutation
+test can run the same checks against deliberately broken builds of the oracle.
+Every check raises AssertionError on failure.
+"""
+from __future__ import annotations
+
+import os
+import random
+
+import numpy as np
+
+import oracle
+from oracle import spec
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+MOD = 1 << 64
+SECTOR = 512
+
+
+def golden_vectors():
+    out = []
+    with open(os.path.join(GOLDEN, "djb2_eq1_vectors.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            hx, val = line.split()[:2]
+            out.append((b"" if hx == "-" else bytes.fromhex(hx), int(val)))
+    return out
+
+
+# ---------------------------------------------------------------- signature
+def pin_golden(lib):
+    """Hand-worked values of Eq. (1)."""
+    for data, want in golden_vectors():
+        got = oracle.djb2(data, lib=lib)
+        assert got == want, (data, got, want)
+
+
+def pin_constant_sectors(lib):
+    """A sector of 512 copies of byte c has the geometric-series value
+    5381*33^512 + c*(33^512 - 1)/32 (mod 2^64); c = 0 is 5381*33^512."""
+    p = 33 ** 512
+    for c in (0, 1, 0x20, 0x7F, 0x80, 0xFF):
+        want = (5381 * p + c * ((p - 1) // 32)) % MOD
+        got = oracle.djb2(bytes([c]) * SECTOR, lib=lib)
+        assert got == want, (c, hex(got), hex(want))
+
+
+def pin_closed_form(lib, n=64, seed=7):
+    """Random sectors: the oracle equals the unrolled closed form of Eq. (1)."""
+    rng = random.Random(seed)
+    for _ in range(n):
+        s = bytes(rng.getrandbits(8) for _ in range(SECTOR))
+        assert oracle.djb2(s, lib=lib) == spec.djb2_closed(s)
+
+
+def pin_mod32(lib, n=64, seed=8):
+    """33 = 1 (mod 32), so h mod 32 = (5381 + sum of bytes) mod 32."""
+    rng = random.Random(seed)
+    for _ in range(n):
+        s = bytes(rng.getrandbits(8) for _ in range(SECTOR))
+        assert oracle.djb2(s, lib=lib) % 32 == (5381 + sum(s)) % 32
+
+
+def pin_collisions(lib, n=32, seed=9):
+    """(a, b) -> (a+1, b-33) at adjacent positions keeps the signature."""
+    rng = random.Random(seed)
+    done = 0
+    while done < n:
+        s = bytes(rng.getrandbits(8) for _ in range(SECTOR))
+        i = rng.randrange(SECTOR - 1)
+        if s[i] > 254 or s[i + 1] < 33:
+            continue
+        t = spec.collide(s, i)
+        assert t != s
+        assert oracle.djb2(t, lib=lib) == oracle.djb2(s, lib=lib)
+        done += 1
+
+
+def pin_crafted(lib, seed=10):
+    """Sectors crafted in base 33 reach any chosen signature."""
+    rng = random.Random(seed)
+    for target in (0, 1, 5381, MOD - 1, rng.getrandbits(64), rng.getrandbits(64)):
+        prefix = bytes(rng.getrandbits(8) for _ in range(rng.randrange(0, 400)))
+        assert oracle.djb2(spec.craft_sector(prefix, target), lib=lib) == target
+
+
+def pin_batch_signatures(lib, seed=11):
+    """The threaded per-sector routine agrees with the one-sector routine."""
+    rng = np.random.default_rng(seed)
+    secs = rng.integers(0, 256, size=(257, SECTOR), dtype=np.uint8)
+    got = oracle.sector_signatures(secs, threads=3, lib=lib)
+    for i in range(0, 257, 16):
+        assert int(got[i]) == spec.djb2_closed(secs[i].tobytes())
+
+
+SIGNATURE_PINS = [pin_golden, pin_constant_sectors, pin_closed_form, pin_mod32, pin_collisions,
+                  pin_crafted, pin_batch_signatures]
+
+
+# ----------------------------------------------------------- sets of results
+def small_case(seed=3, n_disk=700, tail=77):
+    """A tiny master set with uneven file sizes and a disk image with planted
+    clusters, partial overwrites, duplicates, zero sectors and crafted
+    signature collisions, as raw bytes."""
+    rng = random.Random(seed)
+    sizes = [37, 8, 21, 64, 3, 50]                 # sectors per file, not multiples of 8
+    masters = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(sum(sizes))]
+    offsets = [0]
+    for s in sizes:
+        offsets.append(offsets[-1] + s)
+    # duplicates: same bytes at the same and at another cluster position
+    masters[offsets[3] + 9] = masters[offsets[0] + 1]      # tau 1 == tau 1
+    masters[offsets[5] + 4] = masters[offsets[0] + 1]      # tau 4 != tau 1
+    masters[offsets[2] + 5] = masters[offsets[1] + 2]      # tau 5 != tau 2
+    disk = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(n_disk)]
+    truth = []
+    for c in range(n_disk // 8):
+        u = rng.random()
+        if u < 0.3:
+            f = rng.randrange(len(sizes))
+            ncl = sizes[f] // 8
+            if ncl == 0:
+                continue
+            q = rng.randrange(ncl)
+            r = rng.choice([0, 0, 1, 2, 3])
+            for i in range(r, 8):
+                disk[8 * c + i] = masters[offsets[f] + 8 * q + i]
+                truth.append((8 * c + i, f, 8 * q + i))
+        elif u < 0.35:
+            for i in range(8):
+                disk[8 * c + i] = bytes(SECTOR)
+        elif u < 0.45:
+            # crafted collision of a master sector at the right position, near the end of
+            # the sector: flagged, not equal
+            f = rng.randrange(len(sizes))
+            k = rng.randrange(sizes[f])
+            i = k % 8
+            src = masters[offsets[f] + k]
+            pos = next(p for p in range(SECTOR - 2, 0, -1) if src[p] <= 254 and src[p + 1] >= 33)
+            disk[8 * c + i] = spec.collide(src, pos)
+    image = b"".join(disk) + bytes(rng.getrandbits(8) for _ in range(tail))
+    return image, masters, offsets, truth
+
+
+def _as_tuples(arr):
+    return [(int(r["disk_sector"]), int(r["file_id"]), int(r["sector_in_file"])) for r in arr]
+
+
+def pin_sets_vs_definition(lib, seed=3):
+    """Flags equal the definition computed with the closed form and Python sets;
+    confirmed matches equal a pure-Python all-pairs byte comparison; the C
+    brute force agrees; every planted sector is flagged and confirmed."""
+    image, masters, offsets, truth = small_case(seed)
+    mflat = b"".join(masters)
+    for tau0, any_tau in ((0, False), (3, False), (7, False), (0, True)):
+        ix = oracle.Index(np.frombuffer(mflat, np.uint8), offsets, threads=2, lib=lib)
+        flags = [int(x) for x in ix.flag_image(np.frombuffer(image, np.uint8), tau0, any_tau, threads=2)]
+        want_flags = spec.flagged_by_definition(image, masters, offsets, tau0, any_tau)
+        assert flags == want_flags, (tau0, any_tau)
+        conf = _as_tuples(ix.confirm_image(np.frombuffer(image, np.uint8), flags, tau0, any_tau))
+        want = spec.brute_force_matches(image, masters, offsets, tau0, any_tau)
+        assert conf == want, (tau0, any_tau)
+        brute = _as_tuples(oracle.bruteforce(np.frombuffer(image, np.uint8), np.frombuffer(mflat, np.uint8),
+                                             offsets, tau0, any_tau, threads=2, lib=lib))
+        assert brute == want
+        assert set(j for j, _, _ in want) <= set(flags)
+        if tau0 == 0 and not any_tau:
+            assert set(truth) <= set(want)
+            # crafted collisions exist and are flagged without being confirmed
+            assert len(set(flags) - set(j for j, _, _ in want)) > 0
+
+
+def pin_edges(lib):
+    """Empty image, sub-sector image, empty master set, all-zero disk against a
+    zero master sector, and a master whose signature is 0."""
+    rng = random.Random(12)
+    masters = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(9)]
+    ix = oracle.Index(np.frombuffer(b"".join(masters), np.uint8), [0, 9], lib=lib)
+    assert ix.flag_image(np.zeros(0, np.uint8)).size == 0
+    assert ix.flag_image(np.frombuffer(masters[0][:511], np.uint8)).size == 0
+    empty = oracle.Index(np.zeros(0, np.uint8), [0], lib=lib)
+    assert empty.flag_image(np.frombuffer(b"".join(masters), np.uint8)).size == 0
+    # zero master sector at cluster position 2: every zero disk sector at position 2 is flagged
+    zm = list(masters)
+    zm[2] = bytes(SECTOR)
+    zix = oracle.Index(np.frombuffer(b"".join(zm), np.uint8), [0, 9], lib=lib)
+    got = [int(x) for x in zix.flag_image(np.zeros(64 * SECTOR, np.uint8))]
+    assert got == [j for j in range(64) if j % 8 == 2]
+    got = [int(x) for x in zix.flag_image(np.zeros(64 * SECTOR, np.uint8), any_tau=True)]
+    assert got == list(range(64))
+    # a master sector whose signature is 0 is matched like any other
+    crafted = spec.craft_sector(b"sig-zero", 0)
+    cm = list(masters)
+    cm[5] = crafted
+    cix = oracle.Index(np.frombuffer(b"".join(cm), np.uint8), [0, 9], lib=lib)
+    disk = bytearray(rng.getrandbits(8) for _ in range(16 * SECTOR))
+    disk[13 * SECTOR:14 * SECTOR] = crafted
+    assert [int(x) for x in cix.flag_image(np.frombuffer(bytes(disk), np.uint8))] == [13]
+
+
+SET_PINS = [pin_sets_vs_definition, pin_edges]
+ALL_PINS = SIGNATURE_PINS + SET_PINS
