@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Disk-scan throughput of the carving path on one MI355X.
+
+A step is one pass of the whole hot path over a device-resident disk image:
+scan_image (sector loads, djb2-64 signatures, cluster positions, index probe,
+ordered compaction of the flagged ids), flagged_sectors (ids into a device
+buffer) and confirm_matches (byte comparison of every flagged sector with its
+candidate master sectors, ordered records into a device buffer). The master
+index is built once, before timing.
+
+Prints one JSON line. `value` is image GB/s (1e9 B) over the timed steps;
+`roofline` prices the signature/probe kernel's algorithmic bytes (512 B read
+per sector + 1/8 B of flag bitmap written) against 8 TB/s of HBM3E, with its
+duration from HIP events recorded on the stream it runs on; `cpu_baseline`
+times the CPU oracle on a bounded sample of the same image.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "disk GB/s scanned (bit-exact flags) and % HBM roofline; p99 latency served"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SECTOR_ALG = 512 + 1.0 / 8.0   # read the sector once, write one flag bit
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ms, img, n_sectors: int, target_s: float):
+    """The oracle, as it is, on the host cores: signatures + membership + flag
+    list over the first sectors of the same image (the master sort is timed
+    apart and excluded)."""
+    import oracle
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    ix = oracle.Index(ms.sectors.cpu().numpy(), ms.file_offsets, threads=threads)
+    t_sort = time.perf_counter() - t0
+    probe = min(n_sectors, 1 << 17)               # 64 MiB to size the sample
+    host = img.data[:probe * 512].cpu().numpy()
+    t0 = time.perf_counter()
+    ix.flag_image(host, threads=threads)
+    rate = probe / max(time.perf_counter() - t0, 1e-6)
+    n = int(min(n_sectors, max(probe, rate * target_s)))
+    n -= n % 8
+    host = img.data[:n * 512].cpu().numpy()
+    t0 = time.perf_counter()
+    flags = ix.flag_image(host, threads=threads)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(n * 512 / dt / 1e9, 4),
+        "unit": "GB/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"first {n} sectors ({n * 512 / 2**30:.2f} GiB) of the benchmark image, {len(flags)} flagged; "
+                   f"signatures + sorted-array membership + flag list in {dt:.2f} s on {threads} threads "
+                   f"({cpu_model()}); master sort {t_sort:.2f} s excluded"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="mid", choices=["tiny", "mid", "large"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the scan has no cross-GPU step, and only --gpus 1 is supported "
+              "(sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_0901_1307_amd import carve
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = synth.CONFIGS[args.config]
+    t0 = time.perf_counter()
+    log(f"[bench] generating {cfg.name}: {cfg.n_master_sectors} master sectors, {cfg.n_disk_sectors} disk sectors")
+    ms = synth.master_set(cfg, device="cuda")
+    img = synth.disk_image(cfg, ms, device="cuda")
+    torch.cuda.synchronize()
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f} s; building the index")
+    t0 = time.perf_counter()
+    idx = carve.build_master_index(ms.sectors, ms.file_offsets)
+    log(f"[bench] index built in {time.perf_counter() - t0:.2f} s: {idx.stats()}")
+
+    n_sectors = cfg.n_disk_sectors
+    image_bytes = img.data.numel()
+    flag_out = torch.empty(n_sectors, dtype=torch.int64, device="cuda")
+    sc = carve.scan_image(idx, img.data)
+    n_flag = carve.flagged_sectors(sc, flag_out).numel()
+    n_match = carve.confirm_matches(idx, sc, torch.empty(16 * max(1, 4 * n_flag), dtype=torch.uint8, device="cuda"))
+    match_out = torch.empty(16 * max(1, 2 * n_match + 1024), dtype=torch.uint8, device="cuda")
+    log(f"[bench] {n_flag} flagged, {n_match} confirmed")
+
+    def step():
+        carve.scan_image(idx, img.data, scan=sc)
+        nf = carve.flagged_sectors(sc, flag_out).numel()
+        nm = carve.confirm_matches(idx, sc, match_out)
+        return nf, nm
+
+    for _ in range(args.warmup):
+        step()
+    sc.set_timing(True)
+    kernel_ms = []
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        nf, nm = step()
+        assert (nf, nm) == (n_flag, n_match)
+        kernel_ms.append(sc.kernel_ms())
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    sc.set_timing(False)
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (event), wall {wall * 1e3 / args.steps:.3f} ms/step")
+
+    value = image_bytes / (ms_per_step * 1e-3) / 1e9
+    k_avg = sum(kernel_ms) / len(kernel_ms)
+    achieved = n_sectors * BYTES_PER_SECTOR_ALG / (k_avg * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{cfg.name}: {image_bytes / 2**30:.0f} GiB device-resident disk image "
+                         f"({n_sectors} sectors of 512 B) against {cfg.n_master_sectors} master sectors "
+                         f"in {len(ms.file_offsets) - 1} files, djb2-64, per-cluster positions"),
+            "image_bytes": image_bytes,
+            "n_sectors": n_sectors,
+            "n_master_sectors": cfg.n_master_sectors,
+            "seed": cfg.seed,
+        },
+        "sectors_per_s": round(n_sectors / (ms_per_step * 1e-3)),
+        "hbm_frac_of_value": round(value / HBM_PEAK_GBS, 4),
+        "flagged": n_flag,
+        "confirmed": n_match,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_scan<kFlags> (signature + probe)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel_ms": round(k_avg, 4),
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(ms, img, n_sectors, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

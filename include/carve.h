@@ -1,0 +1,167 @@
+/*
+ * carve.h -- C ABI of the MI355X (gfx950) hash-based sector carving library.
+ *
+ * The method (Collange, Dandass, Daumas, Defour, "Using Graphics Processors
+ * for Parallelizing Hash-based Data Carving"):
+ *   - Section 2: a sector is 512 bytes and a cluster is 8 consecutive sectors;
+ *     files of interest start on a cluster and occupy whole sectors.
+ *   - Eq. (1), Section 2.2, with the 64-bit accumulator of Section 4: the
+ *     signature of a sector is djb2, h = 5381, h = h*33 + s for each byte s
+ *     (unsigned, address order), modulo 2^64.
+ *   - Section 3.1: the signatures of the master ("known") sectors at cluster
+ *     position tau form the set S_tau; a disk sector at position tau is
+ *     flagged when its signature is in S_tau, and flagged sectors are
+ *     confirmed by a byte-for-byte comparison with the master sectors of the
+ *     same signature.
+ *
+ * Conventions for every entry point:
+ *   - Return value: CARVE_OK (0) or a negative carve_status. On failure,
+ *     carve_last_error() returns a message for the calling thread.
+ *   - "device" pointers are HIP device memory of the current device (for
+ *     example a torch tensor's data_ptr()); "host" pointers are host memory;
+ *     "host or device" accepts either.
+ *   - Byte buffers of sectors must be 16-byte aligned.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Sector ids are relative to the start of the buffer passed in.
+ *   - Nothing here allocates or frees the caller's buffers.
+ */
+#ifndef CARVE_H
+#define CARVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct carve_index carve_index; /* resident master-signature index */
+typedef struct carve_scan carve_scan;   /* result buffers of one scan      */
+
+typedef enum {
+  CARVE_OK = 0,
+  CARVE_EINVAL = -1,       /* bad argument: null/misaligned pointer, bad enum, bad sizes */
+  CARVE_ENOMEM = -2,       /* device or host allocation failed */
+  CARVE_ETRUNC = -3,       /* output capacity too small; *n_out holds the full count */
+  CARVE_EDEVICE = -4,      /* a HIP call failed */
+  CARVE_EUNSUPPORTED = -5  /* valid request this build does not handle */
+} carve_status;
+
+typedef enum {
+  CARVE_SIG_DJB2_64 = 0    /* Eq. (1), 64-bit accumulator (Section 4) */
+} carve_sig_kind;
+
+typedef enum {
+  CARVE_TAU_PER_CLUSTER = 0, /* sector j matches S_tau with tau = (j + tau0) mod 8 (Section 3.1) */
+  CARVE_TAU_ANY = 1          /* sector j matches a master sector at any cluster position */
+} carve_tau_mode;
+
+typedef struct {
+  uint32_t sig_kind;       /* carve_sig_kind; 0 = djb2-64 */
+  float max_load;          /* hash-table load factor ceiling in (0, 0.9]; 0 = 0.5 */
+  uint32_t reserved[6];    /* must be zero */
+} carve_index_params;
+
+typedef struct {
+  uint64_t disk_sector;    /* flagged disk sector id */
+  uint32_t file_id;        /* master file index */
+  uint32_t sector_in_file; /* sector index inside that file */
+} carve_match;             /* 16 bytes */
+
+typedef struct {
+  uint64_t n_master_sectors;
+  uint64_t n_unique_signatures;  /* distinct signatures (any position) */
+  uint64_t n_buckets;            /* 16-slot buckets of the hash table */
+  uint64_t n_overflow_keys;      /* keys stored outside their home bucket */
+  uint64_t device_bytes;         /* device memory owned by the index */
+} carve_index_stats;
+
+/*
+ * build_master_index -- build the resident index of the master sectors
+ * (Section 3.1, the tables S_tau and their linear-probing insertion, Eq. (3)).
+ *   master_sectors      device, 16-B aligned, file_sector_offsets[n_files]
+ *                       packed 512-byte sectors, file after file. BORROWED:
+ *                       confirm_matches reads it, so it must stay valid and
+ *                       unchanged until free_index.
+ *   file_sector_offsets host, n_files+1 ascending values, [0] == 0; file f
+ *                       owns sectors [off[f], off[f+1]) and its sector k sits
+ *                       at cluster position k mod 8. A file's trailing
+ *                       partial sector is not part of this array.
+ *   params              host or NULL for defaults.
+ *   stream              all work is enqueued on it; the call returns after
+ *                       the build completes (it synchronizes the stream).
+ *   out                 receives the new index (owned; release with free_index).
+ * Errors: EINVAL (null out, misaligned or null masters with sectors > 0,
+ * offsets not ascending or not starting at 0, bad params), EUNSUPPORTED
+ * (2^32-1 or more master sectors, unknown sig_kind), ENOMEM, EDEVICE.
+ */
+int build_master_index(const void* master_sectors, const uint64_t* file_sector_offsets, uint32_t n_files,
+                       const carve_index_params* params, void* stream, carve_index** out);
+
+/*
+ * scan_image -- signature, cluster position, index probe and flag compaction
+ * of every whole sector of a device-resident image (Section 3.2 and the
+ * filter of Section 3.1). Asynchronous: enqueued on `stream`.
+ *   idx        index from build_master_index (not modified; several scans may
+ *              use one index concurrently on different streams).
+ *   image      device, 16-B aligned, n_bytes bytes. BORROWED until the scan is
+ *              freed or reused. The trailing n_bytes % 512 bytes are ignored.
+ *   tau0       cluster position of the image's first sector (0..7).
+ *   tau_mode   carve_tau_mode.
+ *   io         in: NULL to create a scan object, or a scan object to reuse
+ *              (its previous results are discarded; it must not be in use on
+ *              another stream). out: the scan object (release with free_scan).
+ * Errors: EINVAL (null idx/io, null or misaligned image with n_bytes >= 512,
+ * tau0 > 7, bad tau_mode), ENOMEM, EDEVICE.
+ */
+int scan_image(const carve_index* idx, const void* image, uint64_t n_bytes, uint32_t tau0, uint32_t tau_mode,
+               void* stream, carve_scan** io);
+
+/*
+ * flagged_sectors -- ascending ids of the flagged sectors of the last scan
+ * (the match buffer of Section 3.2). Synchronizes the scan's stream.
+ *   out    host or device, room for `cap` ids (may be NULL when cap == 0).
+ *   n_out  host; receives the number of flagged sectors.
+ * Returns ETRUNC (after copying the first cap ids) when the count exceeds cap.
+ */
+int flagged_sectors(carve_scan* sc, uint64_t* out, uint64_t cap, uint64_t* n_out);
+
+/*
+ * confirm_matches -- byte-for-byte confirmation of the flagged sectors of the
+ * last scan (Section 3.1): every (flagged disk sector, master sector) pair
+ * with equal signatures, a compatible cluster position and equal 512 bytes,
+ * ordered by (disk_sector, file_id, sector_in_file), each pair once.
+ * Runs on the scan's stream and synchronizes it.
+ *   out    host or device, room for `cap` records (may be NULL when cap == 0).
+ *   n_out  host; receives the number of confirmed pairs.
+ * Returns ETRUNC (after copying the first cap records) when it exceeds cap.
+ */
+int confirm_matches(const carve_index* idx, carve_scan* sc, carve_match* out, uint64_t cap, uint64_t* n_out);
+
+/*
+ * sector_signatures -- djb2-64 signature (Eq. (1), Section 4) of each of
+ * n_sectors packed sectors. sectors: device, 16-B aligned; sigs: device,
+ * n_sectors values. Asynchronous on `stream`.
+ */
+int sector_signatures(const void* sectors, uint64_t n_sectors, uint64_t* sigs, void* stream);
+
+/* index_stats -- sizes of a built index (host struct). */
+int index_stats(const carve_index* idx, carve_index_stats* out);
+
+/* scan_set_timing -- when enable != 0, later scan_image calls bracket the
+ * signature/probe kernel with HIP events on the scan's stream. */
+int scan_set_timing(carve_scan* sc, int enable);
+
+/* scan_kernel_ms -- duration of the signature/probe kernel of the last timed
+ * scan, in milliseconds (synchronizes on its end event). EINVAL if the last
+ * scan was not timed. */
+int scan_kernel_ms(carve_scan* sc, float* ms);
+
+void free_index(carve_index* idx);  /* NULL is a no-op; the caller ensures no scan is running */
+void free_scan(carve_scan* sc);     /* NULL is a no-op; waits for the scan's stream */
+const char* carve_last_error(void); /* message of this thread's last failure, "" if none */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CARVE_H */

@@ -1,0 +1,262 @@
+"""Python binding of the carving library's C ABI (include/carve.h).
+
+Argument marshalling only: every step of the scan runs in the HIP kernels of
+libcarve.so. torch provides device memory and the current HIP stream. There
+is no CPU fallback: without the built library on a GPU, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcarve.so")
+SECTOR = 512
+
+CARVE_OK, CARVE_EINVAL, CARVE_ENOMEM, CARVE_ETRUNC, CARVE_EDEVICE, CARVE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CARVE_SIG_DJB2_64 = 0
+CARVE_TAU_PER_CLUSTER, CARVE_TAU_ANY = 0, 1
+
+MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4")])
+
+EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_matches", "sector_signatures",
+           "index_stats", "scan_set_timing", "scan_kernel_ms", "free_index", "free_scan", "carve_last_error")
+
+
+class CarveError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"carve error {code}: {msg}")
+        self.code = code
+
+
+class _IndexParams(ctypes.Structure):
+    _fields_ = [("sig_kind", ctypes.c_uint32), ("max_load", ctypes.c_float), ("reserved", ctypes.c_uint32 * 6)]
+
+
+class _IndexStats(ctypes.Structure):
+    _fields_ = [("n_master_sectors", ctypes.c_uint64), ("n_unique_signatures", ctypes.c_uint64),
+                ("n_buckets", ctypes.c_uint64), ("n_overflow_keys", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """The compiled library; raises if it has not been built."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_0901_1307_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, U64, U32, I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    PU64 = ctypes.POINTER(ctypes.c_uint64)
+    lib.build_master_index.restype = I32
+    lib.build_master_index.argtypes = [P, P, U32, ctypes.POINTER(_IndexParams), P, PP]
+    lib.scan_image.restype = I32
+    lib.scan_image.argtypes = [P, P, U64, U32, U32, P, PP]
+    lib.flagged_sectors.restype = I32
+    lib.flagged_sectors.argtypes = [P, P, U64, PU64]
+    lib.confirm_matches.restype = I32
+    lib.confirm_matches.argtypes = [P, P, P, U64, PU64]
+    lib.sector_signatures.restype = I32
+    lib.sector_signatures.argtypes = [P, U64, P, P]
+    lib.index_stats.restype = I32
+    lib.index_stats.argtypes = [P, ctypes.POINTER(_IndexStats)]
+    lib.scan_set_timing.restype = I32
+    lib.scan_set_timing.argtypes = [P, I32]
+    lib.scan_kernel_ms.restype = I32
+    lib.scan_kernel_ms.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
+    lib.free_index.restype = None
+    lib.free_index.argtypes = [P]
+    lib.free_scan.restype = None
+    lib.free_scan.argtypes = [P]
+    lib.carve_last_error.restype = ctypes.c_char_p
+    lib.carve_last_error.argtypes = []
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _check(rc: int, allow_trunc: bool = False) -> int:
+    if rc == CARVE_OK or (allow_trunc and rc == CARVE_ETRUNC):
+        return rc
+    raise CarveError(rc, _lib.carve_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dev_u8(t: torch.Tensor, what: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.uint8 or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous uint8 tensor")
+    return t
+
+
+class Index:
+    """Resident master-signature index (owns the C handle, keeps the master bytes alive)."""
+
+    def __init__(self, handle: int, masters: torch.Tensor, file_offsets: Sequence[int]):
+        self.handle = handle
+        self.masters = masters
+        self.file_offsets = list(file_offsets)
+
+    def stats(self) -> dict:
+        st = _IndexStats()
+        _check(load_library().index_stats(self.handle, ctypes.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in _IndexStats._fields_}
+
+    def close(self):
+        h, self.handle = self.handle, None
+        if h:
+            load_library().free_index(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scan:
+    """Result buffers of a scan (owns the C handle, keeps the image alive)."""
+
+    def __init__(self):
+        self.handle = None
+        self.image = None
+
+    def set_timing(self, enable: bool = True):
+        _check(load_library().scan_set_timing(self.handle, int(enable)))
+
+    def kernel_ms(self) -> float:
+        ms = ctypes.c_float()
+        _check(load_library().scan_kernel_ms(self.handle, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def close(self):
+        h, self.handle = self.handle, None
+        if h:
+            load_library().free_scan(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_master_index(master_sectors: torch.Tensor, file_sector_offsets: Sequence[int], max_load: float = 0.0,
+                       stream=None) -> Index:
+    """Index of packed master sectors (uint8 device tensor, file after file)."""
+    lib = load_library()
+    m = _dev_u8(master_sectors, "master_sectors")
+    off = np.ascontiguousarray(file_sector_offsets, dtype=np.uint64)
+    if off.size < 1:
+        raise ValueError("file_sector_offsets needs at least one entry")
+    if m.numel() != int(off[-1]) * SECTOR:
+        raise ValueError("master_sectors size does not match file_sector_offsets[-1] sectors")
+    p = _IndexParams(CARVE_SIG_DJB2_64, float(max_load))
+    h = ctypes.c_void_p()
+    _check(lib.build_master_index(m.data_ptr() if m.numel() else None, off.ctypes.data, off.size - 1,
+                                  ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))
+    return Index(h.value, m, off.tolist())
+
+
+def scan_image(index: Index, image: torch.Tensor, tau0: int = 0, tau_mode: int = CARVE_TAU_PER_CLUSTER,
+               stream=None, scan: Optional[Scan] = None, n_bytes: Optional[int] = None) -> Scan:
+    """Flag the sectors of a device-resident image (asynchronous on the stream)."""
+    lib = load_library()
+    img = _dev_u8(image, "image")
+    nb = img.numel() if n_bytes is None else int(n_bytes)
+    if nb > img.numel():
+        raise ValueError("n_bytes exceeds the image tensor")
+    sc = scan if scan is not None else Scan()
+    h = ctypes.c_void_p(sc.handle)
+    _check(lib.scan_image(index.handle, img.data_ptr() if nb else None, nb, tau0, tau_mode, _stream_ptr(stream),
+                          ctypes.byref(h)))
+    sc.handle = h.value
+    sc.image = img
+    sc.index = index
+    return sc
+
+
+def flagged_sectors(scan: Scan, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Ascending flagged sector ids as int64: into `out` (host or device) if
+    given, else a new CPU tensor. Synchronizes the scan's stream."""
+    lib = load_library()
+    n = ctypes.c_uint64()
+    if out is None:
+        _check(lib.flagged_sectors(scan.handle, None, 0, ctypes.byref(n)), allow_trunc=True)
+        out = torch.empty(int(n.value), dtype=torch.int64)
+        if out.numel() == 0:
+            return out
+    if out.dtype != torch.int64 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous int64 tensor")
+    rc = _check(lib.flagged_sectors(scan.handle, out.data_ptr() if out.numel() else None, out.numel(),
+                                    ctypes.byref(n)), allow_trunc=True)
+    if rc == CARVE_ETRUNC:
+        raise CarveError(rc, f"{n.value} flagged sectors do not fit in {out.numel()}")
+    return out[:int(n.value)]
+
+
+def confirm_matches(index: Index, scan: Scan, out: Optional[torch.Tensor] = None):
+    """Confirmed (disk_sector, file_id, sector_in_file) records.
+
+    With out=None: a numpy structured array (host). With `out` (a contiguous
+    uint8 tensor of 16*cap bytes, host or device): filled in place, and the
+    number of records is returned."""
+    lib = load_library()
+    n = ctypes.c_uint64()
+    if out is None:
+        cap = 1 << 16
+        while True:
+            buf = np.zeros(cap, dtype=MATCH_DTYPE)
+            rc = _check(lib.confirm_matches(index.handle, scan.handle, buf.ctypes.data, cap, ctypes.byref(n)),
+                        allow_trunc=True)
+            if rc == CARVE_OK:
+                return buf[:int(n.value)].copy()
+            cap = int(n.value)
+    if out.dtype != torch.uint8 or not out.is_contiguous() or out.numel() % 16:
+        raise TypeError("out must be a contiguous uint8 tensor of 16-byte records")
+    cap = out.numel() // 16
+    rc = _check(lib.confirm_matches(index.handle, scan.handle, out.data_ptr() if cap else None, cap,
+                                    ctypes.byref(n)), allow_trunc=True)
+    if rc == CARVE_ETRUNC:
+        raise CarveError(rc, f"{n.value} matches do not fit in {cap}")
+    return int(n.value)
+
+
+def sector_signatures(sectors: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """djb2-64 of each whole sector of a device tensor, as int64 (bit pattern of the uint64)."""
+    lib = load_library()
+    s = _dev_u8(sectors, "sectors")
+    n = s.numel() // SECTOR
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=s.device)
+    _check(lib.sector_signatures(s.data_ptr() if n else None, n, out.data_ptr() if n else None,
+                                 _stream_ptr(stream)))
+    return out
+
+
+def pack_master_files(files: Sequence[torch.Tensor]):
+    """Whole sectors of each file, packed file after file, and the CSR of
+    their sector ranges (a trailing partial sector is not a sector)."""
+    parts, offsets = [], [0]
+    for f in files:
+        n = f.numel() // SECTOR
+        parts.append(f.reshape(-1)[:n * SECTOR])
+        offsets.append(offsets[-1] + n)
+    data = torch.cat(parts) if parts else torch.empty(0, dtype=torch.uint8)
+    return data, offsets

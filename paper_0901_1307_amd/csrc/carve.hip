@@ -1,0 +1,811 @@
+// Kernels and C-ABI host runtime of the carving library (gfx950).
+//
+// Pipeline of one scan (Sections 3.1-3.2):
+//   k_scan<kFlags>    sector loads -> djb2-64 -> cluster position -> index
+//                     probe -> one 64-bit hit word per 64 sectors (ballot)
+//   k_reduce/k_scan_blocks/k_apply   popcount prefix -> ascending sector ids
+// Confirmation (Section 3.1):
+//   k_confirm_probe   re-hash the flagged sectors, find their slot, count
+//                     the compatible candidate master sectors
+//   k_confirm_pairs   list the (flagged sector, candidate) pairs
+//   k_compare         512-byte comparison of each pair
+//   k_emit            ordered match records
+// Index build (Section 3.1, Eq. (3)):
+//   k_master_meta, k_scan<kSigs>, k_insert, k_scatter, k_sort_segments.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/carve.h"
+#include "carve_device.h"
+
+using namespace carve;
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanWaves = kScanThreads / (int)kWave;
+constexpr int kBlockThreads = 256;
+constexpr int kItemsPerThread = 8;
+constexpr int kItemsPerBlock = kBlockThreads * kItemsPerThread;   // 2048
+
+enum { kFlags = 0, kSigs = 1 };
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be placed
+
+// ------------------------------------------------------------------ scan
+template <int kMode>
+__global__ __launch_bounds__(kScanThreads) void k_scan(const uint8_t* __restrict__ image, uint64_t n_sectors,
+                                                      uint32_t tau0, uint32_t any_tau, IndexView ix,
+                                                      uint64_t* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
+  const uint32_t w = threadIdx.x / kWave;
+  const uint32_t l = lane_id();
+  uint8_t* my = lds + w * kTileLds;
+  const uint64_t n_tiles = (n_sectors + kTileSectors - 1) / kTileSectors;
+  const uint64_t stride = (uint64_t)gridDim.x * kScanWaves;
+  for (uint64_t t = (uint64_t)blockIdx.x * kScanWaves + w; t < n_tiles; t += stride) {
+    const uint64_t first = t * kTileSectors;
+    const uint64_t rem = n_sectors - first;
+    const ContiguousRows rows{image + first * kSectorBytes, rem >= kTileSectors ? kTileSectors : (uint32_t)rem};
+    const uint64_t h = tile_signature<true>(rows, my);
+    if constexpr (kMode == kFlags) {
+      const uint32_t tau = (uint32_t)((first + l + tau0) & (kClusterSectors - 1));
+      uint64_t hits = tile_probe(ix, h, tau, any_tau != 0);
+      if (rows.n_valid < kTileSectors) hits &= (1ull << rows.n_valid) - 1ull;
+      if (l == 0) out[t] = hits;
+    } else {
+      if (l < rows.n_valid) out[first + l] = h;
+    }
+  }
+}
+
+// -------------------------------------------------------- prefix sums
+// Item counters: the count of item i.
+struct PopcountItems {
+  const uint64_t* words;
+  __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return (uint64_t)__popcll(words[i]); }
+};
+struct U32Items {
+  const uint32_t* v;
+  __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return v[i]; }
+};
+
+template <class Items>
+__global__ __launch_bounds__(kBlockThreads) void k_reduce(Items items, uint64_t n, uint64_t* __restrict__ blk_sums) {
+  __shared__ uint64_t lds_w[kBlockThreads / kWave];
+  const uint64_t base = (uint64_t)blockIdx.x * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kItemsPerThread; ++k)
+    if (base + k < n) s += items(base + k);
+  uint64_t total;
+  block_exclusive_scan<kBlockThreads>(s, lds_w, &total);
+  if (threadIdx.x == 0) blk_sums[blockIdx.x] = total;
+}
+
+// One block: exclusive offsets of the block sums; total into *total.
+__global__ __launch_bounds__(kBlockThreads) void k_scan_blocks(const uint64_t* __restrict__ blk_sums, uint64_t n_blk,
+                                                              uint64_t* __restrict__ blk_off,
+                                                              uint64_t* __restrict__ total) {
+  __shared__ uint64_t lds_w[kBlockThreads / kWave];
+  uint64_t carry = 0;
+  for (uint64_t b0 = 0; b0 < n_blk; b0 += kBlockThreads) {
+    const uint64_t b = b0 + threadIdx.x;
+    const uint64_t v = b < n_blk ? blk_sums[b] : 0;
+    uint64_t t;
+    const uint64_t ex = block_exclusive_scan<kBlockThreads>(v, lds_w, &t);
+    if (b < n_blk) blk_off[b] = carry + ex;
+    carry += t;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+// Bitmap -> ascending ids of set bits (id = 64*word + bit).
+struct EmitIds {
+  const uint64_t* words;
+  uint64_t* ids;
+  __device__ __forceinline__ uint64_t count(uint64_t i) const { return (uint64_t)__popcll(words[i]); }
+  __device__ __forceinline__ void emit(uint64_t i, uint64_t pos) const {
+    uint64_t x = words[i];
+    while (x) {
+      const int b = __ffsll((long long)x) - 1;
+      ids[pos++] = i * 64 + (uint64_t)b;
+      x &= x - 1;
+    }
+  }
+};
+// u32 counts -> exclusive offsets (out[n] = total).
+template <class T>
+struct EmitOffsets {
+  const uint32_t* v;
+  T* out;
+  __device__ __forceinline__ uint64_t count(uint64_t i) const { return v[i]; }
+  __device__ __forceinline__ void emit(uint64_t i, uint64_t pos) const { out[i] = (T)pos; }
+};
+
+template <class Emit>
+__global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, uint64_t n, const uint64_t* __restrict__ blk_off) {
+  __shared__ uint64_t lds_w[kBlockThreads / kWave];
+  const uint64_t base = (uint64_t)blockIdx.x * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
+  uint64_t c[kItemsPerThread];
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kItemsPerThread; ++k) {
+    c[k] = (base + k < n) ? e.count(base + k) : 0;
+    s += c[k];
+  }
+  uint64_t total;
+  uint64_t pos = blk_off[blockIdx.x] + block_exclusive_scan<kBlockThreads>(s, lds_w, &total);
+#pragma unroll
+  for (int k = 0; k < kItemsPerThread; ++k) {
+    if (base + k < n) e.emit(base + k, pos);
+    pos += c[k];
+  }
+}
+
+template <class T>
+__global__ void k_write_total(T* out, uint64_t n, const uint64_t* total) {
+  out[n] = (T)*total;
+}
+
+// A fill kernel rather than hipMemsetAsync, so the scan sequence can be
+// captured in a HIP graph.
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+struct NonEmptyLists {
+  const uint32_t* off;
+  __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return off[i + 1] != off[i] ? 1u : 0u; }
+};
+
+// ------------------------------------------------------------ build
+__global__ void k_master_meta(const uint64_t* __restrict__ off, uint32_t n_files, uint64_t n_masters,
+                              uint32_t* __restrict__ m_file, uint32_t* __restrict__ m_k) {
+  const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_masters) return;
+  uint32_t lo = 0, hi = n_files - 1;   // last f with off[f] <= m
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= m) lo = mid; else hi = mid - 1;
+  }
+  m_file[m] = lo;
+  m_k[m] = (uint32_t)(m - off[lo]);
+}
+
+// Insert every master signature (Eq. (3) at bucket granularity): first free
+// slot of the home bucket, else of the next bucket, and so on. Equal
+// signatures share one slot. Records the slot of each master, the cluster
+// positions present per slot and the number of masters per slot.
+__global__ void k_insert(const uint64_t* __restrict__ sig, const uint32_t* __restrict__ m_k, uint64_t n_masters,
+                         uint64_t* keys, uint32_t log2_buckets, uint32_t* tau_mask, uint32_t* cnt,
+                         uint32_t* __restrict__ m_slot, uint32_t* overflow, uint32_t* failed) {
+  const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_masters) return;
+  const uint64_t h = sig[m];
+  const uint64_t n_slots = (uint64_t)kBucketSlots << log2_buckets;
+  uint64_t slot = n_slots;   // side slot of signature 0
+  if (h != kEmptyKey) {
+    const uint32_t nb_mask = (1u << log2_buckets) - 1u;
+    const uint32_t home = bucket_of(h, log2_buckets);
+    uint32_t b = home;
+    bool placed = false;
+    for (uint32_t it = 0; it <= nb_mask && !placed; ++it) {
+      for (uint32_t sl = 0; sl < kBucketSlots; ++sl) {
+        unsigned long long* p = (unsigned long long*)(keys + (uint64_t)b * kBucketSlots + sl);
+        unsigned long long cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == kEmptyKey) cur = atomicCAS(p, (unsigned long long)kEmptyKey, (unsigned long long)h);
+        if (cur == kEmptyKey || cur == h) {   // claimed it, or it already holds h
+          slot = (uint64_t)b * kBucketSlots + sl;
+          placed = true;
+          break;
+        }
+      }
+      if (!placed) b = (b + 1) & nb_mask;
+    }
+    if (!placed) {   // only possible with a full table; the load ceiling rules it out
+      atomicAdd(failed, 1u);
+      m_slot[m] = kNoSlot;
+      return;
+    }
+    if (b != home) atomicAdd(overflow, 1u);
+  }
+  m_slot[m] = (uint32_t)slot;
+  atomicOr(&tau_mask[slot], 1u << (m_k[m] & (kClusterSectors - 1)));
+  atomicAdd(&cnt[slot], 1u);
+}
+
+__global__ void k_scatter(const uint32_t* __restrict__ m_slot, uint64_t n_masters, const uint32_t* __restrict__ cand_off,
+                          uint32_t* cursor, uint32_t* __restrict__ unsorted) {
+  const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_masters) return;
+  const uint32_t s = m_slot[m];
+  if (s == kNoSlot) return;
+  unsorted[cand_off[s] + atomicAdd(&cursor[s], 1u)] = (uint32_t)m;
+}
+
+// Candidate lists in ascending master order (so matches come out ordered by
+// file, then sector in file): one wave per list; each element goes to its
+// rank among the list's (distinct) elements, from `unsorted` into `cand`.
+__global__ __launch_bounds__(kBlockThreads) void k_sort_segments(const uint32_t* __restrict__ cand_off, uint64_t n_lists,
+                                                                const uint32_t* __restrict__ unsorted,
+                                                                uint32_t* __restrict__ cand) {
+  const uint32_t l = lane_id();
+  const uint64_t waves = (uint64_t)gridDim.x * (kBlockThreads / kWave);
+  for (uint64_t s = (uint64_t)blockIdx.x * (kBlockThreads / kWave) + threadIdx.x / kWave; s < n_lists; s += waves) {
+    const uint32_t a = cand_off[s], e = cand_off[s + 1];
+    for (uint32_t i = a + l; i < e; i += kWave) {
+      const uint32_t v = unsorted[i];
+      uint32_t rank = 0;
+      for (uint32_t j = a; j < e; ++j) rank += unsorted[j] < v;
+      cand[a + rank] = v;
+    }
+  }
+}
+
+// -------------------------------------------------------- confirmation
+struct ConfirmView {
+  const uint32_t* cand_off;   // n_slots + 2
+  const uint32_t* cand;       // master ids
+  const uint32_t* m_k;        // sector in file, per master
+  uint64_t zero_slot;         // side slot of signature 0
+};
+
+// Wave per 64 flagged sectors: signature (gathered rows), slot, number of
+// candidates at a compatible cluster position.
+__global__ __launch_bounds__(kScanThreads) void k_confirm_probe(const uint8_t* __restrict__ image,
+                                                               const uint64_t* __restrict__ ids, uint64_t n_flagged,
+                                                               uint32_t tau0, uint32_t any_tau, IndexView ix,
+                                                               ConfirmView cv, uint64_t* __restrict__ slot_of,
+                                                               uint32_t* __restrict__ ncand) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
+  const uint32_t w = threadIdx.x / kWave;
+  const uint32_t l = lane_id();
+  uint8_t* my = lds + w * kTileLds;
+  const uint64_t n_tiles = (n_flagged + kTileSectors - 1) / kTileSectors;
+  const uint64_t stride = (uint64_t)gridDim.x * kScanWaves;
+  for (uint64_t t = (uint64_t)blockIdx.x * kScanWaves + w; t < n_tiles; t += stride) {
+    const uint64_t i = t * kTileSectors + l;
+    const bool valid = i < n_flagged;
+    const uint64_t j = valid ? ids[i] : 0;
+    const GatheredRows rows{valid ? (uint64_t)(image + j * kSectorBytes) : 0ull};
+    const uint64_t h = tile_signature<false>(rows, my);
+    if (!valid) continue;
+    const uint32_t tau = (uint32_t)((j + tau0) & (kClusterSectors - 1));
+    uint64_t slot = ~0ull;
+    if (h == kEmptyKey) {
+      slot = cv.zero_slot;
+    } else {
+      const int64_t s = find_slot(ix, h);
+      if (s >= 0) slot = (uint64_t)s;
+    }
+    uint32_t n = 0;
+    if (slot != ~0ull) {
+      for (uint32_t c = cv.cand_off[slot]; c < cv.cand_off[slot + 1]; ++c)
+        n += (any_tau || (cv.m_k[cv.cand[c]] & (kClusterSectors - 1)) == tau) ? 1u : 0u;
+    }
+    slot_of[i] = slot;
+    ncand[i] = n;
+  }
+}
+
+__global__ void k_confirm_pairs(const uint64_t* __restrict__ ids, uint64_t n_flagged, uint32_t tau0, uint32_t any_tau,
+                                ConfirmView cv, const uint64_t* __restrict__ slot_of,
+                                const uint64_t* __restrict__ pair_off, uint64_t* __restrict__ pair_flag,
+                                uint32_t* __restrict__ pair_cand) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_flagged) return;
+  const uint64_t slot = slot_of[i];
+  if (slot == ~0ull) return;
+  const uint32_t tau = (uint32_t)((ids[i] + tau0) & (kClusterSectors - 1));
+  uint64_t p = pair_off[i];
+  for (uint32_t c = cv.cand_off[slot]; c < cv.cand_off[slot + 1]; ++c) {
+    const uint32_t m = cv.cand[c];
+    if (any_tau || (cv.m_k[m] & (kClusterSectors - 1)) == tau) {
+      pair_flag[p] = i;
+      pair_cand[p] = m;
+      ++p;
+    }
+  }
+}
+
+// Wave per pair: 64 lanes x 8 bytes, equal when every lane's bytes are.
+__global__ __launch_bounds__(kBlockThreads) void k_compare(const uint8_t* __restrict__ image,
+                                                          const uint8_t* __restrict__ masters,
+                                                          const uint64_t* __restrict__ ids,
+                                                          const uint64_t* __restrict__ pair_flag,
+                                                          const uint32_t* __restrict__ pair_cand, uint64_t n_pairs,
+                                                          uint32_t* __restrict__ eq) {
+  const uint32_t l = lane_id();
+  const uint64_t waves = (uint64_t)gridDim.x * (kBlockThreads / kWave);
+  for (uint64_t p = (uint64_t)blockIdx.x * (kBlockThreads / kWave) + threadIdx.x / kWave; p < n_pairs; p += waves) {
+    const uint64_t j = ids[pair_flag[p]];
+    const uint64_t m = pair_cand[p];
+    const uint64_t a = ((const uint64_t*)(image + j * kSectorBytes))[l];
+    const uint64_t b = ((const uint64_t*)(masters + m * kSectorBytes))[l];
+    const uint64_t diff = ballot(a != b);
+    if (l == 0) eq[p] = diff == 0 ? 1u : 0u;
+  }
+}
+
+__global__ void k_emit(const uint64_t* __restrict__ ids, const uint64_t* __restrict__ pair_flag,
+                       const uint32_t* __restrict__ pair_cand, const uint32_t* __restrict__ eq,
+                       const uint64_t* __restrict__ out_off, uint64_t n_pairs, const uint32_t* __restrict__ m_file,
+                       const uint32_t* __restrict__ m_k, carve_match* __restrict__ out) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs || !eq[p]) return;
+  const uint32_t m = pair_cand[p];
+  carve_match r;
+  r.disk_sector = ids[pair_flag[p]];
+  r.file_id = m_file[m];
+  r.sector_in_file = m_k[m];
+  out[out_off[p]] = r;
+}
+
+// ============================================================ host side
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(CARVE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CARVE_TRY(expr)          \
+  do {                           \
+    int r_ = (expr);             \
+    if (r_ != CARVE_OK) return r_; \
+  } while (0)
+
+// Device buffer that grows on demand (contents not preserved).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int reserve(size_t need) {
+    if (need <= bytes) return CARVE_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t sz = need < 256 ? 256 : need;
+    if (hipMalloc(&p, sz) != hipSuccess) return fail(CARVE_ENOMEM, "hipMalloc(%zu) failed", sz);
+    bytes = sz;
+    return CARVE_OK;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+// Exclusive scan of n u32 counts into out[0..n] (out[n] = total); total also
+// left in *d_total. ws holds the block sums and offsets.
+template <class T>
+int scan_counts(const uint32_t* in, T* out, uint64_t n, uint64_t* d_total, DevBuf& ws, hipStream_t s) {
+  const uint64_t nb = cdiv(n ? n : 1, kItemsPerBlock);
+  CARVE_TRY(ws.reserve(2 * nb * sizeof(uint64_t)));
+  uint64_t* sums = ws.as<uint64_t>();
+  uint64_t* offs = sums + nb;
+  k_reduce<<<nb, kBlockThreads, 0, s>>>(U32Items{in}, n, sums);
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, nb, offs, d_total);
+  k_apply<<<nb, kBlockThreads, 0, s>>>(EmitOffsets<T>{in, out}, n, offs);
+  k_write_total<T><<<1, 1, 0, s>>>(out, n, d_total);
+  HIP_TRY(hipGetLastError());
+  return CARVE_OK;
+}
+
+int scan_grid(uint64_t n_tiles) {
+  const uint64_t want = cdiv(n_tiles, kScanWaves);
+  const uint64_t cap = (uint64_t)device_cus() * 8;
+  return (int)(want < cap ? (want ? want : 1) : cap);
+}
+
+}  // namespace
+
+// ================================================================ objects
+struct carve_index {
+  int device = 0;
+  uint64_t n_masters = 0;
+  uint32_t n_files = 0;
+  const uint8_t* masters = nullptr;
+  uint32_t log2_buckets = 1;
+  uint64_t n_slots = 0;
+  uint32_t zero_sig_mask = 0;
+  uint64_t n_unique = 0;
+  uint64_t n_overflow = 0;
+  DevBuf keys, tau_mask, cand_off, cand, m_file, m_k;
+  IndexView view() const {
+    return IndexView{keys.as<uint64_t>(), tau_mask.as<uint32_t>(), log2_buckets, zero_sig_mask};
+  }
+  ConfirmView cview() const {
+    return ConfirmView{cand_off.as<uint32_t>(), cand.as<uint32_t>(), m_k.as<uint32_t>(), n_slots};
+  }
+};
+
+struct carve_scan {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  const carve_index* idx = nullptr;
+  const uint8_t* image = nullptr;
+  uint64_t n_sectors = 0;
+  uint32_t tau0 = 0, tau_mode = 0;
+  DevBuf bitmap, ws, ids, count;
+  uint64_t* h_count = nullptr;       // pinned
+  // confirmation
+  DevBuf slot_of, ncand, pair_off, pair_flag, pair_cand, eq, out_off, matches, cws, ctotal;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timing = false, timed = false;
+};
+
+extern "C" const char* carve_last_error(void) { return g_err.c_str(); }
+
+extern "C" int sector_signatures(const void* sectors, uint64_t n_sectors, uint64_t* sigs, void* stream) {
+  if (n_sectors == 0) return CARVE_OK;
+  if (!sectors || !sigs) return fail(CARVE_EINVAL, "sector_signatures: null pointer");
+  if ((uintptr_t)sectors % 16) return fail(CARVE_EINVAL, "sector_signatures: sectors not 16-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t n_tiles = cdiv(n_sectors, kTileSectors);
+  k_scan<kSigs><<<scan_grid(n_tiles), kScanThreads, 0, s>>>((const uint8_t*)sectors, n_sectors, 0, 0, IndexView{},
+                                                            sigs);
+  HIP_TRY(hipGetLastError());
+  return CARVE_OK;
+}
+
+extern "C" void free_index(carve_index* idx) {
+  if (!idx) return;
+  idx->keys.release();
+  idx->tau_mask.release();
+  idx->cand_off.release();
+  idx->cand.release();
+  idx->m_file.release();
+  idx->m_k.release();
+  delete idx;
+}
+
+extern "C" int build_master_index(const void* master_sectors, const uint64_t* file_sector_offsets, uint32_t n_files,
+                                  const carve_index_params* params, void* stream, carve_index** out) {
+  if (!out) return fail(CARVE_EINVAL, "build_master_index: out is null");
+  *out = nullptr;
+  if (!file_sector_offsets && n_files) return fail(CARVE_EINVAL, "build_master_index: null offsets");
+  carve_index_params p{};
+  p.max_load = 0.5f;
+  if (params) {
+    p = *params;
+    if (p.max_load == 0.f) p.max_load = 0.5f;
+    for (uint32_t r : p.reserved)
+      if (r) return fail(CARVE_EINVAL, "build_master_index: reserved params must be zero");
+  }
+  if (p.sig_kind != CARVE_SIG_DJB2_64) return fail(CARVE_EUNSUPPORTED, "build_master_index: unknown sig_kind %u", p.sig_kind);
+  if (!(p.max_load > 0.f && p.max_load <= 0.9f)) return fail(CARVE_EINVAL, "build_master_index: max_load out of (0, 0.9]");
+  uint64_t n_masters = 0;
+  if (n_files) {
+    if (file_sector_offsets[0] != 0) return fail(CARVE_EINVAL, "build_master_index: offsets[0] != 0");
+    for (uint32_t f = 0; f < n_files; ++f)
+      if (file_sector_offsets[f + 1] < file_sector_offsets[f])
+        return fail(CARVE_EINVAL, "build_master_index: offsets not ascending at file %u", f);
+    n_masters = file_sector_offsets[n_files];
+  }
+  if (n_masters >= 0xFFFFFFFFull) return fail(CARVE_EUNSUPPORTED, "build_master_index: too many master sectors");
+  if (n_masters && !master_sectors) return fail(CARVE_EINVAL, "build_master_index: null master_sectors");
+  if ((uintptr_t)master_sectors % 16) return fail(CARVE_EINVAL, "build_master_index: masters not 16-byte aligned");
+
+  hipStream_t s = (hipStream_t)stream;
+  carve_index* ix = new carve_index();
+  auto bail = [&](int code) {
+    free_index(ix);
+    return code;
+  };
+  (void)hipGetDevice(&ix->device);
+  ix->n_masters = n_masters;
+  ix->n_files = n_files;
+  ix->masters = (const uint8_t*)master_sectors;
+  uint32_t lb = 1;
+  while (((uint64_t)kBucketSlots << lb) * p.max_load < (double)n_masters) ++lb;
+  if (lb > 30) return bail(fail(CARVE_EUNSUPPORTED, "build_master_index: table too large"));
+  ix->log2_buckets = lb;
+  ix->n_slots = (uint64_t)kBucketSlots << lb;
+  const uint64_t n_lists = ix->n_slots + 1;   // + side slot of signature 0
+
+  int rc;
+  if ((rc = ix->keys.reserve(ix->n_slots * 8)) || (rc = ix->tau_mask.reserve(n_lists * 4)) ||
+      (rc = ix->cand_off.reserve((n_lists + 1) * 4)) || (rc = ix->cand.reserve((n_masters ? n_masters : 1) * 4)) ||
+      (rc = ix->m_file.reserve((n_masters ? n_masters : 1) * 4)) || (rc = ix->m_k.reserve((n_masters ? n_masters : 1) * 4)))
+    return bail(rc);
+  DevBuf d_off, sig, cnt, m_slot, tmp, ws, misc;
+  auto cleanup = [&]() {
+    d_off.release();
+    sig.release();
+    cnt.release();
+    m_slot.release();
+    tmp.release();
+    ws.release();
+    misc.release();
+  };
+  auto bail2 = [&](int code) {
+    cleanup();
+    return bail(code);
+  };
+  if ((rc = d_off.reserve((n_files + 1) * 8)) || (rc = sig.reserve((n_masters ? n_masters : 1) * 8)) ||
+      (rc = cnt.reserve(n_lists * 4)) || (rc = m_slot.reserve((n_masters ? n_masters : 1) * 4)) ||
+      (rc = tmp.reserve((n_masters ? n_masters : 1) * 4)) || (rc = misc.reserve(64)))
+    return bail2(rc);
+  uint32_t* d_overflow = misc.as<uint32_t>();
+  uint32_t* d_failed = d_overflow + 1;
+  uint64_t* d_total = misc.as<uint64_t>() + 1;
+#define BUILD_TRY(expr)                                                                            \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return bail2(fail(CARVE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
+  } while (0)
+  BUILD_TRY(hipMemsetAsync(ix->keys.p, 0, ix->n_slots * 8, s));
+  BUILD_TRY(hipMemsetAsync(ix->tau_mask.p, 0, n_lists * 4, s));
+  BUILD_TRY(hipMemsetAsync(cnt.p, 0, n_lists * 4, s));
+  BUILD_TRY(hipMemsetAsync(misc.p, 0, 64, s));
+  if (n_masters) {
+    BUILD_TRY(hipMemcpyAsync(d_off.p, file_sector_offsets, (n_files + 1) * 8, hipMemcpyHostToDevice, s));
+    const uint32_t nbk = (uint32_t)cdiv(n_masters, 256);
+    k_master_meta<<<nbk, 256, 0, s>>>(d_off.as<uint64_t>(), n_files, n_masters, ix->m_file.as<uint32_t>(),
+                                     ix->m_k.as<uint32_t>());
+    const uint64_t n_tiles = cdiv(n_masters, kTileSectors);
+    k_scan<kSigs><<<scan_grid(n_tiles), kScanThreads, 0, s>>>(ix->masters, n_masters, 0, 0, IndexView{},
+                                                              sig.as<uint64_t>());
+    k_insert<<<nbk, 256, 0, s>>>(sig.as<uint64_t>(), ix->m_k.as<uint32_t>(), n_masters, ix->keys.as<uint64_t>(), lb,
+                                ix->tau_mask.as<uint32_t>(), cnt.as<uint32_t>(), m_slot.as<uint32_t>(), d_overflow,
+                                d_failed);
+    BUILD_TRY(hipGetLastError());
+  }
+  if ((rc = scan_counts<uint32_t>(cnt.as<uint32_t>(), ix->cand_off.as<uint32_t>(), n_lists, d_total, ws, s)))
+    return bail2(rc);
+  if (n_masters) {
+    BUILD_TRY(hipMemsetAsync(cnt.p, 0, n_lists * 4, s));   // reused as scatter cursors
+    const uint32_t nbk = (uint32_t)cdiv(n_masters, 256);
+    k_scatter<<<nbk, 256, 0, s>>>(m_slot.as<uint32_t>(), n_masters, ix->cand_off.as<uint32_t>(), cnt.as<uint32_t>(),
+                                 tmp.as<uint32_t>());
+    k_sort_segments<<<device_cus() * 8, kBlockThreads, 0, s>>>(ix->cand_off.as<uint32_t>(), n_lists,
+                                                                tmp.as<uint32_t>(), ix->cand.as<uint32_t>());
+    BUILD_TRY(hipGetLastError());
+  }
+  {   // distinct signatures = non-empty candidate lists
+    const uint64_t nb = cdiv(n_lists, kItemsPerBlock);
+    if ((rc = ws.reserve(2 * nb * 8))) return bail2(rc);
+    k_reduce<<<nb, kBlockThreads, 0, s>>>(NonEmptyLists{ix->cand_off.as<uint32_t>()}, n_lists, ws.as<uint64_t>());
+    k_scan_blocks<<<1, kBlockThreads, 0, s>>>(ws.as<uint64_t>(), nb, ws.as<uint64_t>() + nb, d_total + 1);
+    BUILD_TRY(hipGetLastError());
+  }
+  uint32_t h_misc[2] = {0, 0};
+  uint64_t h_unique = 0;
+  uint32_t zmask = 0;
+  BUILD_TRY(hipMemcpyAsync(h_misc, misc.p, 8, hipMemcpyDeviceToHost, s));
+  BUILD_TRY(hipMemcpyAsync(&h_unique, d_total + 1, 8, hipMemcpyDeviceToHost, s));
+  BUILD_TRY(hipMemcpyAsync(&zmask, ix->tau_mask.as<uint32_t>() + ix->n_slots, 4, hipMemcpyDeviceToHost, s));
+  BUILD_TRY(hipStreamSynchronize(s));
+#undef BUILD_TRY
+  if (h_misc[1]) return bail2(fail(CARVE_EDEVICE, "build_master_index: %u keys could not be placed", h_misc[1]));
+  ix->n_overflow = h_misc[0];
+  ix->zero_sig_mask = zmask;
+  ix->n_unique = h_unique;
+  cleanup();
+  *out = ix;
+  return CARVE_OK;
+}
+
+extern "C" int index_stats(const carve_index* idx, carve_index_stats* out) {
+  if (!idx || !out) return fail(CARVE_EINVAL, "index_stats: null argument");
+  out->n_master_sectors = idx->n_masters;
+  out->n_unique_signatures = idx->n_unique;
+  out->n_buckets = 1ull << idx->log2_buckets;
+  out->n_overflow_keys = idx->n_overflow;
+  out->device_bytes = idx->keys.bytes + idx->tau_mask.bytes + idx->cand_off.bytes + idx->cand.bytes +
+                      idx->m_file.bytes + idx->m_k.bytes;
+  return CARVE_OK;
+}
+
+extern "C" void free_scan(carve_scan* sc) {
+  if (!sc) return;
+  (void)hipStreamSynchronize(sc->stream);
+  for (DevBuf* b : {&sc->bitmap, &sc->ws, &sc->ids, &sc->count, &sc->slot_of, &sc->ncand, &sc->pair_off,
+                    &sc->pair_flag, &sc->pair_cand, &sc->eq, &sc->out_off, &sc->matches, &sc->cws, &sc->ctotal})
+    b->release();
+  if (sc->h_count) (void)hipHostFree(sc->h_count);
+  if (sc->ev0) (void)hipEventDestroy(sc->ev0);
+  if (sc->ev1) (void)hipEventDestroy(sc->ev1);
+  delete sc;
+}
+
+extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_bytes, uint32_t tau0,
+                          uint32_t tau_mode, void* stream, carve_scan** io) {
+  if (!idx || !io) return fail(CARVE_EINVAL, "scan_image: null idx or io");
+  if (tau0 > 7) return fail(CARVE_EINVAL, "scan_image: tau0 %u > 7", tau0);
+  if (tau_mode != CARVE_TAU_PER_CLUSTER && tau_mode != CARVE_TAU_ANY)
+    return fail(CARVE_EINVAL, "scan_image: bad tau_mode %u", tau_mode);
+  const uint64_t n_sectors = n_bytes / kSectorBytes;
+  if (n_sectors && !image) return fail(CARVE_EINVAL, "scan_image: null image");
+  if ((uintptr_t)image % 16) return fail(CARVE_EINVAL, "scan_image: image not 16-byte aligned");
+  carve_scan* sc = *io;
+  bool created = false;
+  if (!sc) {
+    sc = new carve_scan();
+    created = true;
+    (void)hipGetDevice(&sc->device);
+    if (hipHostMalloc((void**)&sc->h_count, 64, hipHostMallocDefault) != hipSuccess) {
+      delete sc;
+      return fail(CARVE_ENOMEM, "scan_image: pinned allocation failed");
+    }
+  }
+  auto bail = [&](int code) {
+    if (created) free_scan(sc);
+    return code;
+  };
+  sc->stream = (hipStream_t)stream;
+  sc->idx = idx;
+  sc->image = (const uint8_t*)image;
+  sc->n_sectors = n_sectors;
+  sc->tau0 = tau0;
+  sc->tau_mode = tau_mode;
+  sc->timed = false;
+  const uint64_t n_words = cdiv(n_sectors, 64);
+  const uint64_t nb = cdiv(n_words ? n_words : 1, kItemsPerBlock);
+  int rc;
+  if ((rc = sc->bitmap.reserve((n_words ? n_words : 1) * 8)) || (rc = sc->ws.reserve(2 * nb * 8)) ||
+      (rc = sc->ids.reserve((n_sectors ? n_sectors : 1) * 8)) || (rc = sc->count.reserve(64)))
+    return bail(rc);
+  hipStream_t s = sc->stream;
+  uint64_t* d_count = sc->count.as<uint64_t>();
+  if (n_sectors == 0) {   // nothing to scan: the count is zero
+    k_fill_u64<<<1, 64, 0, s>>>(d_count, 1, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: launch failed: %s", hipGetErrorString(e)));
+    *io = sc;
+    return CARVE_OK;
+  }
+  if (sc->timing) {
+    if (!sc->ev0 && (hipEventCreate(&sc->ev0) != hipSuccess || hipEventCreate(&sc->ev1) != hipSuccess))
+      return bail(fail(CARVE_EDEVICE, "scan_image: event creation failed"));
+    if (hipEventRecord(sc->ev0, s) != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: event record failed"));
+  }
+  const uint64_t n_tiles = cdiv(n_sectors, kTileSectors);
+  k_scan<kFlags><<<scan_grid(n_tiles), kScanThreads, 0, s>>>(sc->image, n_sectors, tau0,
+                                                             tau_mode == CARVE_TAU_ANY ? 1u : 0u, idx->view(),
+                                                             sc->bitmap.as<uint64_t>());
+  if (sc->timing) {
+    if (hipEventRecord(sc->ev1, s) != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: event record failed"));
+    sc->timed = true;
+  }
+  uint64_t* sums = sc->ws.as<uint64_t>();
+  uint64_t* offs = sums + nb;
+  k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{sc->bitmap.as<uint64_t>()}, n_words, sums);
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, nb, offs, d_count);
+  k_apply<<<nb, kBlockThreads, 0, s>>>(EmitIds{sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>()}, n_words, offs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: launch failed: %s", hipGetErrorString(e)));
+  *io = sc;
+  return CARVE_OK;
+}
+
+extern "C" int scan_set_timing(carve_scan* sc, int enable) {
+  if (!sc) return fail(CARVE_EINVAL, "scan_set_timing: null scan");
+  sc->timing = enable != 0;
+  return CARVE_OK;
+}
+
+extern "C" int scan_kernel_ms(carve_scan* sc, float* ms) {
+  if (!sc || !ms) return fail(CARVE_EINVAL, "scan_kernel_ms: null argument");
+  if (!sc->timed) return fail(CARVE_EINVAL, "scan_kernel_ms: the last scan was not timed");
+  HIP_TRY(hipEventSynchronize(sc->ev1));
+  HIP_TRY(hipEventElapsedTime(ms, sc->ev0, sc->ev1));
+  return CARVE_OK;
+}
+
+namespace {
+int read_count(carve_scan* sc, const uint64_t* d, uint64_t* h) {
+  HIP_TRY(hipMemcpyAsync(sc->h_count, d, 8, hipMemcpyDeviceToHost, sc->stream));
+  HIP_TRY(hipStreamSynchronize(sc->stream));
+  *h = sc->h_count[0];
+  return CARVE_OK;
+}
+}  // namespace
+
+extern "C" int flagged_sectors(carve_scan* sc, uint64_t* out, uint64_t cap, uint64_t* n_out) {
+  if (!sc || !n_out) return fail(CARVE_EINVAL, "flagged_sectors: null argument");
+  if (cap && !out) return fail(CARVE_EINVAL, "flagged_sectors: null out with cap > 0");
+  uint64_t n = 0;
+  CARVE_TRY(read_count(sc, sc->count.as<uint64_t>(), &n));
+  *n_out = n;
+  const uint64_t k = n < cap ? n : cap;
+  if (k) {
+    HIP_TRY(hipMemcpyAsync(out, sc->ids.p, k * 8, hipMemcpyDefault, sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+  }
+  if (n > cap) return fail(CARVE_ETRUNC, "flagged_sectors: %llu flagged, capacity %llu", (unsigned long long)n,
+                           (unsigned long long)cap);
+  return CARVE_OK;
+}
+
+extern "C" int confirm_matches(const carve_index* idx, carve_scan* sc, carve_match* out, uint64_t cap,
+                               uint64_t* n_out) {
+  if (!idx || !sc || !n_out) return fail(CARVE_EINVAL, "confirm_matches: null argument");
+  if (cap && !out) return fail(CARVE_EINVAL, "confirm_matches: null out with cap > 0");
+  if (sc->idx != idx) return fail(CARVE_EINVAL, "confirm_matches: scan was made with another index");
+  hipStream_t s = sc->stream;
+  uint64_t nf = 0;
+  CARVE_TRY(read_count(sc, sc->count.as<uint64_t>(), &nf));
+  *n_out = 0;
+  if (nf == 0) return CARVE_OK;
+  CARVE_TRY(sc->slot_of.reserve(nf * 8));
+  CARVE_TRY(sc->ncand.reserve(nf * 4));
+  CARVE_TRY(sc->pair_off.reserve((nf + 1) * 8));
+  CARVE_TRY(sc->ctotal.reserve(64));
+  const uint32_t any = sc->tau_mode == CARVE_TAU_ANY ? 1u : 0u;
+  const uint64_t n_tiles = cdiv(nf, kTileSectors);
+  k_confirm_probe<<<scan_grid(n_tiles), kScanThreads, 0, s>>>(sc->image, sc->ids.as<uint64_t>(), nf, sc->tau0, any,
+                                                              idx->view(), idx->cview(), sc->slot_of.as<uint64_t>(),
+                                                              sc->ncand.as<uint32_t>());
+  uint64_t* d_tot = sc->ctotal.as<uint64_t>();
+  CARVE_TRY(scan_counts<uint64_t>(sc->ncand.as<uint32_t>(), sc->pair_off.as<uint64_t>(), nf, d_tot, sc->cws, s));
+  uint64_t np = 0;
+  CARVE_TRY(read_count(sc, d_tot, &np));
+  if (np == 0) return CARVE_OK;
+  CARVE_TRY(sc->pair_flag.reserve(np * 8));
+  CARVE_TRY(sc->pair_cand.reserve(np * 4));
+  CARVE_TRY(sc->eq.reserve(np * 4));
+  CARVE_TRY(sc->out_off.reserve((np + 1) * 8));
+  k_confirm_pairs<<<cdiv(nf, 256), 256, 0, s>>>(sc->ids.as<uint64_t>(), nf, sc->tau0, any, idx->cview(),
+                                                sc->slot_of.as<uint64_t>(), sc->pair_off.as<uint64_t>(),
+                                                sc->pair_flag.as<uint64_t>(), sc->pair_cand.as<uint32_t>());
+  const uint64_t cmp_blocks = cdiv(np, kBlockThreads / kWave);
+  const uint64_t cmp_cap = (uint64_t)device_cus() * 16;
+  k_compare<<<cmp_blocks < cmp_cap ? cmp_blocks : cmp_cap, kBlockThreads, 0, s>>>(
+      sc->image, idx->masters, sc->ids.as<uint64_t>(), sc->pair_flag.as<uint64_t>(), sc->pair_cand.as<uint32_t>(), np,
+      sc->eq.as<uint32_t>());
+  CARVE_TRY(scan_counts<uint64_t>(sc->eq.as<uint32_t>(), sc->out_off.as<uint64_t>(), np, d_tot + 1, sc->cws, s));
+  uint64_t nm = 0;
+  CARVE_TRY(read_count(sc, d_tot + 1, &nm));
+  *n_out = nm;
+  if (nm) {
+    CARVE_TRY(sc->matches.reserve(nm * sizeof(carve_match)));
+    k_emit<<<cdiv(np, 256), 256, 0, s>>>(sc->ids.as<uint64_t>(), sc->pair_flag.as<uint64_t>(),
+                                        sc->pair_cand.as<uint32_t>(), sc->eq.as<uint32_t>(), sc->out_off.as<uint64_t>(),
+                                        np, idx->m_file.as<uint32_t>(), idx->m_k.as<uint32_t>(),
+                                        sc->matches.as<carve_match>());
+    HIP_TRY(hipGetLastError());
+    const uint64_t k = nm < cap ? nm : cap;
+    if (k) HIP_TRY(hipMemcpyAsync(out, sc->matches.p, k * sizeof(carve_match), hipMemcpyDefault, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (nm > cap) return fail(CARVE_ETRUNC, "confirm_matches: %llu matches, capacity %llu", (unsigned long long)nm,
+                            (unsigned long long)cap);
+  return CARVE_OK;
+}

@@ -1,0 +1,297 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Integer work throughout: the bar is bit-exact equality of signatures, of the
+ascending flagged-sector list and of the ordered match records."""
+import random
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pins
+import synth
+from gpu_util import assert_same_matches, dev_bytes, gpu_flags_and_matches, oracle_flags_and_matches
+from oracle import spec
+from paper_0901_1307_amd import carve
+
+pytestmark = pytest.mark.gpu
+SECTOR = 512
+MOD = 1 << 64
+K_BUCKET = 0x9E3779B97F4A7C15
+
+
+def _u64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+# ---------------------------------------------------------------- signatures
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 64 * 37 + 13, 4096])
+def test_signatures_random(n):
+    g = torch.Generator().manual_seed(n)
+    host = torch.randint(0, 256, (n, SECTOR), dtype=torch.uint8, generator=g)
+    got = _u64(carve.sector_signatures(host.cuda()))
+    want = oracle.sector_signatures(host.numpy(), threads=4)
+    assert np.array_equal(got, want)
+
+
+def test_signatures_special_sectors():
+    rng = random.Random(5)
+    secs = [bytes(SECTOR), b"\xff" * SECTOR, bytes(i & 255 for i in range(SECTOR))]
+    secs += [bytes([c]) * SECTOR for c in (1, 0x21, 0x80)]
+    secs += [spec.craft_sector(bytes(rng.getrandbits(8) for _ in range(100)), t)
+             for t in (0, 1, MOD - 1, 5381, rng.getrandbits(64))]
+    host = np.frombuffer(b"".join(secs), np.uint8)
+    got = _u64(carve.sector_signatures(torch.from_numpy(host.copy()).cuda()))
+    assert [int(x) for x in got] == [spec.djb2_closed(s) for s in secs]
+
+
+def test_signatures_ignore_trailing_bytes():
+    g = torch.Generator().manual_seed(1)
+    host = torch.randint(0, 256, (3 * SECTOR + 100,), dtype=torch.uint8, generator=g)
+    got = _u64(carve.sector_signatures(host.cuda()))
+    assert got.size == 3
+    assert np.array_equal(got, oracle.sector_signatures(host[:3 * SECTOR].numpy()))
+
+
+# ------------------------------------------------------- small adversarial
+@pytest.mark.parametrize("tau0,any_tau", [(0, False), (3, False), (7, False), (0, True), (5, True)])
+def test_small_case(tau0, any_tau):
+    image, masters, offsets, truth = pins.small_case(seed=3)
+    mflat = b"".join(masters)
+    idx = carve.build_master_index(dev_bytes(mflat), offsets)
+    img = dev_bytes(image)
+    flags, matches, _ = gpu_flags_and_matches(idx, img, tau0, any_tau)
+    wf, wm = oracle_flags_and_matches(np.frombuffer(mflat, np.uint8), offsets, np.frombuffer(image, np.uint8),
+                                      tau0, any_tau)
+    assert np.array_equal(flags, wf)
+    assert_same_matches(matches, wm)
+
+
+def test_index_stats_small():
+    _, masters, offsets, _ = pins.small_case(seed=3)
+    idx = carve.build_master_index(dev_bytes(b"".join(masters)), offsets)
+    st = idx.stats()
+    assert st["n_master_sectors"] == len(masters)
+    assert st["n_unique_signatures"] == len(set(masters))
+
+
+# ------------------------------------------------------- tiny configuration
+@pytest.fixture(scope="module")
+def tiny_gpu():
+    cfg = synth.CONFIGS["tiny"]
+    ms = synth.master_set(cfg, device="cuda")
+    img = synth.disk_image(cfg, ms, device="cuda")
+    idx = carve.build_master_index(ms.sectors, ms.file_offsets)
+    return cfg, ms, img, idx
+
+
+@pytest.mark.parametrize("tau0,any_tau", [(0, False), (6, False), (0, True)])
+def test_tiny_config(tiny_gpu, tau0, any_tau):
+    cfg, ms, img, idx = tiny_gpu
+    flags, matches, _ = gpu_flags_and_matches(idx, img.data, tau0, any_tau)
+    wf, wm = oracle_flags_and_matches(ms.sectors.cpu().numpy(), ms.file_offsets, img.data.cpu().numpy(), tau0, any_tau)
+    assert np.array_equal(flags, wf)
+    assert_same_matches(matches, wm)
+    if tau0 == 0 and not any_tau:
+        assert len(flags) > 5000
+
+
+def test_tiny_config_bruteforce(tiny_gpu):
+    """GPU confirmed set == all-pairs byte comparison (no signatures at all)."""
+    cfg, ms, img, idx = tiny_gpu
+    _, matches, _ = gpu_flags_and_matches(idx, img.data)
+    brute = oracle.bruteforce(img.data.cpu().numpy(), ms.sectors.cpu().numpy(), ms.file_offsets,
+                              threads=oracle.default_threads())
+    assert_same_matches(matches, brute)
+
+
+def test_deterministic_and_reusable_scan(tiny_gpu):
+    cfg, ms, img, idx = tiny_gpu
+    f1, m1, sc = gpu_flags_and_matches(idx, img.data)
+    f2, m2, _ = gpu_flags_and_matches(idx, img.data, scan=sc)       # reuse the scan object
+    assert np.array_equal(f1, f2)
+    assert_same_matches(m1, m2)
+    # a shorter image through the same scan object
+    f3, _, _ = gpu_flags_and_matches(idx, img.data[:1000 * SECTOR + 7], scan=sc)
+    assert np.array_equal(f3, f1[f1 < 1000])
+
+
+def test_chunked_scan_with_tau0(tiny_gpu):
+    """Scanning an image in chunks that start mid-cluster, with tau0 = start mod 8,
+    gives the same flags as one scan."""
+    cfg, ms, img, idx = tiny_gpu
+    full, _, _ = gpu_flags_and_matches(idx, img.data)
+    got = []
+    bounds = [0, 5, 4099, 77777, cfg.n_disk_sectors]
+    for a, b in zip(bounds, bounds[1:]):
+        f, _, _ = gpu_flags_and_matches(idx, img.data[a * SECTOR:b * SECTOR].clone(), tau0=a % 8)
+        got.append(f + np.uint64(a))
+    assert np.array_equal(np.concatenate(got), full)
+
+
+# ---------------------------------------------------------------- edge cases
+def test_empty_and_subsector_images(tiny_gpu):
+    cfg, ms, img, idx = tiny_gpu
+    for nbytes in (0, 1, 511):
+        t = img.data[:max(nbytes, 1)].clone()
+        sc = carve.scan_image(idx, t, n_bytes=nbytes)
+        assert carve.flagged_sectors(sc).numel() == 0
+        assert len(carve.confirm_matches(idx, sc)) == 0
+
+
+def test_single_sector_image(tiny_gpu):
+    cfg, ms, img, idx = tiny_gpu
+    one = ms.sectors[8].clone().reshape(-1)           # master sector k = 8 (tau 0)
+    f, m, _ = gpu_flags_and_matches(idx, one)
+    assert f.tolist() == [0]
+    assert (int(m["file_id"][0]), int(m["sector_in_file"][0])) == (0, 8)
+    f, _, _ = gpu_flags_and_matches(idx, one, tau0=1)
+    assert f.tolist() == []
+
+
+def test_empty_master_set():
+    idx = carve.build_master_index(torch.empty(0, dtype=torch.uint8, device="cuda"), [0])
+    img = torch.zeros(64 * SECTOR, dtype=torch.uint8, device="cuda")
+    f, m, _ = gpu_flags_and_matches(idx, img)
+    assert f.size == 0 and len(m) == 0
+
+
+def test_zero_disk_against_zero_master():
+    rng = random.Random(4)
+    masters = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(20)]
+    masters[3] = bytes(SECTOR)
+    masters[13] = bytes(SECTOR)                        # second file, k = 3 as well
+    offsets = [0, 10, 20]
+    idx = carve.build_master_index(dev_bytes(b"".join(masters)), offsets)
+    img = torch.zeros(1000 * SECTOR, dtype=torch.uint8, device="cuda")
+    for any_tau in (False, True):
+        f, m, _ = gpu_flags_and_matches(idx, img, any_tau=any_tau)
+        wf, wm = oracle_flags_and_matches(np.frombuffer(b"".join(masters), np.uint8), offsets,
+                                          np.zeros(1000 * SECTOR, np.uint8), any_tau=any_tau)
+        assert np.array_equal(f, wf)
+        assert_same_matches(m, wm)
+    assert len(m) == 2000
+
+
+def test_master_with_signature_zero():
+    """Signature 0 is the empty-slot marker of the table; it must still match."""
+    rng = random.Random(6)
+    masters = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(16)]
+    z = spec.craft_sector(b"zero", 0)
+    z2 = spec.craft_sector(b"zero-2", 0)               # same signature, other bytes
+    masters[5] = z
+    offsets = [0, 16]
+    idx = carve.build_master_index(dev_bytes(b"".join(masters)), offsets)
+    disk = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(64)]
+    disk[13] = z          # tau 5: flagged and confirmed
+    disk[21] = z2         # tau 5: flagged, not confirmed
+    disk[22] = z          # tau 6: not flagged
+    f, m, _ = gpu_flags_and_matches(idx, dev_bytes(b"".join(disk)))
+    assert f.tolist() == [13, 21]
+    assert m["disk_sector"].tolist() == [13]
+    f, m, _ = gpu_flags_and_matches(idx, dev_bytes(b"".join(disk)), any_tau=True)
+    assert f.tolist() == [13, 21, 22]
+
+
+def _inv(a: int) -> int:
+    return pow(a, -1, MOD)
+
+
+def _crafted_batch(prefix: bytes, targets):
+    """Sectors with given signatures: shared prefix, 13 base-33 digits at the end."""
+    body = prefix + bytes(SECTOR - 13 - len(prefix))
+    base = spec.djb2_closed(body + bytes(13))
+    out = []
+    for t in targets:
+        need = (t - base) % MOD
+        d = []
+        for _ in range(13):
+            d.append(need % 33)
+            need //= 33
+        out.append(body + bytes(d[12 - i] for i in range(13)))
+    return out
+
+
+def test_long_probe_chains():
+    """Thousands of master signatures whose home bucket is bucket 0 (so they
+    overflow into many later buckets), probed by present and absent sectors."""
+    rng = random.Random(7)
+    kinv = _inv(K_BUCKET)
+    n_same = 3000
+    vals = rng.sample(range(1, 1 << 30), 2 * n_same)
+    targets = [(v * kinv) % MOD for v in vals]          # target*K < 2^30: home bucket 0
+    crafted = _crafted_batch(b"chain", targets)
+    masters = crafted[:n_same] + [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(5000)]
+    offsets = [0, 4000, len(masters)]
+    idx = carve.build_master_index(dev_bytes(b"".join(masters)), offsets)
+    st = idx.stats()
+    assert st["n_overflow_keys"] > 2000
+    disk = []
+    for i in range(4096):
+        r = rng.random()
+        if r < 0.3:
+            disk.append(crafted[rng.randrange(n_same)])          # present
+        elif r < 0.6:
+            disk.append(crafted[n_same + rng.randrange(n_same)])  # absent, same home bucket
+        else:
+            disk.append(bytes(rng.getrandbits(8) for _ in range(SECTOR)))
+    image = b"".join(disk)
+    for any_tau in (False, True):
+        f, m, _ = gpu_flags_and_matches(idx, dev_bytes(image), any_tau=any_tau)
+        wf, wm = oracle_flags_and_matches(np.frombuffer(b"".join(masters), np.uint8), offsets,
+                                          np.frombuffer(image, np.uint8), any_tau=any_tau)
+        assert np.array_equal(f, wf)
+        assert_same_matches(m, wm)
+
+
+def test_many_duplicates_of_one_sector():
+    """A sector repeated in many master files: every copy is reported, ordered."""
+    rng = random.Random(8)
+    dup = bytes(rng.getrandbits(8) for _ in range(SECTOR))
+    masters, offsets = [], [0]
+    for f in range(300):
+        n = 8 + f % 5
+        sec = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(n)]
+        sec[f % n] = dup
+        masters += sec
+        offsets.append(len(masters))
+    idx = carve.build_master_index(dev_bytes(b"".join(masters)), offsets)
+    disk = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(256)]
+    for j in (3, 64, 65, 200):
+        disk[j] = dup
+    image = b"".join(disk)
+    for any_tau in (False, True):
+        f, m, _ = gpu_flags_and_matches(idx, dev_bytes(image), any_tau=any_tau)
+        wf, wm = oracle_flags_and_matches(np.frombuffer(b"".join(masters), np.uint8), offsets,
+                                          np.frombuffer(image, np.uint8), any_tau=any_tau)
+        assert np.array_equal(f, wf)
+        assert_same_matches(m, wm)
+    assert len(m) == 4 * 300
+
+
+def test_invalid_arguments():
+    img = torch.zeros(4 * SECTOR + 16, dtype=torch.uint8, device="cuda")
+    idx = carve.build_master_index(torch.zeros(SECTOR, dtype=torch.uint8, device="cuda"), [0, 1])
+    with pytest.raises(carve.CarveError) as e:
+        carve.scan_image(idx, img[1:])                          # misaligned
+    assert e.value.code == carve.CARVE_EINVAL
+    with pytest.raises(carve.CarveError):
+        carve.scan_image(idx, img, tau0=8)
+    with pytest.raises(carve.CarveError):
+        carve.scan_image(idx, img, tau_mode=7)
+    with pytest.raises(carve.CarveError):
+        carve.build_master_index(torch.zeros(2 * SECTOR, dtype=torch.uint8, device="cuda"), [1, 2])
+    # a zero master sector: with any position, all 4 zero disk sectors are flagged
+    sc = carve.scan_image(idx, img, tau_mode=carve.CARVE_TAU_ANY)
+    out = torch.empty(2, dtype=torch.int64)
+    with pytest.raises(carve.CarveError) as e:
+        carve.flagged_sectors(sc, out)
+    assert e.value.code == carve.CARVE_ETRUNC
+    assert out.tolist() == [0, 1]                               # the first cap ids were copied
+    assert carve.flagged_sectors(sc).tolist() == [0, 1, 2, 3]   # retry with room
+    rec = torch.empty(16 * 3, dtype=torch.uint8)
+    with pytest.raises(carve.CarveError) as e:
+        carve.confirm_matches(idx, sc, rec)
+    assert e.value.code == carve.CARVE_ETRUNC
+    assert len(carve.confirm_matches(idx, sc)) == 4
