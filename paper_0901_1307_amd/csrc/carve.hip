@@ -4,12 +4,10 @@
 //   k_scan<kFlags>    sector loads -> djb2-64 -> cluster position -> index
 //                     probe -> one 64-bit hit word per 64 sectors (ballot)
 //   k_reduce/k_scan_blocks/k_apply   popcount prefix -> ascending sector ids
-// Confirmation (Section 3.1):
-//   k_confirm_probe   re-hash the flagged sectors, find their slot, count
-//                     the compatible candidate master sectors
-//   k_confirm_pairs   list the (flagged sector, candidate) pairs
-//   k_compare         512-byte comparison of each pair
-//   k_emit            ordered match records
+// Confirmation (Section 3.1), from the slot each flagged sector matched:
+//   k_confirm_count   512-byte comparison with every compatible candidate
+//   prefix sum        output offsets
+//   k_confirm_emit    ordered match records
 // Index build (Section 3.1, Eq. (3)):
 //   k_master_meta, k_scan<kSigs>, k_insert, k_scatter, k_sort_segments.
 #include <hip/hip_runtime.h>
@@ -41,21 +39,36 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be pla
 template <int kMode>
 __global__ __launch_bounds__(kScanThreads) void k_scan(const uint8_t* __restrict__ image, uint64_t n_sectors,
                                                       uint32_t tau0, uint32_t any_tau, IndexView ix,
-                                                      uint64_t* __restrict__ out) {
+                                                      uint64_t wt, uint64_t* __restrict__ out,
+                                                      uint32_t* __restrict__ hit_slot) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
   const uint32_t w = threadIdx.x / kWave;
   const uint32_t l = lane_id();
   uint8_t* my = lds + w * kTileLds;
   const uint64_t n_tiles = (n_sectors + kTileSectors - 1) / kTileSectors;
   const uint64_t stride = (uint64_t)gridDim.x * kScanWaves;
-  for (uint64_t t = (uint64_t)blockIdx.x * kScanWaves + w; t < n_tiles; t += stride) {
-    const uint64_t first = t * kTileSectors;
+  uint64_t t = (uint64_t)blockIdx.x * kScanWaves + w;
+  if (t >= n_tiles) return;
+  auto rows_of = [&](uint64_t tt) {
+    const uint64_t first = tt * kTileSectors;
     const uint64_t rem = n_sectors - first;
-    const ContiguousRows rows{image + first * kSectorBytes, rem >= kTileSectors ? kTileSectors : (uint32_t)rem};
-    const uint64_t h = tile_signature<true>(rows, my);
+    return ContiguousRows{image + first * kSectorBytes, rem >= kTileSectors ? kTileSectors : (uint32_t)rem};
+  };
+  PhaseRegs A, B;
+  load_phase<true>(rows_of(t), 0, A);
+  for (; t < n_tiles; t += stride) {
+    const ContiguousRows rows = rows_of(t);
+    const uint64_t tn = t + stride;
+    // The next tile's first phase is loaded while this tile's last one is
+    // hashed. Unconditionally (the last tile reloads itself): a load under a
+    // branch would make the compiler wait for every load at the join.
+    const uint64_t h = tile_signature_pipelined<true>(rows, my, wt, A, B, [&](PhaseRegs& R) {
+      load_phase<true>(rows_of(tn < n_tiles ? tn : t), 0, R);
+    });
+    const uint64_t first = t * kTileSectors;
     if constexpr (kMode == kFlags) {
       const uint32_t tau = (uint32_t)((first + l + tau0) & (kClusterSectors - 1));
-      uint64_t hits = tile_probe(ix, h, tau, any_tau != 0);
+      uint64_t hits = tile_probe(ix, h, tau, any_tau != 0, hit_slot + first);
       if (rows.n_valid < kTileSectors) hits &= (1ull << rows.n_valid) - 1ull;
       if (l == 0) out[t] = hits;
     } else {
@@ -221,6 +234,11 @@ __global__ void k_insert(const uint64_t* __restrict__ sig, const uint32_t* __res
   atomicAdd(&cnt[slot], 1u);
 }
 
+__global__ void k_narrow_masks(const uint32_t* __restrict__ m32, uint64_t n, uint8_t* __restrict__ m8) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) m8[i] = (uint8_t)m32[i];
+}
+
 __global__ void k_scatter(const uint32_t* __restrict__ m_slot, uint64_t n_masters, const uint32_t* __restrict__ cand_off,
                           uint32_t* cursor, uint32_t* __restrict__ unsorted) {
   const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -251,101 +269,107 @@ __global__ __launch_bounds__(kBlockThreads) void k_sort_segments(const uint32_t*
 
 // -------------------------------------------------------- confirmation
 struct ConfirmView {
-  const uint32_t* cand_off;   // n_slots + 2
-  const uint32_t* cand;       // master ids
-  const uint32_t* m_k;        // sector in file, per master
-  uint64_t zero_slot;         // side slot of signature 0
+  const uint32_t* cand_off;   // n_slots + 2: candidate list of each slot (+ signature 0)
+  const uint32_t* cand;       // master sector ids, ascending within each list
+  const uint32_t* m_file;     // file of each master sector
+  const uint32_t* m_k;        // sector in file of each master sector
+  const uint8_t* masters;     // packed master sectors
 };
 
-// Wave per 64 flagged sectors: signature (gathered rows), slot, number of
-// candidates at a compatible cluster position.
-__global__ __launch_bounds__(kScanThreads) void k_confirm_probe(const uint8_t* __restrict__ image,
-                                                               const uint64_t* __restrict__ ids, uint64_t n_flagged,
-                                                               uint32_t tau0, uint32_t any_tau, IndexView ix,
-                                                               ConfirmView cv, uint64_t* __restrict__ slot_of,
-                                                               uint32_t* __restrict__ ncand) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
-  const uint32_t w = threadIdx.x / kWave;
+constexpr int kConfirmLanes = 16;   // lanes per flagged sector: 32 B each
+
+__device__ __forceinline__ bool compatible(const ConfirmView& cv, uint32_t m, uint32_t tau, uint32_t any_tau) {
+  return any_tau || (cv.m_k[m] & (kClusterSectors - 1)) == tau;
+}
+
+// 16 lanes per flagged sector: compare its 512 bytes with every candidate
+// master sector of its slot at a compatible cluster position. Records the
+// number of equal ones and, for the first 64 compatible candidates, which.
+__global__ __launch_bounds__(kBlockThreads) void k_confirm_count(const uint8_t* __restrict__ image,
+                                                                const uint64_t* __restrict__ ids, uint64_t n_flagged,
+                                                                const uint32_t* __restrict__ hit_slot, uint32_t tau0,
+                                                                uint32_t any_tau, ConfirmView cv,
+                                                                uint32_t* __restrict__ n_match,
+                                                                uint64_t* __restrict__ match_mask) {
   const uint32_t l = lane_id();
-  uint8_t* my = lds + w * kTileLds;
-  const uint64_t n_tiles = (n_flagged + kTileSectors - 1) / kTileSectors;
-  const uint64_t stride = (uint64_t)gridDim.x * kScanWaves;
-  for (uint64_t t = (uint64_t)blockIdx.x * kScanWaves + w; t < n_tiles; t += stride) {
-    const uint64_t i = t * kTileSectors + l;
-    const bool valid = i < n_flagged;
-    const uint64_t j = valid ? ids[i] : 0;
-    const GatheredRows rows{valid ? (uint64_t)(image + j * kSectorBytes) : 0ull};
-    const uint64_t h = tile_signature<false>(rows, my);
-    if (!valid) continue;
+  const uint32_t g = l / kConfirmLanes, gl = l % kConfirmLanes;
+  const uint64_t per_block = kBlockThreads / kConfirmLanes;
+  const uint64_t n_groups = (uint64_t)gridDim.x * per_block;
+  for (uint64_t i = (uint64_t)blockIdx.x * per_block + threadIdx.x / kConfirmLanes; i < n_flagged; i += n_groups) {
+    const uint64_t j = ids[i];
+    const uint32_t slot = hit_slot[j];
     const uint32_t tau = (uint32_t)((j + tau0) & (kClusterSectors - 1));
-    uint64_t slot = ~0ull;
-    if (h == kEmptyKey) {
-      slot = cv.zero_slot;
-    } else {
-      const int64_t s = find_slot(ix, h);
-      if (s >= 0) slot = (uint64_t)s;
+    const u32x4* d = (const u32x4*)(image + j * kSectorBytes) + gl;
+    const u32x4 d0 = d[0], d1 = d[kConfirmLanes];
+    uint32_t cnt = 0, rank = 0;
+    uint64_t mask = 0;
+    for (uint32_t c = cv.cand_off[slot], e = cv.cand_off[slot + 1]; c < e; ++c) {
+      const uint32_t m = cv.cand[c];
+      if (!compatible(cv, m, tau, any_tau)) continue;   // same decision in all 16 lanes
+      const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * kSectorBytes) + gl;
+      const u32x4 q0 = q[0], q1 = q[kConfirmLanes];
+      const u32x4 x = (d0 ^ q0) | (d1 ^ q1);
+      const uint64_t diff = ballot((x.x | x.y | x.z | x.w) != 0);
+      if (((diff >> (g * kConfirmLanes)) & 0xFFFFull) == 0) {
+        ++cnt;
+        if (rank < 64) mask |= 1ull << rank;
+      }
+      ++rank;
     }
-    uint32_t n = 0;
-    if (slot != ~0ull) {
-      for (uint32_t c = cv.cand_off[slot]; c < cv.cand_off[slot + 1]; ++c)
-        n += (any_tau || (cv.m_k[cv.cand[c]] & (kClusterSectors - 1)) == tau) ? 1u : 0u;
+    if (gl == 0) {
+      n_match[i] = cnt;
+      match_mask[i] = mask;
     }
-    slot_of[i] = slot;
-    ncand[i] = n;
   }
 }
 
-__global__ void k_confirm_pairs(const uint64_t* __restrict__ ids, uint64_t n_flagged, uint32_t tau0, uint32_t any_tau,
-                                ConfirmView cv, const uint64_t* __restrict__ slot_of,
-                                const uint64_t* __restrict__ pair_off, uint64_t* __restrict__ pair_flag,
-                                uint32_t* __restrict__ pair_cand) {
+__device__ __forceinline__ bool sectors_equal(const uint8_t* a, const uint8_t* b) {
+  const u32x4* x = (const u32x4*)a;
+  const u32x4* y = (const u32x4*)b;
+  for (int k = 0; k < (int)(kSectorBytes / 16); ++k) {
+    const u32x4 d = x[k] ^ y[k];
+    if (d.x | d.y | d.z | d.w) return false;
+  }
+  return true;
+}
+
+// Thread per flagged sector: its confirmed matches, in candidate (= file,
+// sector-in-file) order, at its offset of the output; records past `cap` are
+// counted but not written.
+__global__ void k_confirm_emit(const uint8_t* __restrict__ image, const uint64_t* __restrict__ ids, uint64_t n_flagged,
+                               const uint32_t* __restrict__ hit_slot, uint32_t tau0, uint32_t any_tau, ConfirmView cv,
+                               const uint64_t* __restrict__ match_mask, const uint64_t* __restrict__ out_off,
+                               carve_match* __restrict__ out, uint64_t cap) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_flagged) return;
-  const uint64_t slot = slot_of[i];
-  if (slot == ~0ull) return;
-  const uint32_t tau = (uint32_t)((ids[i] + tau0) & (kClusterSectors - 1));
-  uint64_t p = pair_off[i];
-  for (uint32_t c = cv.cand_off[slot]; c < cv.cand_off[slot + 1]; ++c) {
+  const uint64_t j = ids[i];
+  const uint32_t slot = hit_slot[j];
+  const uint32_t tau = (uint32_t)((j + tau0) & (kClusterSectors - 1));
+  const uint64_t mask = match_mask[i];
+  uint64_t pos = out_off[i];
+  if (pos >= cap) return;
+  uint32_t rank = 0;
+  for (uint32_t c = cv.cand_off[slot], e = cv.cand_off[slot + 1]; c < e && pos < cap; ++c) {
     const uint32_t m = cv.cand[c];
-    if (any_tau || (cv.m_k[m] & (kClusterSectors - 1)) == tau) {
-      pair_flag[p] = i;
-      pair_cand[p] = m;
-      ++p;
-    }
+    if (!compatible(cv, m, tau, any_tau)) continue;
+    const bool eq = rank < 64 ? ((mask >> rank) & 1u) != 0
+                              : sectors_equal(image + j * kSectorBytes, cv.masters + (uint64_t)m * kSectorBytes);
+    ++rank;
+    if (!eq) continue;
+    carve_match r;
+    r.disk_sector = j;
+    r.file_id = cv.m_file[m];
+    r.sector_in_file = cv.m_k[m];
+    out[pos++] = r;
   }
 }
 
-// Wave per pair: 64 lanes x 8 bytes, equal when every lane's bytes are.
-__global__ __launch_bounds__(kBlockThreads) void k_compare(const uint8_t* __restrict__ image,
-                                                          const uint8_t* __restrict__ masters,
-                                                          const uint64_t* __restrict__ ids,
-                                                          const uint64_t* __restrict__ pair_flag,
-                                                          const uint32_t* __restrict__ pair_cand, uint64_t n_pairs,
-                                                          uint32_t* __restrict__ eq) {
-  const uint32_t l = lane_id();
-  const uint64_t waves = (uint64_t)gridDim.x * (kBlockThreads / kWave);
-  for (uint64_t p = (uint64_t)blockIdx.x * (kBlockThreads / kWave) + threadIdx.x / kWave; p < n_pairs; p += waves) {
-    const uint64_t j = ids[pair_flag[p]];
-    const uint64_t m = pair_cand[p];
-    const uint64_t a = ((const uint64_t*)(image + j * kSectorBytes))[l];
-    const uint64_t b = ((const uint64_t*)(masters + m * kSectorBytes))[l];
-    const uint64_t diff = ballot(a != b);
-    if (l == 0) eq[p] = diff == 0 ? 1u : 0u;
-  }
-}
-
-__global__ void k_emit(const uint64_t* __restrict__ ids, const uint64_t* __restrict__ pair_flag,
-                       const uint32_t* __restrict__ pair_cand, const uint32_t* __restrict__ eq,
-                       const uint64_t* __restrict__ out_off, uint64_t n_pairs, const uint32_t* __restrict__ m_file,
-                       const uint32_t* __restrict__ m_k, carve_match* __restrict__ out) {
-  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs || !eq[p]) return;
-  const uint32_t m = pair_cand[p];
-  carve_match r;
-  r.disk_sector = ids[pair_flag[p]];
-  r.file_id = m_file[m];
-  r.sector_in_file = m_k[m];
-  out[out_off[p]] = r;
+// Copies min(*count, cap) ids.
+__global__ void k_copy_ids(const uint64_t* __restrict__ ids, const uint64_t* __restrict__ count, uint64_t cap,
+                           uint64_t* __restrict__ out) {
+  const uint64_t n = *count < cap ? *count : cap;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = ids[i];
 }
 
 // ============================================================ host side
@@ -399,6 +423,19 @@ struct DevBuf {
 
 uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
+// Device address of the signature weight table on the current device (0 on failure).
+uint64_t weight_table() {
+  static uint64_t ptr[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_weights)) != hipSuccess) return 0;
+    ptr[dev] = (uint64_t)(uintptr_t)p;
+  }
+  return ptr[dev];
+}
+
 int device_cus() {
   static int cus = 0;
   if (!cus) {
@@ -427,9 +464,14 @@ int scan_counts(const uint32_t* in, T* out, uint64_t n, uint64_t* d_total, DevBu
   return CARVE_OK;
 }
 
-int scan_grid(uint64_t n_tiles) {
-  const uint64_t want = cdiv(n_tiles, kScanWaves);
-  const uint64_t cap = (uint64_t)device_cus() * 8;
+// Blocks of a persistent grid: as many as stay resident at once (so no
+// block waits for a second round), but no more than the work needs.
+template <class Kernel>
+int resident_grid(Kernel kernel, int threads, uint64_t want) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+    per_cu = 1;
+  const uint64_t cap = (uint64_t)device_cus() * (uint64_t)per_cu;
   return (int)(want < cap ? (want ? want : 1) : cap);
 }
 
@@ -446,12 +488,14 @@ struct carve_index {
   uint32_t zero_sig_mask = 0;
   uint64_t n_unique = 0;
   uint64_t n_overflow = 0;
-  DevBuf keys, tau_mask, cand_off, cand, m_file, m_k;
+  uint64_t weights = 0;
+  DevBuf keys, tau_mask, cand_off, cand, m_file, m_k;   // tau_mask: one byte per slot
   IndexView view() const {
-    return IndexView{keys.as<uint64_t>(), tau_mask.as<uint32_t>(), log2_buckets, zero_sig_mask};
+    return IndexView{keys.as<uint64_t>(), tau_mask.as<uint8_t>(), log2_buckets, zero_sig_mask, (uint32_t)n_slots};
   }
   ConfirmView cview() const {
-    return ConfirmView{cand_off.as<uint32_t>(), cand.as<uint32_t>(), m_k.as<uint32_t>(), n_slots};
+    return ConfirmView{cand_off.as<uint32_t>(), cand.as<uint32_t>(), m_file.as<uint32_t>(), m_k.as<uint32_t>(),
+                       masters};
   }
 };
 
@@ -462,10 +506,10 @@ struct carve_scan {
   const uint8_t* image = nullptr;
   uint64_t n_sectors = 0;
   uint32_t tau0 = 0, tau_mode = 0;
-  DevBuf bitmap, ws, ids, count;
-  uint64_t* h_count = nullptr;       // pinned
+  DevBuf bitmap, ws, ids, count, hit_slot;   // hit_slot: matched slot of each flagged sector
+  uint64_t* h_count = nullptr;               // pinned
   // confirmation
-  DevBuf slot_of, ncand, pair_off, pair_flag, pair_cand, eq, out_off, matches, cws, ctotal;
+  DevBuf n_match, match_mask, out_off, matches, cws;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timing = false, timed = false;
 };
@@ -477,9 +521,11 @@ extern "C" int sector_signatures(const void* sectors, uint64_t n_sectors, uint64
   if (!sectors || !sigs) return fail(CARVE_EINVAL, "sector_signatures: null pointer");
   if ((uintptr_t)sectors % 16) return fail(CARVE_EINVAL, "sector_signatures: sectors not 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
+  const uint64_t wt = weight_table();
+  if (!wt) return fail(CARVE_EDEVICE, "sector_signatures: weight table unavailable");
   const uint64_t n_tiles = cdiv(n_sectors, kTileSectors);
-  k_scan<kSigs><<<scan_grid(n_tiles), kScanThreads, 0, s>>>((const uint8_t*)sectors, n_sectors, 0, 0, IndexView{},
-                                                            sigs);
+  k_scan<kSigs><<<resident_grid(k_scan<kSigs>, kScanThreads, cdiv(n_tiles, kScanWaves)), kScanThreads, 0, s>>>(
+      (const uint8_t*)sectors, n_sectors, 0, 0, IndexView{}, wt, sigs, nullptr);
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
@@ -532,20 +578,23 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   ix->n_masters = n_masters;
   ix->n_files = n_files;
   ix->masters = (const uint8_t*)master_sectors;
+  ix->weights = weight_table();
+  if (!ix->weights) return bail(fail(CARVE_EDEVICE, "build_master_index: weight table unavailable"));
   uint32_t lb = 1;
   while (((uint64_t)kBucketSlots << lb) * p.max_load < (double)n_masters) ++lb;
-  if (lb > 30) return bail(fail(CARVE_EUNSUPPORTED, "build_master_index: table too large"));
+  if (lb > 27) return bail(fail(CARVE_EUNSUPPORTED, "build_master_index: table too large"));   // slots fit 32 bits
   ix->log2_buckets = lb;
   ix->n_slots = (uint64_t)kBucketSlots << lb;
   const uint64_t n_lists = ix->n_slots + 1;   // + side slot of signature 0
 
   int rc;
-  if ((rc = ix->keys.reserve(ix->n_slots * 8)) || (rc = ix->tau_mask.reserve(n_lists * 4)) ||
+  if ((rc = ix->keys.reserve(ix->n_slots * 8)) || (rc = ix->tau_mask.reserve(n_lists)) ||
       (rc = ix->cand_off.reserve((n_lists + 1) * 4)) || (rc = ix->cand.reserve((n_masters ? n_masters : 1) * 4)) ||
       (rc = ix->m_file.reserve((n_masters ? n_masters : 1) * 4)) || (rc = ix->m_k.reserve((n_masters ? n_masters : 1) * 4)))
     return bail(rc);
-  DevBuf d_off, sig, cnt, m_slot, tmp, ws, misc;
+  DevBuf d_off, sig, cnt, m_slot, tmp, ws, misc, mask32;
   auto cleanup = [&]() {
+    mask32.release();
     d_off.release();
     sig.release();
     cnt.release();
@@ -560,7 +609,8 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   };
   if ((rc = d_off.reserve((n_files + 1) * 8)) || (rc = sig.reserve((n_masters ? n_masters : 1) * 8)) ||
       (rc = cnt.reserve(n_lists * 4)) || (rc = m_slot.reserve((n_masters ? n_masters : 1) * 4)) ||
-      (rc = tmp.reserve((n_masters ? n_masters : 1) * 4)) || (rc = misc.reserve(64)))
+      (rc = tmp.reserve((n_masters ? n_masters : 1) * 4)) || (rc = misc.reserve(64)) ||
+      (rc = mask32.reserve(n_lists * 4)))
     return bail2(rc);
   uint32_t* d_overflow = misc.as<uint32_t>();
   uint32_t* d_failed = d_overflow + 1;
@@ -571,7 +621,7 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
     if (e_ != hipSuccess) return bail2(fail(CARVE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
   } while (0)
   BUILD_TRY(hipMemsetAsync(ix->keys.p, 0, ix->n_slots * 8, s));
-  BUILD_TRY(hipMemsetAsync(ix->tau_mask.p, 0, n_lists * 4, s));
+  BUILD_TRY(hipMemsetAsync(mask32.p, 0, n_lists * 4, s));
   BUILD_TRY(hipMemsetAsync(cnt.p, 0, n_lists * 4, s));
   BUILD_TRY(hipMemsetAsync(misc.p, 0, 64, s));
   if (n_masters) {
@@ -580,13 +630,16 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
     k_master_meta<<<nbk, 256, 0, s>>>(d_off.as<uint64_t>(), n_files, n_masters, ix->m_file.as<uint32_t>(),
                                      ix->m_k.as<uint32_t>());
     const uint64_t n_tiles = cdiv(n_masters, kTileSectors);
-    k_scan<kSigs><<<scan_grid(n_tiles), kScanThreads, 0, s>>>(ix->masters, n_masters, 0, 0, IndexView{},
-                                                              sig.as<uint64_t>());
+    const uint64_t wt = weight_table();
+    if (!wt) return bail2(fail(CARVE_EDEVICE, "build_master_index: weight table unavailable"));
+    k_scan<kSigs><<<resident_grid(k_scan<kSigs>, kScanThreads, cdiv(n_tiles, kScanWaves)), kScanThreads, 0, s>>>(
+        ix->masters, n_masters, 0, 0, IndexView{}, wt, sig.as<uint64_t>(), nullptr);
     k_insert<<<nbk, 256, 0, s>>>(sig.as<uint64_t>(), ix->m_k.as<uint32_t>(), n_masters, ix->keys.as<uint64_t>(), lb,
-                                ix->tau_mask.as<uint32_t>(), cnt.as<uint32_t>(), m_slot.as<uint32_t>(), d_overflow,
+                                mask32.as<uint32_t>(), cnt.as<uint32_t>(), m_slot.as<uint32_t>(), d_overflow,
                                 d_failed);
     BUILD_TRY(hipGetLastError());
   }
+  k_narrow_masks<<<cdiv(n_lists, 256), 256, 0, s>>>(mask32.as<uint32_t>(), n_lists, ix->tau_mask.as<uint8_t>());
   if ((rc = scan_counts<uint32_t>(cnt.as<uint32_t>(), ix->cand_off.as<uint32_t>(), n_lists, d_total, ws, s)))
     return bail2(rc);
   if (n_masters) {
@@ -610,7 +663,7 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   uint32_t zmask = 0;
   BUILD_TRY(hipMemcpyAsync(h_misc, misc.p, 8, hipMemcpyDeviceToHost, s));
   BUILD_TRY(hipMemcpyAsync(&h_unique, d_total + 1, 8, hipMemcpyDeviceToHost, s));
-  BUILD_TRY(hipMemcpyAsync(&zmask, ix->tau_mask.as<uint32_t>() + ix->n_slots, 4, hipMemcpyDeviceToHost, s));
+  BUILD_TRY(hipMemcpyAsync(&zmask, mask32.as<uint32_t>() + ix->n_slots, 4, hipMemcpyDeviceToHost, s));
   BUILD_TRY(hipStreamSynchronize(s));
 #undef BUILD_TRY
   if (h_misc[1]) return bail2(fail(CARVE_EDEVICE, "build_master_index: %u keys could not be placed", h_misc[1]));
@@ -636,8 +689,8 @@ extern "C" int index_stats(const carve_index* idx, carve_index_stats* out) {
 extern "C" void free_scan(carve_scan* sc) {
   if (!sc) return;
   (void)hipStreamSynchronize(sc->stream);
-  for (DevBuf* b : {&sc->bitmap, &sc->ws, &sc->ids, &sc->count, &sc->slot_of, &sc->ncand, &sc->pair_off,
-                    &sc->pair_flag, &sc->pair_cand, &sc->eq, &sc->out_off, &sc->matches, &sc->cws, &sc->ctotal})
+  for (DevBuf* b : {&sc->bitmap, &sc->ws, &sc->ids, &sc->count, &sc->hit_slot, &sc->n_match, &sc->match_mask,
+                    &sc->out_off, &sc->matches, &sc->cws})
     b->release();
   if (sc->h_count) (void)hipHostFree(sc->h_count);
   if (sc->ev0) (void)hipEventDestroy(sc->ev0);
@@ -680,7 +733,8 @@ extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_
   const uint64_t nb = cdiv(n_words ? n_words : 1, kItemsPerBlock);
   int rc;
   if ((rc = sc->bitmap.reserve((n_words ? n_words : 1) * 8)) || (rc = sc->ws.reserve(2 * nb * 8)) ||
-      (rc = sc->ids.reserve((n_sectors ? n_sectors : 1) * 8)) || (rc = sc->count.reserve(64)))
+      (rc = sc->ids.reserve((n_sectors ? n_sectors : 1) * 8)) || (rc = sc->count.reserve(64)) ||
+      (rc = sc->hit_slot.reserve((n_words ? n_words : 1) * 64 * 4)))   // whole tiles: the last one may overhang
     return bail(rc);
   hipStream_t s = sc->stream;
   uint64_t* d_count = sc->count.as<uint64_t>();
@@ -697,9 +751,9 @@ extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_
     if (hipEventRecord(sc->ev0, s) != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: event record failed"));
   }
   const uint64_t n_tiles = cdiv(n_sectors, kTileSectors);
-  k_scan<kFlags><<<scan_grid(n_tiles), kScanThreads, 0, s>>>(sc->image, n_sectors, tau0,
-                                                             tau_mode == CARVE_TAU_ANY ? 1u : 0u, idx->view(),
-                                                             sc->bitmap.as<uint64_t>());
+  k_scan<kFlags><<<resident_grid(k_scan<kFlags>, kScanThreads, cdiv(n_tiles, kScanWaves)), kScanThreads, 0, s>>>(
+      sc->image, n_sectors, tau0, tau_mode == CARVE_TAU_ANY ? 1u : 0u, idx->view(), idx->weights,
+      sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>());
   if (sc->timing) {
     if (hipEventRecord(sc->ev1, s) != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: event record failed"));
     sc->timed = true;
@@ -736,19 +790,40 @@ int read_count(carve_scan* sc, const uint64_t* d, uint64_t* h) {
   *h = sc->h_count[0];
   return CARVE_OK;
 }
+
+// Device memory the kernels can write directly (else: staging + copy).
+bool is_device_memory(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();   // plain host memory: clear the sticky error
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
 }  // namespace
 
 extern "C" int flagged_sectors(carve_scan* sc, uint64_t* out, uint64_t cap, uint64_t* n_out) {
   if (!sc || !n_out) return fail(CARVE_EINVAL, "flagged_sectors: null argument");
   if (cap && !out) return fail(CARVE_EINVAL, "flagged_sectors: null out with cap > 0");
+  hipStream_t s = sc->stream;
+  const uint64_t* d_count = sc->count.as<uint64_t>();
   uint64_t n = 0;
-  CARVE_TRY(read_count(sc, sc->count.as<uint64_t>(), &n));
-  *n_out = n;
-  const uint64_t k = n < cap ? n : cap;
-  if (k) {
-    HIP_TRY(hipMemcpyAsync(out, sc->ids.p, k * 8, hipMemcpyDefault, sc->stream));
-    HIP_TRY(hipStreamSynchronize(sc->stream));
+  if (cap && is_device_memory(out)) {
+    // copy min(count, cap) ids on the device, then one synchronization
+    const uint64_t blocks = cdiv(cap < sc->n_sectors ? cap : sc->n_sectors, 256);
+    k_copy_ids<<<(unsigned)(blocks ? (blocks < 4096 ? blocks : 4096) : 1), 256, 0, s>>>(sc->ids.as<uint64_t>(), d_count,
+                                                                                      cap, out);
+    HIP_TRY(hipGetLastError());
+    CARVE_TRY(read_count(sc, d_count, &n));
+  } else {
+    CARVE_TRY(read_count(sc, d_count, &n));
+    const uint64_t k = n < cap ? n : cap;
+    if (k) {
+      HIP_TRY(hipMemcpyAsync(out, sc->ids.p, k * 8, hipMemcpyDefault, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
   }
+  *n_out = n;
   if (n > cap) return fail(CARVE_ETRUNC, "flagged_sectors: %llu flagged, capacity %llu", (unsigned long long)n,
                            (unsigned long long)cap);
   return CARVE_OK;
@@ -760,49 +835,53 @@ extern "C" int confirm_matches(const carve_index* idx, carve_scan* sc, carve_mat
   if (cap && !out) return fail(CARVE_EINVAL, "confirm_matches: null out with cap > 0");
   if (sc->idx != idx) return fail(CARVE_EINVAL, "confirm_matches: scan was made with another index");
   hipStream_t s = sc->stream;
-  uint64_t nf = 0;
-  CARVE_TRY(read_count(sc, sc->count.as<uint64_t>(), &nf));
   *n_out = 0;
-  if (nf == 0) return CARVE_OK;
-  CARVE_TRY(sc->slot_of.reserve(nf * 8));
-  CARVE_TRY(sc->ncand.reserve(nf * 4));
-  CARVE_TRY(sc->pair_off.reserve((nf + 1) * 8));
-  CARVE_TRY(sc->ctotal.reserve(64));
+  if (sc->n_sectors == 0) return CARVE_OK;
   const uint32_t any = sc->tau_mode == CARVE_TAU_ANY ? 1u : 0u;
-  const uint64_t n_tiles = cdiv(nf, kTileSectors);
-  k_confirm_probe<<<scan_grid(n_tiles), kScanThreads, 0, s>>>(sc->image, sc->ids.as<uint64_t>(), nf, sc->tau0, any,
-                                                              idx->view(), idx->cview(), sc->slot_of.as<uint64_t>(),
-                                                              sc->ncand.as<uint32_t>());
-  uint64_t* d_tot = sc->ctotal.as<uint64_t>();
-  CARVE_TRY(scan_counts<uint64_t>(sc->ncand.as<uint32_t>(), sc->pair_off.as<uint64_t>(), nf, d_tot, sc->cws, s));
-  uint64_t np = 0;
-  CARVE_TRY(read_count(sc, d_tot, &np));
-  if (np == 0) return CARVE_OK;
-  CARVE_TRY(sc->pair_flag.reserve(np * 8));
-  CARVE_TRY(sc->pair_cand.reserve(np * 4));
-  CARVE_TRY(sc->eq.reserve(np * 4));
-  CARVE_TRY(sc->out_off.reserve((np + 1) * 8));
-  k_confirm_pairs<<<cdiv(nf, 256), 256, 0, s>>>(sc->ids.as<uint64_t>(), nf, sc->tau0, any, idx->cview(),
-                                                sc->slot_of.as<uint64_t>(), sc->pair_off.as<uint64_t>(),
-                                                sc->pair_flag.as<uint64_t>(), sc->pair_cand.as<uint32_t>());
-  const uint64_t cmp_blocks = cdiv(np, kBlockThreads / kWave);
-  const uint64_t cmp_cap = (uint64_t)device_cus() * 16;
-  k_compare<<<cmp_blocks < cmp_cap ? cmp_blocks : cmp_cap, kBlockThreads, 0, s>>>(
-      sc->image, idx->masters, sc->ids.as<uint64_t>(), sc->pair_flag.as<uint64_t>(), sc->pair_cand.as<uint32_t>(), np,
-      sc->eq.as<uint32_t>());
-  CARVE_TRY(scan_counts<uint64_t>(sc->eq.as<uint32_t>(), sc->out_off.as<uint64_t>(), np, d_tot + 1, sc->cws, s));
+  const uint64_t* d_count = sc->count.as<uint64_t>();
+  // The number of flagged sectors is read once here; the kernels below are
+  // sized from it and nothing else waits on the host until the end.
+  uint64_t nf = 0;
+  CARVE_TRY(read_count(sc, d_count, &nf));
+  if (nf == 0) return CARVE_OK;
+  CARVE_TRY(sc->n_match.reserve(nf * 4));
+  CARVE_TRY(sc->match_mask.reserve(nf * 8));
+  CARVE_TRY(sc->out_off.reserve((nf + 1) * 8));
+  const ConfirmView cv = idx->cview();
+  const uint64_t per_block = kBlockThreads / kConfirmLanes;
+  k_confirm_count<<<resident_grid(k_confirm_count, kBlockThreads, cdiv(nf, per_block)), kBlockThreads, 0, s>>>(
+      sc->image, sc->ids.as<uint64_t>(), nf, sc->hit_slot.as<uint32_t>(), sc->tau0, any, cv,
+      sc->n_match.as<uint32_t>(), sc->match_mask.as<uint64_t>());
+  uint64_t* d_total = sc->count.as<uint64_t>() + 1;
+  CARVE_TRY(scan_counts<uint64_t>(sc->n_match.as<uint32_t>(), sc->out_off.as<uint64_t>(), nf, d_total, sc->cws, s));
+  const bool direct = cap && is_device_memory(out);
+  carve_match* dst = out;
+  uint64_t dst_cap = cap;
+  if (!direct) {   // host output: stage on the device, copy after the count is known
+    uint64_t guess = sc->matches.bytes / sizeof(carve_match);
+    if (guess < nf) guess = nf;
+    if (guess > cap) guess = cap;
+    CARVE_TRY(sc->matches.reserve((guess ? guess : 1) * sizeof(carve_match)));
+    dst = sc->matches.as<carve_match>();
+    dst_cap = guess;
+  }
+  k_confirm_emit<<<cdiv(nf, 256), 256, 0, s>>>(sc->image, sc->ids.as<uint64_t>(), nf, sc->hit_slot.as<uint32_t>(),
+                                              sc->tau0, any, cv, sc->match_mask.as<uint64_t>(),
+                                              sc->out_off.as<uint64_t>(), dst, dst_cap);
+  HIP_TRY(hipGetLastError());
   uint64_t nm = 0;
-  CARVE_TRY(read_count(sc, d_tot + 1, &nm));
+  CARVE_TRY(read_count(sc, d_total, &nm));
   *n_out = nm;
-  if (nm) {
-    CARVE_TRY(sc->matches.reserve(nm * sizeof(carve_match)));
-    k_emit<<<cdiv(np, 256), 256, 0, s>>>(sc->ids.as<uint64_t>(), sc->pair_flag.as<uint64_t>(),
-                                        sc->pair_cand.as<uint32_t>(), sc->eq.as<uint32_t>(), sc->out_off.as<uint64_t>(),
-                                        np, idx->m_file.as<uint32_t>(), idx->m_k.as<uint32_t>(),
-                                        sc->matches.as<carve_match>());
-    HIP_TRY(hipGetLastError());
-    const uint64_t k = nm < cap ? nm : cap;
-    if (k) HIP_TRY(hipMemcpyAsync(out, sc->matches.p, k * sizeof(carve_match), hipMemcpyDefault, s));
+  const uint64_t k = nm < cap ? nm : cap;
+  if (!direct && k) {
+    if (k > dst_cap) {   // the staging guess was short: emit again into a large enough buffer
+      CARVE_TRY(sc->matches.reserve(k * sizeof(carve_match)));
+      k_confirm_emit<<<cdiv(nf, 256), 256, 0, s>>>(sc->image, sc->ids.as<uint64_t>(), nf, sc->hit_slot.as<uint32_t>(),
+                                                  sc->tau0, any, cv, sc->match_mask.as<uint64_t>(),
+                                                  sc->out_off.as<uint64_t>(), sc->matches.as<carve_match>(), k);
+      HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipMemcpyAsync(out, sc->matches.p, k * sizeof(carve_match), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
   if (nm > cap) return fail(CARVE_ETRUNC, "confirm_matches: %llu matches, capacity %llu", (unsigned long long)nm,

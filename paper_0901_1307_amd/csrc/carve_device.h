@@ -66,6 +66,24 @@ constexpr uint32_t weight_dword(uint32_t d, uint32_t q) {
   return w;
 }
 
+// All 128 x 8 weight words. They are read from device memory with uniform
+// addresses, i.e. by scalar loads of 16 words at a time; as literals they would
+// cost one scalar move per dot product, as many scalar instructions as vector ones.
+struct WeightTable {
+  uint32_t w[kSectorBytes / 4][8];
+};
+constexpr WeightTable make_weight_table() {
+  WeightTable t{};
+  for (uint32_t d = 0; d < kSectorBytes / 4; ++d)
+    for (uint32_t q = 0; q < 8; ++q) t.w[d][q] = weight_dword(d, q);
+  return t;
+}
+__device__ WeightTable g_weights = make_weight_table();
+
+// Kernels take the table's address as an integer and read it through a
+// constant-address-space pointer: uniform loads from that space are scalar loads.
+typedef const __attribute__((address_space(4))) WeightTable* WeightPtr;
+
 // ------------------------------------------------------------ static for
 template <class F, int... Is>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
@@ -93,31 +111,35 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, uint32_t src) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
-// Byte g of x non-zero -> bit g of the result (x is wave-uniform).
+// Byte g of x non-zero -> bit g of the result (x is wave-uniform): fold each
+// byte onto its low bit, then gather bits 0, 8, ..., 56 with one multiply
+// (the partial products land on distinct bits, so nothing carries).
 __device__ __forceinline__ uint32_t bytes_nonzero(uint64_t x) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int g = 0; g < 8; ++g) r |= ((x >> (8 * g)) & 0xFFu) ? (1u << g) : 0u;
-  return r;
+  x |= x >> 4;
+  x |= x >> 2;
+  x |= x >> 1;
+  x &= 0x0101010101010101ull;
+  return (uint32_t)((x * 0x0102040810204080ull) >> 56);
 }
 
 // ------------------------------------------------------------ tile hash
-// Sector addresses of a tile. Contiguous: sector s is base + s*512 and is
-// valid for s < n_valid. Gathered: each lane holds its own sector pointer
-// (null = invalid) and the others read it with a cross-lane shuffle.
+// Sector addresses of a tile. Contiguous: sector s is base + s*512; sectors
+// past n_valid are replaced by the last valid one (their hash is discarded),
+// so every load stays inside the image without a branch. Gathered: each lane
+// holds its own sector address and the others read it with a shuffle.
 struct ContiguousRows {
   const uint8_t* base;
-  uint32_t n_valid;
-  __device__ __forceinline__ const uint8_t* row(uint32_t s) const { return base + (uint64_t)s * kSectorBytes; }
-  __device__ __forceinline__ bool valid(uint32_t s) const { return s < n_valid; }
+  uint32_t n_valid;   // 1..64
+  __device__ __forceinline__ const uint8_t* row(uint32_t s) const {
+    return base + (uint64_t)(s < n_valid ? s : n_valid - 1) * kSectorBytes;
+  }
 };
 
 struct GatheredRows {
-  uint64_t mine;   // this lane's sector address, 0 if none
+  uint64_t mine;   // this lane's sector address (always a valid sector)
   __device__ __forceinline__ const uint8_t* row(uint32_t s) const {
     return (const uint8_t*)shfl_u64(mine, s);
   }
-  __device__ __forceinline__ bool valid(uint32_t s) const { return row(s) != nullptr; }
 };
 
 template <bool kNonTemporal>
@@ -126,72 +148,102 @@ __device__ __forceinline__ u32x4 load16(const uint8_t* p) {
   else return *(const u32x4*)p;
 }
 
-// Returns, in lane l, the djb2-64 signature of sector l of the tile.
-// lds: this wave's kTileLds-byte staging area.
+// Phase p of a tile: instruction i, lane l loads 16 B of sector 8i + l/8 at
+// byte 128p + 16(l%8); one instruction covers 8 whole 128-byte lines.
+struct PhaseRegs {
+  u32x4 v[8];
+};
+
 template <bool kNonTemporal, class Rows>
-__device__ __forceinline__ uint64_t tile_signature(const Rows& rows, uint8_t* lds) {
+__device__ __forceinline__ void load_phase(const Rows& rows, uint32_t p, PhaseRegs& r) {
+  const uint32_t l = lane_id();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r.v[i] = load16<kNonTemporal>(rows.row(8u * i + (l >> 3)) + p * kPhaseBytes + (l & 7u) * 16u);
+}
+
+// Stage phase P through this wave's LDS area and fold its 128 bytes per
+// sector into the 8 digit-plane accumulators of lane l's sector.
+template <int P>
+__device__ __forceinline__ void hash_phase(const PhaseRegs& r, uint8_t* lds, uint64_t wt, uint32_t (&acc)[8]) {
+  // the loads issued before this call stay above it
+  __builtin_amdgcn_sched_barrier(0);
+  // The weights are loop-invariant; hiding the pointer's identity per phase
+  // keeps the compiler from hoisting all 1024 of them into scalar registers.
+  WeightPtr w = (WeightPtr)wt;
+  asm volatile("" : "+s"(w));
   const uint32_t l = lane_id();
   const uint32_t col = (l & 7u) * 16u;
-  uint32_t acc[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0;
-
-  // instruction i of a phase: lane l loads 16 B of sector 8i + l/8
-  const uint8_t* src[8];
-  bool ok[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const uint32_t s = 8u * i + (l >> 3);
-    ok[i] = rows.valid(s);
-    src[i] = rows.row(s) + col;
-  }
-
-  u32x4 cur[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) cur[i] = ok[i] ? load16<kNonTemporal>(src[i]) : u32x4{0, 0, 0, 0};
-
-  static_for<kPhases>([&](auto P) {
-    constexpr int p = decltype(P)::value;
-    // stage: row s = 8i + l/8, column l%8
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      *(u32x4*)(lds + (8u * i + (l >> 3)) * kRowPitch + col) = cur[i];
-    wave_sync_lds();
-    // next phase's loads are in flight while this phase is hashed
-    if constexpr (p + 1 < (int)kPhases) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        cur[i] = ok[i] ? load16<kNonTemporal>(src[i] + (p + 1) * kPhaseBytes) : u32x4{0, 0, 0, 0};
-    }
-    static_for<8>([&](auto C) {
-      constexpr int c = decltype(C)::value;
-      const u32x4 r = *(const u32x4*)(lds + l * kRowPitch + c * 16);
-      static_for<4>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        constexpr uint32_t d = p * (kPhaseBytes / 4) + c * 4 + k;
-        const uint32_t x = r[k];
-        static_for<8>([&](auto Q) {
-          constexpr int q = decltype(Q)::value;
-          constexpr uint32_t w = weight_dword(d, q);
-          acc[q] = __builtin_amdgcn_udot4(x, w, acc[q], false);
-        });
+  for (int i = 0; i < 8; ++i) *(u32x4*)(lds + (8u * i + (l >> 3)) * kRowPitch + col) = r.v[i];
+  wave_sync_lds();
+  static_for<8>([&](auto C) {
+    constexpr int c = decltype(C)::value;
+    // one 16-byte column (32 weights) at a time, or the weight loads of the
+    // whole phase get hoisted and overflow the scalar registers
+    __builtin_amdgcn_sched_barrier(0);
+    const u32x4 x4 = *(const u32x4*)(lds + l * kRowPitch + c * 16);
+    static_for<4>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr uint32_t d = P * (kPhaseBytes / 4) + c * 4 + k;
+      const uint32_t x = x4[k];
+      static_for<8>([&](auto Q) {
+        constexpr int q = decltype(Q)::value;
+        acc[q] = __builtin_amdgcn_udot4(x, w->w[d][q], acc[q], false);
       });
     });
-    wave_sync_lds();
   });
+  // The accumulators must be final here: an empty asm that "modifies" them
+  // is a side effect, so neither this phase's math can sink below the next
+  // phase's LDS stores nor can those stores rise above it.
+  asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5]),
+               "+v"(acc[6]), "+v"(acc[7]));
+  wave_sync_lds();
+  __builtin_amdgcn_sched_barrier(0);
+}
 
+__device__ __forceinline__ uint64_t finish_signature(const uint32_t (&acc)[8]) {
   uint64_t h = kInitTerm;
 #pragma unroll
   for (int q = 0; q < 8; ++q) h += (uint64_t)acc[q] << (8 * q);
   return h;
 }
 
+// Signature of every sector of a tile (lane l = sector l). A and B are the
+// two register buffers of the load pipeline: on entry A holds (or is
+// receiving) phase 0; phase p+1 loads are issued before phase p is hashed,
+// and `prefetch` (called before the last phase is hashed) may start the next
+// tile's phase 0 into A.
+template <bool kNonTemporal, class Rows, class Prefetch>
+__device__ __forceinline__ uint64_t tile_signature_pipelined(const Rows& rows, uint8_t* lds, uint64_t wt,
+                                                             PhaseRegs& A, PhaseRegs& B, Prefetch&& prefetch) {
+  uint32_t acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0;
+  load_phase<kNonTemporal>(rows, 1, B);
+  hash_phase<0>(A, lds, wt, acc);
+  load_phase<kNonTemporal>(rows, 2, A);
+  hash_phase<1>(B, lds, wt, acc);
+  load_phase<kNonTemporal>(rows, 3, B);
+  hash_phase<2>(A, lds, wt, acc);
+  prefetch(A);
+  hash_phase<3>(B, lds, wt, acc);
+  return finish_signature(acc);
+}
+
+template <bool kNonTemporal, class Rows>
+__device__ __forceinline__ uint64_t tile_signature(const Rows& rows, uint8_t* lds, uint64_t wt) {
+  PhaseRegs A, B;
+  load_phase<kNonTemporal>(rows, 0, A);
+  return tile_signature_pipelined<kNonTemporal>(rows, lds, wt, A, B, [](PhaseRegs&) {});
+}
+
 // ---------------------------------------------------------------- index
 struct IndexView {
-  const uint64_t* keys;       // n_buckets * 16 slots, kEmptyKey = free
-  const uint32_t* tau_mask;   // per slot (+1: the side slot of signature 0), bit t = present at position t
+  const uint64_t* keys;      // n_buckets * 16 slots, kEmptyKey = free
+  const uint8_t* tau_mask;   // per slot, bit t = a master with this signature sits at position t
   uint32_t log2_buckets;
-  uint32_t zero_sig_mask;     // tau mask of signature 0 (the side slot)
+  uint32_t zero_sig_mask;    // positions of signature 0, which has no slot in the table
+  uint32_t zero_slot;        // candidate-list id of signature 0 (= number of table slots)
 };
 
 __device__ __forceinline__ uint32_t bucket_of(uint64_t h, uint32_t log2_buckets) {
@@ -224,41 +276,55 @@ __device__ __forceinline__ bool tau_ok(uint32_t mask, uint32_t tau, bool any_tau
   return any_tau ? (mask != 0) : (((mask >> tau) & 1u) != 0);
 }
 
-// Membership of the 64 lane signatures, cooperatively: in round r, the 8 lanes
-// of group g read the 128-byte home bucket of sector 8r+g (16 B each), so a
-// round is one load instruction over 8 whole lines. Returns the 64-bit hit
-// mask of the tile (bit l = sector l). tau: this lane's cluster position.
-__device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, uint32_t tau, bool any_tau) {
+// Membership of the 64 lane signatures, cooperatively: in round r the 8
+// lanes of group g read the 128-byte home bucket of sector 8r+g (16 B each)
+// and its 16 position masks (2 B each). All 16 loads are issued before any
+// is used, so the tile pays one memory latency. Returns the tile's hit mask
+// (bit l = sector l); tau is this lane's cluster position. For each hit, the
+// slot that matched is stored in slot_out[sector] (the candidate list that
+// confirmation walks).
+__device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, uint32_t tau, bool any_tau,
+                                               uint32_t* __restrict__ slot_out) {
   const uint32_t l = lane_id();
   const uint32_t bkt = bucket_of(h, ix.log2_buckets);
-  uint64_t hits = 0, unresolved = 0;
+  u64x2 kv[8];
+  uint32_t mk[8];
+  uint64_t hs[8];
+  uint32_t ts[8];
+  uint32_t slot0[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const uint32_t s = 8u * r + (l >> 3);
-    const uint64_t hs = shfl_u64(h, s);
+    hs[r] = shfl_u64(h, s);
+    ts[r] = (uint32_t)__shfl((int)tau, (int)s, kWave);
     const uint32_t bs = (uint32_t)__shfl((int)bkt, (int)s, kWave);
-    const uint32_t ts = (uint32_t)__shfl((int)tau, (int)s, kWave);
-    const uint64_t slot0 = (uint64_t)bs * kBucketSlots + 2u * (l & 7u);
-    const u64x2 kv = *(const u64x2*)(ix.keys + slot0);
-    const bool live = hs != kEmptyKey;
-    const bool m0 = live && kv.x == hs;
-    const bool m1 = live && kv.y == hs;
-    const bool empty = !live || kv.x == kEmptyKey || kv.y == kEmptyKey;
-    bool ok = false;
-    if (m0 | m1) ok = tau_ok(ix.tau_mask[slot0 + (m1 ? 1 : 0)], ts, any_tau);
-    const uint64_t b_ok = ballot(ok);
-    const uint64_t b_done = ballot(m0 | m1 | empty);
-    hits |= (uint64_t)bytes_nonzero(b_ok) << (8 * r);
-    unresolved |= (uint64_t)(~bytes_nonzero(b_done) & 0xFFu) << (8 * r);
+    slot0[r] = bs * kBucketSlots + 2u * (l & 7u);
+    kv[r] = *(const u64x2*)(ix.keys + slot0[r]);
+    mk[r] = *(const uint16_t*)(ix.tau_mask + slot0[r]);
+  }
+  uint64_t hits = 0, unresolved = 0;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const bool live = hs[r] != kEmptyKey;
+    const bool m0 = live && kv[r].x == hs[r];
+    const bool m1 = live && kv[r].y == hs[r];
+    const bool empty = !live || kv[r].x == kEmptyKey || kv[r].y == kEmptyKey;
+    const uint32_t mask = m0 ? (mk[r] & 0xFFu) : (mk[r] >> 8);
+    const bool ok = (m0 | m1) && tau_ok(mask, ts[r], any_tau);
+    if (ok) slot_out[8u * r + (l >> 3)] = slot0[r] + (m1 ? 1u : 0u);
+    hits |= (uint64_t)bytes_nonzero(ballot(ok)) << (8 * r);
+    unresolved |= (uint64_t)(~bytes_nonzero(ballot(m0 | m1 | empty)) & 0xFFu) << (8 * r);
   }
   // rare: the home bucket was full and did not hold the key
   bool ok_more = false;
   if ((unresolved >> l) & 1u) {
     const int64_t slot = find_slot(ix, h);
     ok_more = slot >= 0 && tau_ok(ix.tau_mask[slot], tau, any_tau);
+    if (ok_more) slot_out[l] = (uint32_t)slot;
   }
   // signature 0 cannot be stored in the table (it marks free slots)
   const bool ok_zero = (h == kEmptyKey) && tau_ok(ix.zero_sig_mask, tau, any_tau);
+  if (ok_zero) slot_out[l] = ix.zero_slot;
   return hits | ballot(ok_more) | ballot(ok_zero);
 }
 
