@@ -56,10 +56,15 @@ typedef enum {
 } carve_tau_mode;
 
 typedef struct {
-  uint32_t sig_kind;       /* carve_sig_kind; 0 = djb2-64 */
-  float max_load;          /* hash-table load factor ceiling in (0, 0.9]; 0 = 0.5 */
-  uint32_t reserved[6];    /* must be zero */
+  uint32_t sig_kind;           /* carve_sig_kind; 0 = djb2-64 */
+  float max_load;              /* hash-table load factor ceiling in (0, 0.9]; 0 = 0.5 */
+  uint32_t bloom_bits_per_key; /* prefilter in front of the table: 0 = automatic (on when a filter of
+                                  >= 6 bits per distinct signature fits in 2 MiB, so it stays in L2),
+                                  CARVE_BLOOM_OFF = none, else 4..64 bits per signature */
+  uint32_t reserved[5];        /* must be zero */
 } carve_index_params;
+
+#define CARVE_BLOOM_OFF 0xFFFFFFFFu
 
 typedef struct {
   uint64_t disk_sector;    /* flagged disk sector id */
@@ -73,6 +78,7 @@ typedef struct {
   uint64_t n_buckets;            /* 16-slot buckets of the hash table */
   uint64_t n_overflow_keys;      /* keys stored outside their home bucket */
   uint64_t device_bytes;         /* device memory owned by the index */
+  uint64_t bloom_bytes;          /* size of the prefilter, 0 if none */
 } carve_index_stats;
 
 /*

@@ -33,14 +33,18 @@ class CarveError(RuntimeError):
         self.code = code
 
 
+CARVE_BLOOM_OFF = 0xFFFFFFFF
+
+
 class _IndexParams(ctypes.Structure):
-    _fields_ = [("sig_kind", ctypes.c_uint32), ("max_load", ctypes.c_float), ("reserved", ctypes.c_uint32 * 6)]
+    _fields_ = [("sig_kind", ctypes.c_uint32), ("max_load", ctypes.c_float), ("bloom_bits_per_key", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 5)]
 
 
 class _IndexStats(ctypes.Structure):
     _fields_ = [("n_master_sectors", ctypes.c_uint64), ("n_unique_signatures", ctypes.c_uint64),
                 ("n_buckets", ctypes.c_uint64), ("n_overflow_keys", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("bloom_bytes", ctypes.c_uint64)]
 
 
 _lib = None
@@ -158,8 +162,10 @@ class Scan:
 
 
 def build_master_index(master_sectors: torch.Tensor, file_sector_offsets: Sequence[int], max_load: float = 0.0,
-                       stream=None) -> Index:
-    """Index of packed master sectors (uint8 device tensor, file after file)."""
+                       bloom_bits_per_key: int = 0, stream=None) -> Index:
+    """Index of packed master sectors (uint8 device tensor, file after file).
+
+    bloom_bits_per_key: 0 = automatic, CARVE_BLOOM_OFF = no prefilter."""
     lib = load_library()
     m = _dev_u8(master_sectors, "master_sectors")
     off = np.ascontiguousarray(file_sector_offsets, dtype=np.uint64)
@@ -167,7 +173,7 @@ def build_master_index(master_sectors: torch.Tensor, file_sector_offsets: Sequen
         raise ValueError("file_sector_offsets needs at least one entry")
     if m.numel() != int(off[-1]) * SECTOR:
         raise ValueError("master_sectors size does not match file_sector_offsets[-1] sectors")
-    p = _IndexParams(CARVE_SIG_DJB2_64, float(max_load))
+    p = _IndexParams(CARVE_SIG_DJB2_64, float(max_load), int(bloom_bits_per_key))
     h = ctypes.c_void_p()
     _check(lib.build_master_index(m.data_ptr() if m.numel() else None, off.ctypes.data, off.size - 1,
                                   ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))

@@ -36,8 +36,10 @@ enum { kFlags = 0, kSigs = 1 };
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be placed
 
 // ------------------------------------------------------------------ scan
+// 4 waves per SIMD (at most 128 VGPRs): the more waves, the more sector
+// loads are in flight per compute unit.
 template <int kMode>
-__global__ __launch_bounds__(kScanThreads) void k_scan(const uint8_t* __restrict__ image, uint64_t n_sectors,
+__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(const uint8_t* __restrict__ image, uint64_t n_sectors,
                                                       uint32_t tau0, uint32_t any_tau, IndexView ix,
                                                       uint64_t wt, uint64_t* __restrict__ out,
                                                       uint32_t* __restrict__ hit_slot) {
@@ -232,6 +234,19 @@ __global__ void k_insert(const uint64_t* __restrict__ sig, const uint32_t* __res
   m_slot[m] = (uint32_t)slot;
   atomicOr(&tau_mask[slot], 1u << (m_k[m] & (kClusterSectors - 1)));
   atomicAdd(&cnt[slot], 1u);
+}
+
+// Bloom filter of the table's keys (signature 0 is kept apart and not in it).
+__global__ void k_bloom_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t log2_words,
+                              uint64_t* bloom) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slots) return;
+  const uint64_t h = keys[i];
+  if (h == kEmptyKey) return;
+  uint32_t w;
+  uint64_t bits;
+  bloom_place(h, log2_words, &w, &bits);
+  atomicOr((unsigned long long*)(bloom + w), (unsigned long long)bits);
 }
 
 __global__ void k_narrow_masks(const uint32_t* __restrict__ m32, uint64_t n, uint8_t* __restrict__ m8) {
@@ -489,9 +504,11 @@ struct carve_index {
   uint64_t n_unique = 0;
   uint64_t n_overflow = 0;
   uint64_t weights = 0;
-  DevBuf keys, tau_mask, cand_off, cand, m_file, m_k;   // tau_mask: one byte per slot
+  uint32_t log2_bloom_words = 0;
+  DevBuf keys, tau_mask, cand_off, cand, m_file, m_k, bloom;   // tau_mask: one byte per slot
   IndexView view() const {
-    return IndexView{keys.as<uint64_t>(), tau_mask.as<uint8_t>(), log2_buckets, zero_sig_mask, (uint32_t)n_slots};
+    return IndexView{keys.as<uint64_t>(), tau_mask.as<uint8_t>(), bloom.bytes ? bloom.as<uint64_t>() : nullptr,
+                     log2_buckets, log2_bloom_words, zero_sig_mask, (uint32_t)n_slots};
   }
   ConfirmView cview() const {
     return ConfirmView{cand_off.as<uint32_t>(), cand.as<uint32_t>(), m_file.as<uint32_t>(), m_k.as<uint32_t>(),
@@ -538,6 +555,7 @@ extern "C" void free_index(carve_index* idx) {
   idx->cand.release();
   idx->m_file.release();
   idx->m_k.release();
+  idx->bloom.release();
   delete idx;
 }
 
@@ -556,6 +574,9 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   }
   if (p.sig_kind != CARVE_SIG_DJB2_64) return fail(CARVE_EUNSUPPORTED, "build_master_index: unknown sig_kind %u", p.sig_kind);
   if (!(p.max_load > 0.f && p.max_load <= 0.9f)) return fail(CARVE_EINVAL, "build_master_index: max_load out of (0, 0.9]");
+  if (p.bloom_bits_per_key != 0 && p.bloom_bits_per_key != CARVE_BLOOM_OFF &&
+      (p.bloom_bits_per_key < 4 || p.bloom_bits_per_key > 64))
+    return fail(CARVE_EINVAL, "build_master_index: bloom_bits_per_key %u out of 4..64", p.bloom_bits_per_key);
   uint64_t n_masters = 0;
   if (n_files) {
     if (file_sector_offsets[0] != 0) return fail(CARVE_EINVAL, "build_master_index: offsets[0] != 0");
@@ -670,6 +691,27 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   ix->n_overflow = h_misc[0];
   ix->zero_sig_mask = zmask;
   ix->n_unique = h_unique;
+  {   // prefilter: words of 64 bits, a power of two of them
+    constexpr uint64_t kAutoBytes = 2ull << 20;
+    const uint64_t keys_n = h_unique ? h_unique : 1;
+    uint32_t lw = 0;
+    if (p.bloom_bits_per_key == 0) {   // largest filter within kAutoBytes, if it gives >= 6 bits per key
+      while ((8ull << (lw + 1)) <= kAutoBytes && (64ull << lw) < 16 * keys_n) ++lw;
+      if ((64ull << lw) < 6 * keys_n) lw = 0;
+    } else if (p.bloom_bits_per_key != CARVE_BLOOM_OFF) {
+      while ((64ull << lw) < (uint64_t)p.bloom_bits_per_key * keys_n) ++lw;
+    }
+    if (lw > 0 && lw <= 32) {
+      if ((rc = ix->bloom.reserve(8ull << lw))) return bail2(rc);
+      ix->log2_bloom_words = lw;
+      if (hipMemsetAsync(ix->bloom.p, 0, 8ull << lw, s) != hipSuccess)
+        return bail2(fail(CARVE_EDEVICE, "build_master_index: bloom memset failed"));
+      k_bloom_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw,
+                                                          ix->bloom.as<uint64_t>());
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return bail2(fail(CARVE_EDEVICE, "build_master_index: bloom build failed"));
+    }
+  }
   cleanup();
   *out = ix;
   return CARVE_OK;
@@ -682,7 +724,8 @@ extern "C" int index_stats(const carve_index* idx, carve_index_stats* out) {
   out->n_buckets = 1ull << idx->log2_buckets;
   out->n_overflow_keys = idx->n_overflow;
   out->device_bytes = idx->keys.bytes + idx->tau_mask.bytes + idx->cand_off.bytes + idx->cand.bytes +
-                      idx->m_file.bytes + idx->m_k.bytes;
+                      idx->m_file.bytes + idx->m_k.bytes + idx->bloom.bytes;
+  out->bloom_bytes = idx->bloom.bytes;
   return CARVE_OK;
 }
 

@@ -123,22 +123,14 @@ __device__ __forceinline__ uint32_t bytes_nonzero(uint64_t x) {
 }
 
 // ------------------------------------------------------------ tile hash
-// Sector addresses of a tile. Contiguous: sector s is base + s*512; sectors
-// past n_valid are replaced by the last valid one (their hash is discarded),
-// so every load stays inside the image without a branch. Gathered: each lane
-// holds its own sector address and the others read it with a shuffle.
+// Sector addresses of a tile: sector s is base + s*512; sectors past n_valid
+// are replaced by the last valid one (their hash is discarded), so every load
+// stays inside the image without a branch.
 struct ContiguousRows {
   const uint8_t* base;
   uint32_t n_valid;   // 1..64
   __device__ __forceinline__ const uint8_t* row(uint32_t s) const {
     return base + (uint64_t)(s < n_valid ? s : n_valid - 1) * kSectorBytes;
-  }
-};
-
-struct GatheredRows {
-  uint64_t mine;   // this lane's sector address (always a valid sector)
-  __device__ __forceinline__ const uint8_t* row(uint32_t s) const {
-    return (const uint8_t*)shfl_u64(mine, s);
   }
 };
 
@@ -230,21 +222,27 @@ __device__ __forceinline__ uint64_t tile_signature_pipelined(const Rows& rows, u
   return finish_signature(acc);
 }
 
-template <bool kNonTemporal, class Rows>
-__device__ __forceinline__ uint64_t tile_signature(const Rows& rows, uint8_t* lds, uint64_t wt) {
-  PhaseRegs A, B;
-  load_phase<kNonTemporal>(rows, 0, A);
-  return tile_signature_pipelined<kNonTemporal>(rows, lds, wt, A, B, [](PhaseRegs&) {});
-}
-
 // ---------------------------------------------------------------- index
 struct IndexView {
   const uint64_t* keys;      // n_buckets * 16 slots, kEmptyKey = free
   const uint8_t* tau_mask;   // per slot, bit t = a master with this signature sits at position t
+  const uint64_t* bloom;     // blocked Bloom filter of the table's keys, or null
   uint32_t log2_buckets;
+  uint32_t log2_bloom_words;
   uint32_t zero_sig_mask;    // positions of signature 0, which has no slot in the table
   uint32_t zero_slot;        // candidate-list id of signature 0 (= number of table slots)
 };
+
+// Register-blocked Bloom filter: a key owns one 64-bit word and sets 4 of
+// its bits. Word and bit positions come from the high half of a second
+// multiplicative hash (djb2's low bits are weak: 33 = 1 mod 32).
+constexpr uint64_t kBloomMul = 0xD6E8FEB86659FD93ull;
+__device__ __forceinline__ void bloom_place(uint64_t h, uint32_t log2_words, uint32_t* word, uint64_t* bits) {
+  const uint64_t p = h * kBloomMul;
+  *word = (uint32_t)(p >> (64 - log2_words));
+  const uint32_t f = (uint32_t)(p >> (40 - log2_words));   // 24 bits below the word index
+  *bits = (1ull << (f & 63)) | (1ull << ((f >> 6) & 63)) | (1ull << ((f >> 12) & 63)) | (1ull << ((f >> 18) & 63));
+}
 
 __device__ __forceinline__ uint32_t bucket_of(uint64_t h, uint32_t log2_buckets) {
   return (uint32_t)((h * kBucketMul) >> (64 - log2_buckets));
@@ -276,42 +274,61 @@ __device__ __forceinline__ bool tau_ok(uint32_t mask, uint32_t tau, bool any_tau
   return any_tau ? (mask != 0) : (((mask >> tau) & 1u) != 0);
 }
 
-// Membership of the 64 lane signatures, cooperatively: in round r the 8
-// lanes of group g read the 128-byte home bucket of sector 8r+g (16 B each)
-// and its 16 position masks (2 B each). All 16 loads are issued before any
-// is used, so the tile pays one memory latency. Returns the tile's hit mask
-// (bit l = sector l); tau is this lane's cluster position. For each hit, the
-// slot that matched is stored in slot_out[sector] (the candidate list that
-// confirmation walks).
+// Membership of the 64 lane signatures. With a Bloom filter (kept small
+// enough to stay in L2): one 8-byte filter word per sector, and only the
+// sectors that pass probe the table, each lane its own. Without one: a
+// cooperative probe in which, in round r, the 8 lanes of group g read the
+// 128-byte home bucket of sector 8r+g (16 B each) and its 16 position masks
+// (2 B each); all 16 loads are issued before any is used, so the tile pays
+// one memory latency. Returns the tile's hit mask (bit l = sector l); tau is
+// this lane's cluster position. For each hit, the slot that matched is
+// stored in slot_out[sector] (the candidate list that confirmation walks).
 __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, uint32_t tau, bool any_tau,
                                                uint32_t* __restrict__ slot_out) {
   const uint32_t l = lane_id();
+  // signature 0 cannot be stored in the table (it marks free slots)
+  const bool ok_zero = (h == kEmptyKey) && tau_ok(ix.zero_sig_mask, tau, any_tau);
+  if (ok_zero) slot_out[l] = ix.zero_slot;
+  if (ix.bloom) {
+    uint32_t w;
+    uint64_t bits;
+    bloom_place(h, ix.log2_bloom_words, &w, &bits);
+    const bool maybe = h != kEmptyKey && (ix.bloom[w] & bits) == bits;
+    bool ok = false;
+    if (maybe) {
+      const int64_t slot = find_slot(ix, h);
+      ok = slot >= 0 && tau_ok(ix.tau_mask[slot], tau, any_tau);
+      if (ok) slot_out[l] = (uint32_t)slot;
+    }
+    return ballot(ok) | ballot(ok_zero);
+  }
   const uint32_t bkt = bucket_of(h, ix.log2_buckets);
+  // per round: the bucket's slots 2(l%8), 2(l%8)+1 and their masks
   u64x2 kv[8];
   uint32_t mk[8];
-  uint64_t hs[8];
-  uint32_t ts[8];
-  uint32_t slot0[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const uint32_t s = 8u * r + (l >> 3);
-    hs[r] = shfl_u64(h, s);
-    ts[r] = (uint32_t)__shfl((int)tau, (int)s, kWave);
-    const uint32_t bs = (uint32_t)__shfl((int)bkt, (int)s, kWave);
-    slot0[r] = bs * kBucketSlots + 2u * (l & 7u);
-    kv[r] = *(const u64x2*)(ix.keys + slot0[r]);
-    mk[r] = *(const uint16_t*)(ix.tau_mask + slot0[r]);
+    const uint32_t slot0 = (uint32_t)__shfl((int)bkt, (int)s, kWave) * kBucketSlots + 2u * (l & 7u);
+    kv[r] = *(const u64x2*)(ix.keys + slot0);
+    mk[r] = *(const uint16_t*)(ix.tau_mask + slot0);
   }
   uint64_t hits = 0, unresolved = 0;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const bool live = hs[r] != kEmptyKey;
-    const bool m0 = live && kv[r].x == hs[r];
-    const bool m1 = live && kv[r].y == hs[r];
+    // the round's sector, fetched again rather than kept live across the loads
+    const uint32_t s = 8u * r + (l >> 3);
+    const uint64_t hs = shfl_u64(h, s);
+    const uint32_t ts = (uint32_t)__shfl((int)tau, (int)s, kWave);
+    const bool live = hs != kEmptyKey;
+    const bool m0 = live && kv[r].x == hs;
+    const bool m1 = live && kv[r].y == hs;
     const bool empty = !live || kv[r].x == kEmptyKey || kv[r].y == kEmptyKey;
     const uint32_t mask = m0 ? (mk[r] & 0xFFu) : (mk[r] >> 8);
-    const bool ok = (m0 | m1) && tau_ok(mask, ts[r], any_tau);
-    if (ok) slot_out[8u * r + (l >> 3)] = slot0[r] + (m1 ? 1u : 0u);
+    const bool ok = (m0 | m1) && tau_ok(mask, ts, any_tau);
+    // cross-lane reads only with every lane active: lane s may be idle inside `if (ok)`
+    const uint32_t slot0 = (uint32_t)__shfl((int)bkt, (int)s, kWave) * kBucketSlots + 2u * (l & 7u);
+    if (ok) slot_out[s] = slot0 + (m1 ? 1u : 0u);
     hits |= (uint64_t)bytes_nonzero(ballot(ok)) << (8 * r);
     unresolved |= (uint64_t)(~bytes_nonzero(ballot(m0 | m1 | empty)) & 0xFFu) << (8 * r);
   }
@@ -322,9 +339,6 @@ __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, 
     ok_more = slot >= 0 && tau_ok(ix.tau_mask[slot], tau, any_tau);
     if (ok_more) slot_out[l] = (uint32_t)slot;
   }
-  // signature 0 cannot be stored in the table (it marks free slots)
-  const bool ok_zero = (h == kEmptyKey) && tau_ok(ix.zero_sig_mask, tau, any_tau);
-  if (ok_zero) slot_out[l] = ix.zero_slot;
   return hits | ballot(ok_more) | ballot(ok_zero);
 }
 

@@ -55,11 +55,15 @@ def test_signatures_ignore_trailing_bytes():
 
 
 # ------------------------------------------------------- small adversarial
+BLOOMS = [0, carve.CARVE_BLOOM_OFF, 4]   # automatic, none, a deliberately weak filter
+
+
+@pytest.mark.parametrize("bloom", BLOOMS)
 @pytest.mark.parametrize("tau0,any_tau", [(0, False), (3, False), (7, False), (0, True), (5, True)])
-def test_small_case(tau0, any_tau):
+def test_small_case(tau0, any_tau, bloom):
     image, masters, offsets, truth = pins.small_case(seed=3)
     mflat = b"".join(masters)
-    idx = carve.build_master_index(dev_bytes(mflat), offsets)
+    idx = carve.build_master_index(dev_bytes(mflat), offsets, bloom_bits_per_key=bloom)
     img = dev_bytes(image)
     flags, matches, _ = gpu_flags_and_matches(idx, img, tau0, any_tau)
     wf, wm = oracle_flags_and_matches(np.frombuffer(mflat, np.uint8), offsets, np.frombuffer(image, np.uint8),
@@ -74,6 +78,21 @@ def test_index_stats_small():
     st = idx.stats()
     assert st["n_master_sectors"] == len(masters)
     assert st["n_unique_signatures"] == len(set(masters))
+    assert st["bloom_bytes"] > 0
+    off = carve.build_master_index(dev_bytes(b"".join(masters)), offsets, bloom_bits_per_key=carve.CARVE_BLOOM_OFF)
+    assert off.stats()["bloom_bytes"] == 0
+
+
+@pytest.mark.parametrize("bloom", BLOOMS)
+def test_tiny_config_bloom_invariance(tiny_gpu, bloom):
+    """The prefilter is an optimisation only: flags and matches do not depend on it."""
+    cfg, ms, img, idx = tiny_gpu
+    alt = carve.build_master_index(ms.sectors, ms.file_offsets, bloom_bits_per_key=bloom)
+    for tau0, any_tau in ((0, False), (0, True)):
+        f1, m1, _ = gpu_flags_and_matches(idx, img.data, tau0, any_tau)
+        f2, m2, _ = gpu_flags_and_matches(alt, img.data, tau0, any_tau)
+        assert np.array_equal(f1, f2)
+        assert_same_matches(m2, m1)
 
 
 # ------------------------------------------------------- tiny configuration
@@ -213,7 +232,8 @@ def _crafted_batch(prefix: bytes, targets):
     return out
 
 
-def test_long_probe_chains():
+@pytest.mark.parametrize("bloom", BLOOMS)
+def test_long_probe_chains(bloom):
     """Thousands of master signatures whose home bucket is bucket 0 (so they
     overflow into many later buckets), probed by present and absent sectors."""
     rng = random.Random(7)
@@ -224,7 +244,7 @@ def test_long_probe_chains():
     crafted = _crafted_batch(b"chain", targets)
     masters = crafted[:n_same] + [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(5000)]
     offsets = [0, 4000, len(masters)]
-    idx = carve.build_master_index(dev_bytes(b"".join(masters)), offsets)
+    idx = carve.build_master_index(dev_bytes(b"".join(masters)), offsets, bloom_bits_per_key=bloom)
     st = idx.stats()
     assert st["n_overflow_keys"] > 2000
     disk = []
