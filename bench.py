@@ -15,6 +15,7 @@ duration from HIP events recorded on the stream it runs on; `cpu_baseline`
 times the CPU oracle on a bounded sample of the same image.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,45 @@ sys.path.insert(0, ROOT)
 METRIC = "disk GB/s scanned (bit-exact flags) and % HBM roofline; p99 latency served"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SECTOR_ALG = 512 + 1.0 / 8.0   # read the sector once, write one flag bit
+KERNEL_SOURCES = ("paper_0901_1307_amd/csrc/carve.hip", "paper_0901_1307_amd/csrc/carve_device.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_scan_mid.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config: str, kernel_ms: float):
+    """HBM bytes per launch of the scan kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a
+    copy of known size), as a rate over this run's kernel duration; None if
+    there is no summary for this workload or the kernel changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None, None
+    if t.get("config") != config or t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None, None
+    b = float(t["fetch_bytes_per_launch"]) + float(t["write_bytes_per_launch"])
+    return round(b / (kernel_ms * 1e-3) / 1e9, 1), t
+
+
+def calibrate_copy(nbytes: int = 4 << 30, reps: int = 4):
+    """A plain device-to-device copy of known size, for scaling the FETCH_SIZE
+    and WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
 
 
 def log(*a):
@@ -82,11 +122,16 @@ def main():
     ap.add_argument("--config", default="mid", choices=["tiny", "mid", "large"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run a 4 GiB device copy (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the scan has no cross-GPU step, and only --gpus 1 is supported "
               "(sharding is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import torch
 
@@ -144,6 +189,7 @@ def main():
     value = image_bytes / (ms_per_step * 1e-3) / 1e9
     k_avg = sum(kernel_ms) / len(kernel_ms)
     achieved = n_sectors * BYTES_PER_SECTOR_ALG / (k_avg * 1e-3) / 1e9
+    traffic, traffic_src = measured_traffic(cfg.name, k_avg)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -177,8 +223,12 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "kernel_ms": round(k_avg, 4),
+            "algorithmic_bytes_per_launch": round(n_sectors * BYTES_PER_SECTOR_ALG),
+            "traffic_bytes_per_launch": (None if traffic_src is None else
+                                         round(traffic_src["fetch_bytes_per_launch"] +
+                                               traffic_src["write_bytes_per_launch"])),
         },
     }
     if not args.no_cpu_baseline:
