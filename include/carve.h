@@ -36,6 +36,7 @@ extern "C" {
 
 typedef struct carve_index carve_index; /* resident master-signature index */
 typedef struct carve_scan carve_scan;   /* result buffers of one scan      */
+typedef struct carve_batch carve_batch; /* result buffers of a batch scan  */
 
 typedef enum {
   CARVE_OK = 0,
@@ -71,6 +72,27 @@ typedef struct {
   uint32_t file_id;        /* master file index */
   uint32_t sector_in_file; /* sector index inside that file */
 } carve_match;             /* 16 bytes */
+
+typedef struct {
+  uint64_t disk_sector;    /* flagged sector id within its image */
+  uint32_t file_id;
+  uint32_t sector_in_file;
+  uint32_t image;          /* index of the image in the batch */
+  uint32_t reserved;       /* 0 */
+} carve_batch_match;       /* 24 bytes */
+
+typedef struct {
+  const void* image;       /* device, 16-B aligned (may be NULL when n_bytes < 512) */
+  uint64_t n_bytes;        /* trailing n_bytes % 512 bytes are ignored */
+  uint32_t tau0;           /* cluster position of the image's first sector, 0..7 */
+  uint32_t tau_mode;       /* carve_tau_mode */
+} carve_image_desc;        /* 24 bytes */
+
+typedef struct {
+  uint32_t blocks_per_cu;   /* work-groups of the persistent scan grid per compute unit; 0 = as many as fit */
+  uint32_t tiles_per_chunk; /* consecutive 64-sector tiles a wave takes before striding; 0 = 1 */
+  uint32_t reserved[2];     /* must be zero */
+} carve_scan_config;
 
 typedef struct {
   uint64_t n_master_sectors;
@@ -153,6 +175,48 @@ int sector_signatures(const void* sectors, uint64_t n_sectors, uint64_t* sigs, v
 /* index_stats -- sizes of a built index (host struct). */
 int index_stats(const carve_index* idx, carve_index_stats* out);
 
+/*
+ * index_set_scan_config / index_get_scan_config -- launch shape of the scan
+ * kernel for scans with this index (results never depend on it). Setting it
+ * while scans are being enqueued on other threads is a race.
+ */
+int index_set_scan_config(carve_index* idx, const carve_scan_config* cfg);
+int index_get_scan_config(const carve_index* idx, carve_scan_config* cfg);
+
+/*
+ * autotune_scan -- time the scan kernel for each candidate launch shape on a
+ * sample image (device, 16-B aligned, n_bytes >= 512) and keep the fastest
+ * for the index; *best (host, may be NULL) receives it. Synchronizes stream.
+ */
+int autotune_scan(carve_index* idx, const void* sample_image, uint64_t n_bytes, void* stream, carve_scan_config* best);
+
+/*
+ * scan_batch -- scan_image over n_images images at once: one persistent
+ * launch over all their sectors, flags compacted per image (the paper scans
+ * several disks at once, Section 3). Asynchronous on `stream`.
+ *   images   host array of n_images descriptors (images BORROWED as in scan_image).
+ *   io       in: NULL to create a batch object, or one to reuse; out: the batch.
+ * When every descriptor equals the previous call's, nothing but kernels is
+ * enqueued, so a reused call can be captured in a HIP graph and replayed.
+ * Errors: EINVAL (null idx/io/images with n_images > 0, bad descriptor --
+ * which names the image --, new descriptors during stream capture), ENOMEM, EDEVICE.
+ */
+int scan_batch(const carve_index* idx, const carve_image_desc* images, uint32_t n_images, void* stream,
+               carve_batch** io);
+
+/* batch_flag_counts -- flagged sectors per image (host array of n_images). Synchronizes. */
+int batch_flag_counts(carve_batch* b, uint64_t* counts, uint32_t n_images);
+
+/* batch_flagged_sectors -- flagged_sectors for image `image` of the batch. Synchronizes. */
+int batch_flagged_sectors(carve_batch* b, uint32_t image, uint64_t* out, uint64_t cap, uint64_t* n_out);
+
+/*
+ * batch_confirm_matches -- confirm_matches for every image of the batch,
+ * ordered by (image, disk_sector, file_id, sector_in_file). Synchronizes.
+ */
+int batch_confirm_matches(const carve_index* idx, carve_batch* b, carve_batch_match* out, uint64_t cap,
+                          uint64_t* n_out);
+
 /* scan_set_timing -- when enable != 0, later scan_image calls bracket the
  * signature/probe kernel with HIP events on the scan's stream. */
 int scan_set_timing(carve_scan* sc, int enable);
@@ -164,6 +228,7 @@ int scan_kernel_ms(carve_scan* sc, float* ms);
 
 void free_index(carve_index* idx);  /* NULL is a no-op; the caller ensures no scan is running */
 void free_scan(carve_scan* sc);     /* NULL is a no-op; waits for the scan's stream */
+void free_batch(carve_batch* b);    /* NULL is a no-op; waits for the batch's stream */
 const char* carve_last_error(void); /* message of this thread's last failure, "" if none */
 
 #ifdef __cplusplus

@@ -22,9 +22,13 @@ CARVE_SIG_DJB2_64 = 0
 CARVE_TAU_PER_CLUSTER, CARVE_TAU_ANY = 0, 1
 
 MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4")])
+BATCH_MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4"),
+                              ("image", "<u4"), ("reserved", "<u4")])
 
 EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_matches", "sector_signatures",
-           "index_stats", "scan_set_timing", "scan_kernel_ms", "free_index", "free_scan", "carve_last_error")
+           "index_stats", "index_set_scan_config", "index_get_scan_config", "autotune_scan", "scan_batch",
+           "batch_flag_counts", "batch_flagged_sectors", "batch_confirm_matches", "scan_set_timing",
+           "scan_kernel_ms", "free_index", "free_scan", "free_batch", "carve_last_error")
 
 
 class CarveError(RuntimeError):
@@ -39,6 +43,16 @@ CARVE_BLOOM_OFF = 0xFFFFFFFF
 class _IndexParams(ctypes.Structure):
     _fields_ = [("sig_kind", ctypes.c_uint32), ("max_load", ctypes.c_float), ("bloom_bits_per_key", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32 * 5)]
+
+
+class _ScanConfig(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("tiles_per_chunk", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
+
+
+class _ImageDesc(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("n_bytes", ctypes.c_uint64), ("tau0", ctypes.c_uint32),
+                ("tau_mode", ctypes.c_uint32)]
 
 
 class _IndexStats(ctypes.Structure):
@@ -74,6 +88,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sector_signatures.argtypes = [P, U64, P, P]
     lib.index_stats.restype = I32
     lib.index_stats.argtypes = [P, ctypes.POINTER(_IndexStats)]
+    lib.index_set_scan_config.restype = I32
+    lib.index_set_scan_config.argtypes = [P, ctypes.POINTER(_ScanConfig)]
+    lib.index_get_scan_config.restype = I32
+    lib.index_get_scan_config.argtypes = [P, ctypes.POINTER(_ScanConfig)]
+    lib.autotune_scan.restype = I32
+    lib.autotune_scan.argtypes = [P, P, U64, P, ctypes.POINTER(_ScanConfig)]
+    lib.scan_batch.restype = I32
+    lib.scan_batch.argtypes = [P, ctypes.POINTER(_ImageDesc), U32, P, PP]
+    lib.batch_flag_counts.restype = I32
+    lib.batch_flag_counts.argtypes = [P, P, U32]
+    lib.batch_flagged_sectors.restype = I32
+    lib.batch_flagged_sectors.argtypes = [P, U32, P, U64, PU64]
+    lib.batch_confirm_matches.restype = I32
+    lib.batch_confirm_matches.argtypes = [P, P, P, U64, PU64]
+    lib.free_batch.restype = None
+    lib.free_batch.argtypes = [P]
     lib.scan_set_timing.restype = I32
     lib.scan_set_timing.argtypes = [P, I32]
     lib.scan_kernel_ms.restype = I32
@@ -122,6 +152,23 @@ class Index:
         _check(load_library().index_stats(self.handle, ctypes.byref(st)))
         return {k: int(getattr(st, k)) for k, _ in _IndexStats._fields_}
 
+    def scan_config(self) -> dict:
+        c = _ScanConfig()
+        _check(load_library().index_get_scan_config(self.handle, ctypes.byref(c)))
+        return {"blocks_per_cu": int(c.blocks_per_cu), "tiles_per_chunk": int(c.tiles_per_chunk)}
+
+    def set_scan_config(self, blocks_per_cu: int = 0, tiles_per_chunk: int = 0):
+        c = _ScanConfig(int(blocks_per_cu), int(tiles_per_chunk))
+        _check(load_library().index_set_scan_config(self.handle, ctypes.byref(c)))
+
+    def autotune(self, sample: torch.Tensor, stream=None) -> dict:
+        """Time the candidate launch shapes on a sample image; keep the fastest."""
+        img = _dev_u8(sample, "sample")
+        c = _ScanConfig()
+        _check(load_library().autotune_scan(self.handle, img.data_ptr(), img.numel(), _stream_ptr(stream),
+                                            ctypes.byref(c)))
+        return {"blocks_per_cu": int(c.blocks_per_cu), "tiles_per_chunk": int(c.tiles_per_chunk)}
+
     def close(self):
         h, self.handle = self.handle, None
         if h:
@@ -153,6 +200,33 @@ class Scan:
         h, self.handle = self.handle, None
         if h:
             load_library().free_scan(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Result buffers of a batch scan (owns the C handle, keeps the images alive)."""
+
+    def __init__(self):
+        self.handle = None
+        self.images = None
+
+    def set_timing(self, enable: bool = True):
+        _check(load_library().scan_set_timing(self.handle, int(enable)))
+
+    def kernel_ms(self) -> float:
+        ms = ctypes.c_float()
+        _check(load_library().scan_kernel_ms(self.handle, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def close(self):
+        h, self.handle = self.handle, None
+        if h:
+            load_library().free_batch(h)
 
     def __del__(self):
         try:
@@ -266,3 +340,69 @@ def pack_master_files(files: Sequence[torch.Tensor]):
         offsets.append(offsets[-1] + n)
     data = torch.cat(parts) if parts else torch.empty(0, dtype=torch.uint8)
     return data, offsets
+
+
+def scan_batch(index: Index, images: Sequence, stream=None, batch: Optional[Batch] = None) -> Batch:
+    """Flag the sectors of many device-resident images in one launch.
+
+    images: a sequence of uint8 device tensors, or of (tensor, tau0, tau_mode)."""
+    lib = load_library()
+    descs = (_ImageDesc * max(1, len(images)))()
+    keep = []
+    for i, it in enumerate(images):
+        t, tau0, mode = (it, 0, CARVE_TAU_PER_CLUSTER) if isinstance(it, torch.Tensor) else it
+        t = _dev_u8(t, f"images[{i}]")
+        keep.append(t)
+        descs[i] = _ImageDesc(t.data_ptr() if t.numel() else None, t.numel(), int(tau0), int(mode))
+    b = batch if batch is not None else Batch()
+    h = ctypes.c_void_p(b.handle)
+    _check(lib.scan_batch(index.handle, descs, len(images), _stream_ptr(stream), ctypes.byref(h)))
+    b.handle = h.value
+    b.images = keep
+    b.index = index
+    return b
+
+
+def batch_flag_counts(batch: Batch) -> np.ndarray:
+    """Flagged sectors per image (synchronizes)."""
+    n = len(batch.images)
+    out = np.zeros(max(n, 1), dtype=np.uint64)
+    _check(load_library().batch_flag_counts(batch.handle, out.ctypes.data, n))
+    return out[:n]
+
+
+def batch_flagged_sectors(batch: Batch, image: int) -> torch.Tensor:
+    """Ascending flagged sector ids of one image of the batch (CPU int64 tensor)."""
+    lib = load_library()
+    n = ctypes.c_uint64()
+    _check(lib.batch_flagged_sectors(batch.handle, image, None, 0, ctypes.byref(n)), allow_trunc=True)
+    out = torch.empty(int(n.value), dtype=torch.int64)
+    if out.numel():
+        _check(lib.batch_flagged_sectors(batch.handle, image, out.data_ptr(), out.numel(), ctypes.byref(n)))
+    return out
+
+
+def batch_confirm_matches(index: Index, batch: Batch, out: Optional[torch.Tensor] = None):
+    """Confirmed matches of every image, ordered by (image, disk_sector, file_id,
+    sector_in_file): a numpy structured array, or the count when `out` (a
+    contiguous uint8 tensor of 24-byte records, host or device) is given."""
+    lib = load_library()
+    n = ctypes.c_uint64()
+    rec = BATCH_MATCH_DTYPE.itemsize
+    if out is None:
+        cap = 1 << 16
+        while True:
+            buf = np.zeros(cap, dtype=BATCH_MATCH_DTYPE)
+            rc = _check(lib.batch_confirm_matches(index.handle, batch.handle, buf.ctypes.data, cap, ctypes.byref(n)),
+                        allow_trunc=True)
+            if rc == CARVE_OK:
+                return buf[:int(n.value)].copy()
+            cap = int(n.value)
+    if out.dtype != torch.uint8 or not out.is_contiguous() or out.numel() % rec:
+        raise TypeError("out must be a contiguous uint8 tensor of 24-byte records")
+    cap = out.numel() // rec
+    rc = _check(lib.batch_confirm_matches(index.handle, batch.handle, out.data_ptr() if cap else None, cap,
+                                          ctypes.byref(n)), allow_trunc=True)
+    if rc == CARVE_ETRUNC:
+        raise CarveError(rc, f"{n.value} matches do not fit in {cap}")
+    return int(n.value)

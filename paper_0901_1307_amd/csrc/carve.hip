@@ -1,15 +1,24 @@
 // Kernels and C-ABI host runtime of the carving library (gfx950).
 //
-// Pipeline of one scan (Sections 3.1-3.2):
+// A scan covers one image or a batch of images. Their sectors form one tile
+// space: image after image, each padded to whole 64-sector tiles. Every
+// kernel below indexes that space, so a batch of uneven images costs no more
+// launches than one image.
+//
+// Pipeline of a scan (Sections 3.1-3.2):
 //   k_scan<kFlags>    sector loads -> djb2-64 -> cluster position -> index
-//                     probe -> one 64-bit hit word per 64 sectors (ballot)
-//   k_reduce/k_scan_blocks/k_apply   popcount prefix -> ascending sector ids
+//                     probe -> one 64-bit hit word per tile (ballot); the
+//                     matched slot of each flagged sector is recorded
+//   k_reduce / k_scan_blocks / k_apply<EmitIds>   popcount prefix ->
+//                     ascending flagged sector ids (per image, image order)
+//   k_image_offsets   (batches) where each image's ids start
 // Confirmation (Section 3.1), from the slot each flagged sector matched:
 //   k_confirm_count   512-byte comparison with every compatible candidate
 //   prefix sum        output offsets
 //   k_confirm_emit    ordered match records
 // Index build (Section 3.1, Eq. (3)):
-//   k_master_meta, k_scan<kSigs>, k_insert, k_scatter, k_sort_segments.
+//   k_master_meta, k_scan<kSigs>, k_insert, k_narrow_masks, k_scatter,
+//   k_sort_segments, k_bloom_build.
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdint.h>
@@ -35,59 +44,120 @@ constexpr int kItemsPerBlock = kBlockThreads * kItemsPerThread;   // 2048
 enum { kFlags = 0, kSigs = 1 };
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be placed
 
+// ------------------------------------------------------------ images
+// One image of a scan. tile_begin: its first tile in the scan's tile space.
+struct ImageDesc {
+  const uint8_t* base;
+  uint64_t n_sectors;
+  uint64_t tile_begin;
+  uint32_t tau0;      // cluster position of the image's first sector
+  uint32_t any_tau;   // 1: match at any cluster position
+};
+
+// Where a tile's sectors are.
+struct TileRef {
+  const uint8_t* base;   // its first sector
+  uint32_t n_valid;      // 1..64 sectors
+  uint32_t tau_first;    // cluster position of its first sector
+  uint32_t any_tau;
+  uint32_t image;
+};
+
+__device__ __forceinline__ TileRef tile_of(const ImageDesc& d, uint64_t g, uint32_t image) {
+  const uint64_t first = (g - d.tile_begin) * kTileSectors;
+  const uint64_t rem = d.n_sectors - first;
+  return TileRef{d.base + first * kSectorBytes, rem >= kTileSectors ? kTileSectors : (uint32_t)rem,
+                 (uint32_t)((first + d.tau0) & (kClusterSectors - 1)), d.any_tau, image};
+}
+
+// A scan of one image: the descriptor travels by value.
+struct OneImage {
+  ImageDesc d;
+  __device__ __forceinline__ uint64_t n_tiles() const { return (d.n_sectors + kTileSectors - 1) / kTileSectors; }
+  // `cursor` is the image of the previous lookup (tiles are visited in increasing order)
+  __device__ __forceinline__ TileRef tile(uint64_t g, uint32_t&) const { return tile_of(d, g, 0); }
+  __device__ __forceinline__ const ImageDesc& image(uint32_t) const { return d; }
+  __device__ __forceinline__ uint32_t image_of_tile(uint64_t) const { return 0; }
+};
+
+// A batch: descriptors in device memory, n + 1 of them (the last one only
+// carries the total tile count in tile_begin).
+struct ManyImages {
+  const ImageDesc* __restrict__ d;
+  uint32_t n;
+  __device__ __forceinline__ uint64_t n_tiles() const { return d[n].tile_begin; }
+  __device__ __forceinline__ TileRef tile(uint64_t g, uint32_t& cursor) const {
+    while (g >= d[cursor + 1].tile_begin) ++cursor;   // skips empty images too
+    return tile_of(d[cursor], g, cursor);
+  }
+  __device__ __forceinline__ const ImageDesc& image(uint32_t i) const { return d[i]; }
+  __device__ __forceinline__ uint32_t image_of_tile(uint64_t g) const {   // last i with d[i].tile_begin <= g
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (d[mid].tile_begin <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  }
+};
+
 // ------------------------------------------------------------------ scan
-// 4 waves per SIMD (at most 128 VGPRs): the more waves, the more sector
-// loads are in flight per compute unit.
-template <int kMode>
-__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(const uint8_t* __restrict__ image, uint64_t n_sectors,
-                                                      uint32_t tau0, uint32_t any_tau, IndexView ix,
-                                                      uint64_t wt, uint64_t* __restrict__ out,
-                                                      uint32_t* __restrict__ hit_slot) {
+// Persistent grid over the tile space: wave q takes chunks q, q + W, ... of
+// `chunk` consecutive tiles (W = waves in the grid). 4 waves per SIMD (at
+// most 128 VGPRs): the more waves, the more sector loads in flight per CU.
+template <int kMode, class Src>
+__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(
+    Src src, uint32_t chunk, IndexView ix, uint64_t wt, uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
   const uint32_t w = threadIdx.x / kWave;
   const uint32_t l = lane_id();
   uint8_t* my = lds + w * kTileLds;
-  const uint64_t n_tiles = (n_sectors + kTileSectors - 1) / kTileSectors;
-  const uint64_t stride = (uint64_t)gridDim.x * kScanWaves;
-  uint64_t t = (uint64_t)blockIdx.x * kScanWaves + w;
-  if (t >= n_tiles) return;
-  auto rows_of = [&](uint64_t tt) {
-    const uint64_t first = tt * kTileSectors;
-    const uint64_t rem = n_sectors - first;
-    return ContiguousRows{image + first * kSectorBytes, rem >= kTileSectors ? kTileSectors : (uint32_t)rem};
+  const uint64_t n_tiles = src.n_tiles();
+  const uint64_t n_waves = (uint64_t)gridDim.x * kScanWaves;
+  uint64_t g = ((uint64_t)blockIdx.x * kScanWaves + w) * chunk;
+  if (g >= n_tiles) return;
+  auto next_of = [&](uint64_t t) {
+    return ((t + 1) % chunk != 0) ? t + 1 : t + 1 + (n_waves - 1) * chunk;
   };
+  uint32_t cur = 0;
+  TileRef tr = src.tile(g, cur);
   PhaseRegs A, B;
-  load_phase<true>(rows_of(t), 0, A);
-  for (; t < n_tiles; t += stride) {
-    const ContiguousRows rows = rows_of(t);
-    const uint64_t tn = t + stride;
+  load_phase<true>(ContiguousRows{tr.base, tr.n_valid}, 0, A);
+  while (true) {
+    const uint64_t gn = next_of(g);
+    const bool more = gn < n_tiles;
+    uint32_t cur_n = cur;
+    const TileRef tn = more ? src.tile(gn, cur_n) : tr;
     // The next tile's first phase is loaded while this tile's last one is
     // hashed. Unconditionally (the last tile reloads itself): a load under a
     // branch would make the compiler wait for every load at the join.
-    const uint64_t h = tile_signature_pipelined<true>(rows, my, wt, A, B, [&](PhaseRegs& R) {
-      load_phase<true>(rows_of(tn < n_tiles ? tn : t), 0, R);
-    });
-    const uint64_t first = t * kTileSectors;
+    const uint64_t h = tile_signature_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, wt, A, B,
+                                                      [&](PhaseRegs& R) {
+                                                        load_phase<true>(ContiguousRows{tn.base, tn.n_valid}, 0, R);
+                                                      });
     if constexpr (kMode == kFlags) {
-      const uint32_t tau = (uint32_t)((first + l + tau0) & (kClusterSectors - 1));
-      uint64_t hits = tile_probe(ix, h, tau, any_tau != 0, hit_slot + first);
-      if (rows.n_valid < kTileSectors) hits &= (1ull << rows.n_valid) - 1ull;
-      if (l == 0) out[t] = hits;
+      const uint32_t tau = (tr.tau_first + l) & (kClusterSectors - 1);
+      uint64_t hits = tile_probe(ix, h, tau, tr.any_tau != 0, hit_slot + g * kTileSectors);
+      if (tr.n_valid < kTileSectors) hits &= (1ull << tr.n_valid) - 1ull;
+      if (l == 0) out[g] = hits;
     } else {
-      if (l < rows.n_valid) out[first + l] = h;
+      if (l < tr.n_valid) out[g * kTileSectors + l] = h;   // one image: tile g holds sectors 64g..
     }
+    if (!more) break;
+    g = gn;
+    cur = cur_n;
+    tr = tn;
   }
 }
 
 // -------------------------------------------------------- prefix sums
-// Item counters: the count of item i.
-struct PopcountItems {
-  const uint64_t* words;
-  __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return (uint64_t)__popcll(words[i]); }
-};
 struct U32Items {
   const uint32_t* v;
   __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return v[i]; }
+};
+struct PopcountItems {
+  const uint64_t* words;
+  __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return (uint64_t)__popcll(words[i]); }
 };
 
 template <class Items>
@@ -120,16 +190,25 @@ __global__ __launch_bounds__(kBlockThreads) void k_scan_blocks(const uint64_t* _
   if (threadIdx.x == 0) *total = carry;
 }
 
-// Bitmap -> ascending ids of set bits (id = 64*word + bit).
+// Hit words -> ascending ids of the flagged sectors, relative to their image
+// (and, for batches, the image of each).
+template <class Src>
 struct EmitIds {
+  Src src;
   const uint64_t* words;
   uint64_t* ids;
+  uint32_t* img_of;   // null for one image
   __device__ __forceinline__ uint64_t count(uint64_t i) const { return (uint64_t)__popcll(words[i]); }
   __device__ __forceinline__ void emit(uint64_t i, uint64_t pos) const {
     uint64_t x = words[i];
+    if (!x) return;
+    const uint32_t im = src.image_of_tile(i);
+    const uint64_t first = (i - src.image(im).tile_begin) * kTileSectors;
     while (x) {
       const int b = __ffsll((long long)x) - 1;
-      ids[pos++] = i * 64 + (uint64_t)b;
+      ids[pos] = first + (uint64_t)b;
+      if (img_of) img_of[pos] = im;
+      ++pos;
       x &= x - 1;
     }
   }
@@ -166,6 +245,24 @@ __global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, uint64_t n, con
 template <class T>
 __global__ void k_write_total(T* out, uint64_t n, const uint64_t* total) {
   out[n] = (T)*total;
+}
+
+// Batches: first flagged-id position of each image (img_off[n] = total), from
+// the block offsets of the compaction and the words before each boundary.
+__global__ void k_image_offsets(ManyImages src, const uint64_t* __restrict__ words,
+                                const uint64_t* __restrict__ blk_off, const uint64_t* __restrict__ total,
+                                uint64_t* __restrict__ img_off) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > src.n) return;
+  const uint64_t w = src.d[i].tile_begin;
+  if (w >= src.d[src.n].tile_begin) {
+    img_off[i] = *total;
+    return;
+  }
+  const uint64_t b = w / kItemsPerBlock;
+  uint64_t pos = blk_off[b];
+  for (uint64_t k = b * kItemsPerBlock; k < w; ++k) pos += (uint64_t)__popcll(words[k]);
+  img_off[i] = pos;
 }
 
 // A fill kernel rather than hipMemsetAsync, so the scan sequence can be
@@ -297,13 +394,34 @@ __device__ __forceinline__ bool compatible(const ConfirmView& cv, uint32_t m, ui
   return any_tau || (cv.m_k[m] & (kClusterSectors - 1)) == tau;
 }
 
+// The i-th flagged sector of a scan: its bytes, cluster position, rule and slot.
+struct Flagged {
+  const uint8_t* bytes;
+  uint64_t j;       // sector id in its image
+  uint32_t image;
+  uint32_t tau;
+  uint32_t any_tau;
+  uint32_t slot;
+};
+
+template <class Src>
+__device__ __forceinline__ Flagged flagged(const Src& src, const uint64_t* ids, const uint32_t* img_of,
+                                           const uint32_t* hit_slot, uint64_t i) {
+  const uint32_t im = img_of ? img_of[i] : 0u;
+  const ImageDesc& d = src.image(im);
+  const uint64_t j = ids[i];
+  return Flagged{d.base + j * kSectorBytes, j, im, (uint32_t)((j + d.tau0) & (kClusterSectors - 1)), d.any_tau,
+                 hit_slot[d.tile_begin * kTileSectors + j]};
+}
+
 // 16 lanes per flagged sector: compare its 512 bytes with every candidate
 // master sector of its slot at a compatible cluster position. Records the
 // number of equal ones and, for the first 64 compatible candidates, which.
-__global__ __launch_bounds__(kBlockThreads) void k_confirm_count(const uint8_t* __restrict__ image,
-                                                                const uint64_t* __restrict__ ids, uint64_t n_flagged,
-                                                                const uint32_t* __restrict__ hit_slot, uint32_t tau0,
-                                                                uint32_t any_tau, ConfirmView cv,
+template <class Src>
+__global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const uint64_t* __restrict__ ids,
+                                                                const uint32_t* __restrict__ img_of,
+                                                                uint64_t n_flagged,
+                                                                const uint32_t* __restrict__ hit_slot, ConfirmView cv,
                                                                 uint32_t* __restrict__ n_match,
                                                                 uint64_t* __restrict__ match_mask) {
   const uint32_t l = lane_id();
@@ -311,16 +429,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(const uint8_t* 
   const uint64_t per_block = kBlockThreads / kConfirmLanes;
   const uint64_t n_groups = (uint64_t)gridDim.x * per_block;
   for (uint64_t i = (uint64_t)blockIdx.x * per_block + threadIdx.x / kConfirmLanes; i < n_flagged; i += n_groups) {
-    const uint64_t j = ids[i];
-    const uint32_t slot = hit_slot[j];
-    const uint32_t tau = (uint32_t)((j + tau0) & (kClusterSectors - 1));
-    const u32x4* d = (const u32x4*)(image + j * kSectorBytes) + gl;
+    const Flagged f = flagged(src, ids, img_of, hit_slot, i);
+    const u32x4* d = (const u32x4*)f.bytes + gl;
     const u32x4 d0 = d[0], d1 = d[kConfirmLanes];
     uint32_t cnt = 0, rank = 0;
     uint64_t mask = 0;
-    for (uint32_t c = cv.cand_off[slot], e = cv.cand_off[slot + 1]; c < e; ++c) {
+    for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e; ++c) {
       const uint32_t m = cv.cand[c];
-      if (!compatible(cv, m, tau, any_tau)) continue;   // same decision in all 16 lanes
+      if (!compatible(cv, m, f.tau, f.any_tau)) continue;   // same decision in all 16 lanes
       const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * kSectorBytes) + gl;
       const u32x4 q0 = q[0], q1 = q[kConfirmLanes];
       const u32x4 x = (d0 ^ q0) | (d1 ^ q1);
@@ -348,38 +464,51 @@ __device__ __forceinline__ bool sectors_equal(const uint8_t* a, const uint8_t* b
   return true;
 }
 
+__device__ __forceinline__ void put_record(carve_match* out, uint64_t pos, uint64_t j, uint32_t f, uint32_t k,
+                                           uint32_t) {
+  carve_match r;
+  r.disk_sector = j;
+  r.file_id = f;
+  r.sector_in_file = k;
+  out[pos] = r;
+}
+__device__ __forceinline__ void put_record(carve_batch_match* out, uint64_t pos, uint64_t j, uint32_t f, uint32_t k,
+                                           uint32_t image) {
+  carve_batch_match r;
+  r.disk_sector = j;
+  r.file_id = f;
+  r.sector_in_file = k;
+  r.image = image;
+  r.reserved = 0;
+  out[pos] = r;
+}
+
 // Thread per flagged sector: its confirmed matches, in candidate (= file,
 // sector-in-file) order, at its offset of the output; records past `cap` are
 // counted but not written.
-__global__ void k_confirm_emit(const uint8_t* __restrict__ image, const uint64_t* __restrict__ ids, uint64_t n_flagged,
-                               const uint32_t* __restrict__ hit_slot, uint32_t tau0, uint32_t any_tau, ConfirmView cv,
+template <class Src, class Rec>
+__global__ void k_confirm_emit(Src src, const uint64_t* __restrict__ ids, const uint32_t* __restrict__ img_of,
+                               uint64_t n_flagged, const uint32_t* __restrict__ hit_slot, ConfirmView cv,
                                const uint64_t* __restrict__ match_mask, const uint64_t* __restrict__ out_off,
-                               carve_match* __restrict__ out, uint64_t cap) {
+                               Rec* __restrict__ out, uint64_t cap) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_flagged) return;
-  const uint64_t j = ids[i];
-  const uint32_t slot = hit_slot[j];
-  const uint32_t tau = (uint32_t)((j + tau0) & (kClusterSectors - 1));
-  const uint64_t mask = match_mask[i];
   uint64_t pos = out_off[i];
   if (pos >= cap) return;
+  const Flagged f = flagged(src, ids, img_of, hit_slot, i);
+  const uint64_t mask = match_mask[i];
   uint32_t rank = 0;
-  for (uint32_t c = cv.cand_off[slot], e = cv.cand_off[slot + 1]; c < e && pos < cap; ++c) {
+  for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e && pos < cap; ++c) {
     const uint32_t m = cv.cand[c];
-    if (!compatible(cv, m, tau, any_tau)) continue;
+    if (!compatible(cv, m, f.tau, f.any_tau)) continue;
     const bool eq = rank < 64 ? ((mask >> rank) & 1u) != 0
-                              : sectors_equal(image + j * kSectorBytes, cv.masters + (uint64_t)m * kSectorBytes);
+                              : sectors_equal(f.bytes, cv.masters + (uint64_t)m * kSectorBytes);
     ++rank;
-    if (!eq) continue;
-    carve_match r;
-    r.disk_sector = j;
-    r.file_id = cv.m_file[m];
-    r.sector_in_file = cv.m_k[m];
-    out[pos++] = r;
+    if (eq) put_record(out, pos++, f.j, cv.m_file[m], cv.m_k[m], f.image);
   }
 }
 
-// Copies min(*count, cap) ids.
+// Copies ids [begin, begin + min(*count - begin, cap)).
 __global__ void k_copy_ids(const uint64_t* __restrict__ ids, const uint64_t* __restrict__ count, uint64_t cap,
                            uint64_t* __restrict__ out) {
   const uint64_t n = *count < cap ? *count : cap;
@@ -401,15 +530,15 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
     if (e_ != hipSuccess) return fail(CARVE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-#define CARVE_TRY(expr)          \
-  do {                           \
-    int r_ = (expr);             \
+#define CARVE_TRY(expr)            \
+  do {                             \
+    int r_ = (expr);               \
     if (r_ != CARVE_OK) return r_; \
   } while (0)
 
@@ -431,6 +560,29 @@ struct DevBuf {
   T* as() const { return (T*)p; }
   void release() {
     if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// Pinned host buffer that grows on demand.
+struct HostBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int reserve(size_t need) {
+    if (need <= bytes) return CARVE_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t sz = need < 256 ? 256 : need;
+    if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) return fail(CARVE_ENOMEM, "hipHostMalloc failed");
+    bytes = sz;
+    return CARVE_OK;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+  void release() {
+    if (p) (void)hipHostFree(p);
     p = nullptr;
     bytes = 0;
   }
@@ -479,13 +631,15 @@ int scan_counts(const uint32_t* in, T* out, uint64_t n, uint64_t* d_total, DevBu
   return CARVE_OK;
 }
 
-// Blocks of a persistent grid: as many as stay resident at once (so no
-// block waits for a second round), but no more than the work needs.
+// Blocks of a persistent grid: as many as stay resident at once (capped by
+// `per_cu_cap` when non-zero) so no block waits for a second round, and no
+// more than the work needs.
 template <class Kernel>
-int resident_grid(Kernel kernel, int threads, uint64_t want) {
+int resident_grid(Kernel kernel, int threads, uint64_t want, uint32_t per_cu_cap = 0) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
     per_cu = 1;
+  if (per_cu_cap && (uint32_t)per_cu > per_cu_cap) per_cu = (int)per_cu_cap;
   const uint64_t cap = (uint64_t)device_cus() * (uint64_t)per_cu;
   return (int)(want < cap ? (want ? want : 1) : cap);
 }
@@ -505,6 +659,7 @@ struct carve_index {
   uint64_t n_overflow = 0;
   uint64_t weights = 0;
   uint32_t log2_bloom_words = 0;
+  carve_scan_config cfg{};
   DevBuf keys, tau_mask, cand_off, cand, m_file, m_k, bloom;   // tau_mask: one byte per slot
   IndexView view() const {
     return IndexView{keys.as<uint64_t>(), tau_mask.as<uint8_t>(), bloom.bytes ? bloom.as<uint64_t>() : nullptr,
@@ -516,21 +671,200 @@ struct carve_index {
   }
 };
 
+// Results of one scan (one image, or a batch of them).
 struct carve_scan {
   int device = 0;
   hipStream_t stream = nullptr;
   const carve_index* idx = nullptr;
-  const uint8_t* image = nullptr;
-  uint64_t n_sectors = 0;
-  uint32_t tau0 = 0, tau_mode = 0;
-  DevBuf bitmap, ws, ids, count, hit_slot;   // hit_slot: matched slot of each flagged sector
-  uint64_t* h_count = nullptr;               // pinned
+  bool batch = false;
+  std::vector<ImageDesc> desc;   // n_images + 1 (the last: total tiles)
+  uint32_t n_images = 0;
+  uint64_t n_tiles = 0;
+  uint64_t max_sectors = 0;      // largest id space of one image, for flagged_sectors' copy kernel
+  DevBuf d_desc;                 // batches: the descriptors on the device
+  HostBuf h_desc;                // pinned staging for their upload
+  std::vector<ImageDesc> uploaded;
+  DevBuf bitmap, ws, ids, img_of, count, hit_slot, img_off;   // hit_slot: matched slot of each flagged sector
+  HostBuf h_small, h_img_off;                                 // pinned readbacks
   // confirmation
   DevBuf n_match, match_mask, out_off, matches, cws;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timing = false, timed = false;
 };
+struct carve_batch : carve_scan {};
 
+namespace {
+
+OneImage one_image(const carve_scan* sc) { return OneImage{sc->desc[0]}; }
+ManyImages many_images(const carve_scan* sc) {
+  return ManyImages{sc->d_desc.as<ImageDesc>(), sc->n_images};
+}
+
+int read_u64(carve_scan* sc, const uint64_t* d, uint64_t* h) {
+  CARVE_TRY(sc->h_small.reserve(64));
+  HIP_TRY(hipMemcpyAsync(sc->h_small.p, d, 8, hipMemcpyDeviceToHost, sc->stream));
+  HIP_TRY(hipStreamSynchronize(sc->stream));
+  *h = sc->h_small.as<uint64_t>()[0];
+  return CARVE_OK;
+}
+
+// Device memory the kernels can write directly (else: staging + copy).
+bool is_device_memory(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();   // plain host memory: clear the sticky error
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
+
+bool same_desc(const std::vector<ImageDesc>& a, const std::vector<ImageDesc>& b) {
+  return a.size() == b.size() && (a.empty() || memcmp(a.data(), b.data(), a.size() * sizeof(ImageDesc)) == 0);
+}
+
+int validate_image(const void* image, uint64_t n_bytes, uint32_t tau0, uint32_t tau_mode, const char* who,
+                   long which) {
+  char tag[64] = "";
+  if (which >= 0) snprintf(tag, sizeof tag, " (image %ld)", which);
+  if (tau0 > 7) return fail(CARVE_EINVAL, "%s: tau0 %u > 7%s", who, tau0, tag);
+  if (tau_mode != CARVE_TAU_PER_CLUSTER && tau_mode != CARVE_TAU_ANY)
+    return fail(CARVE_EINVAL, "%s: bad tau_mode %u%s", who, tau_mode, tag);
+  if (n_bytes / kSectorBytes && !image) return fail(CARVE_EINVAL, "%s: null image%s", who, tag);
+  if ((uintptr_t)image % 16) return fail(CARVE_EINVAL, "%s: image not 16-byte aligned%s", who, tag);
+  return CARVE_OK;
+}
+
+// Launch the scan kernel, the compaction and (batches) the per-image offsets.
+template <class Src>
+int launch_scan(carve_scan* sc, const Src& src) {
+  const carve_index* idx = sc->idx;
+  hipStream_t s = sc->stream;
+  const uint64_t n_words = sc->n_tiles;
+  uint64_t* d_count = sc->count.as<uint64_t>();
+  if (n_words == 0) {   // nothing to scan: the count is zero
+    k_fill_u64<<<1, 64, 0, s>>>(d_count, 1, 0);
+    if (sc->batch) k_fill_u64<<<1, 256, 0, s>>>(sc->img_off.as<uint64_t>(), sc->n_images + 1, 0);
+    HIP_TRY(hipGetLastError());
+    return CARVE_OK;
+  }
+  if (sc->timing) HIP_TRY(hipEventRecord(sc->ev0, s));
+  const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
+  const int grid = resident_grid(k_scan<kFlags, Src>, kScanThreads, cdiv(cdiv(n_words, chunk), kScanWaves),
+                                 idx->cfg.blocks_per_cu);
+  k_scan<kFlags, Src><<<grid, kScanThreads, 0, s>>>(src, chunk, idx->view(), idx->weights, sc->bitmap.as<uint64_t>(),
+                                                    sc->hit_slot.as<uint32_t>());
+  if (sc->timing) {
+    HIP_TRY(hipEventRecord(sc->ev1, s));
+    sc->timed = true;
+  }
+  const uint64_t nb = cdiv(n_words, kItemsPerBlock);
+  uint64_t* sums = sc->ws.as<uint64_t>();
+  uint64_t* offs = sums + nb;
+  k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{sc->bitmap.as<uint64_t>()}, n_words, sums);
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, nb, offs, d_count);
+  k_apply<<<nb, kBlockThreads, 0, s>>>(
+      EmitIds<Src>{src, sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr},
+      n_words, offs);
+  if constexpr (std::is_same<Src, ManyImages>::value) {
+    k_image_offsets<<<cdiv(sc->n_images + 1, 256), 256, 0, s>>>(src, sc->bitmap.as<uint64_t>(), offs, d_count,
+                                                                sc->img_off.as<uint64_t>());
+  }
+  HIP_TRY(hipGetLastError());
+  return CARVE_OK;
+}
+
+// Buffers for a tile space of n_tiles tiles.
+int reserve_scan(carve_scan* sc) {
+  const uint64_t n_words = sc->n_tiles ? sc->n_tiles : 1;
+  const uint64_t nb = cdiv(n_words, kItemsPerBlock);
+  CARVE_TRY(sc->bitmap.reserve(n_words * 8));
+  CARVE_TRY(sc->ws.reserve(2 * nb * 8));
+  CARVE_TRY(sc->ids.reserve(n_words * kTileSectors * 8));
+  CARVE_TRY(sc->hit_slot.reserve(n_words * kTileSectors * 4));
+  CARVE_TRY(sc->count.reserve(64));
+  if (sc->batch) {
+    CARVE_TRY(sc->img_of.reserve(n_words * kTileSectors * 4));
+    CARVE_TRY(sc->img_off.reserve((sc->n_images + 1) * 8));
+  }
+  if (sc->timing && !sc->ev0) {
+    HIP_TRY(hipEventCreate(&sc->ev0));
+    HIP_TRY(hipEventCreate(&sc->ev1));
+  }
+  return CARVE_OK;
+}
+
+// Confirmation of every flagged sector of the scan into `out` (host or device).
+template <class Src, class Rec>
+int confirm_all(const carve_index* idx, carve_scan* sc, const Src& src, Rec* out, uint64_t cap, uint64_t* n_out) {
+  hipStream_t s = sc->stream;
+  *n_out = 0;
+  if (sc->n_tiles == 0) return CARVE_OK;
+  const uint64_t* d_count = sc->count.as<uint64_t>();
+  // The number of flagged sectors is read once here; the kernels below are
+  // sized from it and nothing else waits on the host until the end.
+  uint64_t nf = 0;
+  CARVE_TRY(read_u64(sc, d_count, &nf));
+  if (nf == 0) return CARVE_OK;
+  CARVE_TRY(sc->n_match.reserve(nf * 4));
+  CARVE_TRY(sc->match_mask.reserve(nf * 8));
+  CARVE_TRY(sc->out_off.reserve((nf + 1) * 8));
+  const ConfirmView cv = idx->cview();
+  const uint32_t* img_of = sc->batch ? sc->img_of.as<uint32_t>() : nullptr;
+  const uint64_t per_block = kBlockThreads / kConfirmLanes;
+  k_confirm_count<Src><<<resident_grid(k_confirm_count<Src>, kBlockThreads, cdiv(nf, per_block)), kBlockThreads, 0,
+                         s>>>(src, sc->ids.as<uint64_t>(), img_of, nf, sc->hit_slot.as<uint32_t>(), cv,
+                              sc->n_match.as<uint32_t>(), sc->match_mask.as<uint64_t>());
+  uint64_t* d_total = sc->count.as<uint64_t>() + 1;
+  CARVE_TRY(scan_counts<uint64_t>(sc->n_match.as<uint32_t>(), sc->out_off.as<uint64_t>(), nf, d_total, sc->cws, s));
+  const bool direct = cap && is_device_memory(out);
+  Rec* dst = out;
+  uint64_t dst_cap = cap;
+  if (!direct) {   // host output: stage on the device, copy after the count is known
+    uint64_t guess = sc->matches.bytes / sizeof(Rec);
+    if (guess < nf) guess = nf;
+    if (guess > cap) guess = cap;
+    CARVE_TRY(sc->matches.reserve((guess ? guess : 1) * sizeof(Rec)));
+    dst = sc->matches.as<Rec>();
+    dst_cap = guess;
+  }
+  auto emit = [&](Rec* to, uint64_t to_cap) {
+    k_confirm_emit<Src, Rec><<<cdiv(nf, 256), 256, 0, s>>>(src, sc->ids.as<uint64_t>(), img_of, nf,
+                                                          sc->hit_slot.as<uint32_t>(), cv,
+                                                          sc->match_mask.as<uint64_t>(), sc->out_off.as<uint64_t>(),
+                                                          to, to_cap);
+  };
+  emit(dst, dst_cap);
+  HIP_TRY(hipGetLastError());
+  uint64_t nm = 0;
+  CARVE_TRY(read_u64(sc, d_total, &nm));
+  *n_out = nm;
+  const uint64_t k = nm < cap ? nm : cap;
+  if (!direct && k) {
+    if (k > dst_cap) {   // the staging guess was short: emit again into a large enough buffer
+      CARVE_TRY(sc->matches.reserve(k * sizeof(Rec)));
+      emit(sc->matches.as<Rec>(), k);
+      HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipMemcpyAsync(out, sc->matches.p, k * sizeof(Rec), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (nm > cap) return fail(CARVE_ETRUNC, "confirm: %llu matches, capacity %llu", (unsigned long long)nm,
+                            (unsigned long long)cap);
+  return CARVE_OK;
+}
+
+// min(count, cap) ids starting at `first` of the scan's id list into `out`.
+int copy_ids(carve_scan* sc, uint64_t first, uint64_t n, uint64_t* out, uint64_t cap) {
+  const uint64_t k = n < cap ? n : cap;
+  if (!k) return CARVE_OK;
+  HIP_TRY(hipMemcpyAsync(out, sc->ids.as<uint64_t>() + first, k * 8, hipMemcpyDefault, sc->stream));
+  HIP_TRY(hipStreamSynchronize(sc->stream));
+  return CARVE_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
 extern "C" const char* carve_last_error(void) { return g_err.c_str(); }
 
 extern "C" int sector_signatures(const void* sectors, uint64_t n_sectors, uint64_t* sigs, void* stream) {
@@ -540,9 +874,10 @@ extern "C" int sector_signatures(const void* sectors, uint64_t n_sectors, uint64
   hipStream_t s = (hipStream_t)stream;
   const uint64_t wt = weight_table();
   if (!wt) return fail(CARVE_EDEVICE, "sector_signatures: weight table unavailable");
+  const OneImage src{ImageDesc{(const uint8_t*)sectors, n_sectors, 0, 0, 0}};
   const uint64_t n_tiles = cdiv(n_sectors, kTileSectors);
-  k_scan<kSigs><<<resident_grid(k_scan<kSigs>, kScanThreads, cdiv(n_tiles, kScanWaves)), kScanThreads, 0, s>>>(
-      (const uint8_t*)sectors, n_sectors, 0, 0, IndexView{}, wt, sigs, nullptr);
+  k_scan<kSigs, OneImage><<<resident_grid(k_scan<kSigs, OneImage>, kScanThreads, cdiv(n_tiles, kScanWaves)),
+                            kScanThreads, 0, s>>>(src, 1, IndexView{}, wt, sigs, nullptr);
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
@@ -653,8 +988,9 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
     const uint64_t n_tiles = cdiv(n_masters, kTileSectors);
     const uint64_t wt = weight_table();
     if (!wt) return bail2(fail(CARVE_EDEVICE, "build_master_index: weight table unavailable"));
-    k_scan<kSigs><<<resident_grid(k_scan<kSigs>, kScanThreads, cdiv(n_tiles, kScanWaves)), kScanThreads, 0, s>>>(
-        ix->masters, n_masters, 0, 0, IndexView{}, wt, sig.as<uint64_t>(), nullptr);
+    const OneImage src{ImageDesc{ix->masters, n_masters, 0, 0, 0}};
+    k_scan<kSigs, OneImage><<<resident_grid(k_scan<kSigs, OneImage>, kScanThreads, cdiv(n_tiles, kScanWaves)),
+                              kScanThreads, 0, s>>>(src, 1, IndexView{}, wt, sig.as<uint64_t>(), nullptr);
     k_insert<<<nbk, 256, 0, s>>>(sig.as<uint64_t>(), ix->m_k.as<uint32_t>(), n_masters, ix->keys.as<uint64_t>(), lb,
                                 mask32.as<uint32_t>(), cnt.as<uint32_t>(), m_slot.as<uint32_t>(), d_overflow,
                                 d_failed);
@@ -729,92 +1065,128 @@ extern "C" int index_stats(const carve_index* idx, carve_index_stats* out) {
   return CARVE_OK;
 }
 
+extern "C" int index_set_scan_config(carve_index* idx, const carve_scan_config* cfg) {
+  if (!idx || !cfg) return fail(CARVE_EINVAL, "index_set_scan_config: null argument");
+  if (cfg->reserved[0] || cfg->reserved[1]) return fail(CARVE_EINVAL, "index_set_scan_config: reserved must be zero");
+  if (cfg->blocks_per_cu > 64 || cfg->tiles_per_chunk > (1u << 20))
+    return fail(CARVE_EINVAL, "index_set_scan_config: out of range");
+  idx->cfg = *cfg;
+  return CARVE_OK;
+}
+
+extern "C" int index_get_scan_config(const carve_index* idx, carve_scan_config* cfg) {
+  if (!idx || !cfg) return fail(CARVE_EINVAL, "index_get_scan_config: null argument");
+  *cfg = idx->cfg;
+  return CARVE_OK;
+}
+
 extern "C" void free_scan(carve_scan* sc) {
   if (!sc) return;
   (void)hipStreamSynchronize(sc->stream);
-  for (DevBuf* b : {&sc->bitmap, &sc->ws, &sc->ids, &sc->count, &sc->hit_slot, &sc->n_match, &sc->match_mask,
-                    &sc->out_off, &sc->matches, &sc->cws})
+  for (DevBuf* b : {&sc->d_desc, &sc->bitmap, &sc->ws, &sc->ids, &sc->img_of, &sc->count, &sc->hit_slot, &sc->img_off,
+                    &sc->n_match, &sc->match_mask, &sc->out_off, &sc->matches, &sc->cws})
     b->release();
-  if (sc->h_count) (void)hipHostFree(sc->h_count);
+  sc->h_desc.release();
+  sc->h_small.release();
+  sc->h_img_off.release();
   if (sc->ev0) (void)hipEventDestroy(sc->ev0);
   if (sc->ev1) (void)hipEventDestroy(sc->ev1);
-  delete sc;
+  if (sc->batch) delete static_cast<carve_batch*>(sc);
+  else delete sc;
 }
+
+extern "C" void free_batch(carve_batch* b) { free_scan(b); }
 
 extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_bytes, uint32_t tau0,
                           uint32_t tau_mode, void* stream, carve_scan** io) {
   if (!idx || !io) return fail(CARVE_EINVAL, "scan_image: null idx or io");
-  if (tau0 > 7) return fail(CARVE_EINVAL, "scan_image: tau0 %u > 7", tau0);
-  if (tau_mode != CARVE_TAU_PER_CLUSTER && tau_mode != CARVE_TAU_ANY)
-    return fail(CARVE_EINVAL, "scan_image: bad tau_mode %u", tau_mode);
-  const uint64_t n_sectors = n_bytes / kSectorBytes;
-  if (n_sectors && !image) return fail(CARVE_EINVAL, "scan_image: null image");
-  if ((uintptr_t)image % 16) return fail(CARVE_EINVAL, "scan_image: image not 16-byte aligned");
+  CARVE_TRY(validate_image(image, n_bytes, tau0, tau_mode, "scan_image", -1));
+  if (*io && (*io)->batch) return fail(CARVE_EINVAL, "scan_image: io is a batch object");
   carve_scan* sc = *io;
-  bool created = false;
-  if (!sc) {
+  const bool created = !sc;
+  if (created) {
     sc = new carve_scan();
-    created = true;
     (void)hipGetDevice(&sc->device);
-    if (hipHostMalloc((void**)&sc->h_count, 64, hipHostMallocDefault) != hipSuccess) {
-      delete sc;
-      return fail(CARVE_ENOMEM, "scan_image: pinned allocation failed");
-    }
   }
-  auto bail = [&](int code) {
-    if (created) free_scan(sc);
-    return code;
-  };
+  const uint64_t n_sectors = n_bytes / kSectorBytes;
   sc->stream = (hipStream_t)stream;
   sc->idx = idx;
-  sc->image = (const uint8_t*)image;
-  sc->n_sectors = n_sectors;
-  sc->tau0 = tau0;
-  sc->tau_mode = tau_mode;
+  sc->n_images = 1;
+  sc->n_tiles = cdiv(n_sectors, kTileSectors);
+  sc->max_sectors = n_sectors;
+  sc->desc.assign(2, ImageDesc{});
+  sc->desc[0] = ImageDesc{(const uint8_t*)image, n_sectors, 0, tau0, tau_mode == CARVE_TAU_ANY ? 1u : 0u};
+  sc->desc[1].tile_begin = sc->n_tiles;
   sc->timed = false;
-  const uint64_t n_words = cdiv(n_sectors, 64);
-  const uint64_t nb = cdiv(n_words ? n_words : 1, kItemsPerBlock);
-  int rc;
-  if ((rc = sc->bitmap.reserve((n_words ? n_words : 1) * 8)) || (rc = sc->ws.reserve(2 * nb * 8)) ||
-      (rc = sc->ids.reserve((n_sectors ? n_sectors : 1) * 8)) || (rc = sc->count.reserve(64)) ||
-      (rc = sc->hit_slot.reserve((n_words ? n_words : 1) * 64 * 4)))   // whole tiles: the last one may overhang
-    return bail(rc);
-  hipStream_t s = sc->stream;
-  uint64_t* d_count = sc->count.as<uint64_t>();
-  if (n_sectors == 0) {   // nothing to scan: the count is zero
-    k_fill_u64<<<1, 64, 0, s>>>(d_count, 1, 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: launch failed: %s", hipGetErrorString(e)));
-    *io = sc;
-    return CARVE_OK;
+  int rc = reserve_scan(sc);
+  if (rc == CARVE_OK) rc = launch_scan(sc, one_image(sc));
+  if (rc != CARVE_OK) {
+    if (created) free_scan(sc);
+    return rc;
   }
-  if (sc->timing) {
-    if (!sc->ev0 && (hipEventCreate(&sc->ev0) != hipSuccess || hipEventCreate(&sc->ev1) != hipSuccess))
-      return bail(fail(CARVE_EDEVICE, "scan_image: event creation failed"));
-    if (hipEventRecord(sc->ev0, s) != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: event record failed"));
-  }
-  const uint64_t n_tiles = cdiv(n_sectors, kTileSectors);
-  k_scan<kFlags><<<resident_grid(k_scan<kFlags>, kScanThreads, cdiv(n_tiles, kScanWaves)), kScanThreads, 0, s>>>(
-      sc->image, n_sectors, tau0, tau_mode == CARVE_TAU_ANY ? 1u : 0u, idx->view(), idx->weights,
-      sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>());
-  if (sc->timing) {
-    if (hipEventRecord(sc->ev1, s) != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: event record failed"));
-    sc->timed = true;
-  }
-  uint64_t* sums = sc->ws.as<uint64_t>();
-  uint64_t* offs = sums + nb;
-  k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{sc->bitmap.as<uint64_t>()}, n_words, sums);
-  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, nb, offs, d_count);
-  k_apply<<<nb, kBlockThreads, 0, s>>>(EmitIds{sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>()}, n_words, offs);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_image: launch failed: %s", hipGetErrorString(e)));
   *io = sc;
+  return CARVE_OK;
+}
+
+extern "C" int scan_batch(const carve_index* idx, const carve_image_desc* images, uint32_t n_images, void* stream,
+                          carve_batch** io) {
+  if (!idx || !io || (n_images && !images)) return fail(CARVE_EINVAL, "scan_batch: null argument");
+  std::vector<ImageDesc> desc(n_images + 1);
+  uint64_t tiles = 0, max_sectors = 0;
+  for (uint32_t i = 0; i < n_images; ++i) {
+    const carve_image_desc& d = images[i];
+    CARVE_TRY(validate_image(d.image, d.n_bytes, d.tau0, d.tau_mode, "scan_batch", (long)i));
+    const uint64_t n = d.n_bytes / kSectorBytes;
+    desc[i] = ImageDesc{(const uint8_t*)d.image, n, tiles, d.tau0, d.tau_mode == CARVE_TAU_ANY ? 1u : 0u};
+    tiles += cdiv(n, kTileSectors);
+    if (n > max_sectors) max_sectors = n;
+  }
+  desc[n_images] = ImageDesc{nullptr, 0, tiles, 0, 0};
+  carve_batch* b = *io;
+  const bool created = !b;
+  if (created) {
+    b = new carve_batch();
+    b->batch = true;
+    (void)hipGetDevice(&b->device);
+  }
+  auto bail = [&](int code) {
+    if (created) free_batch(b);
+    return code;
+  };
+  b->stream = (hipStream_t)stream;
+  b->idx = idx;
+  b->n_images = n_images;
+  b->n_tiles = tiles;
+  b->max_sectors = max_sectors;
+  b->desc = desc;
+  b->timed = false;
+  int rc;
+  if ((rc = reserve_scan(b))) return bail(rc);
+  if (!same_desc(desc, b->uploaded)) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(b->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return bail(fail(CARVE_EINVAL, "scan_batch: new image descriptors while the stream is being captured"));
+    const size_t bytes = desc.size() * sizeof(ImageDesc);
+    // the staging buffer may still feed the previous upload
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(fail(CARVE_EDEVICE, "scan_batch: sync failed"));
+    if ((rc = b->d_desc.reserve(bytes)) || (rc = b->h_desc.reserve(bytes))) return bail(rc);
+    memcpy(b->h_desc.p, desc.data(), bytes);
+    if (hipMemcpyAsync(b->d_desc.p, b->h_desc.p, bytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+      return bail(fail(CARVE_EDEVICE, "scan_batch: descriptor upload failed"));
+    b->uploaded = desc;
+  }
+  if ((rc = launch_scan(b, many_images(b)))) return bail(rc);
+  *io = b;
   return CARVE_OK;
 }
 
 extern "C" int scan_set_timing(carve_scan* sc, int enable) {
   if (!sc) return fail(CARVE_EINVAL, "scan_set_timing: null scan");
   sc->timing = enable != 0;
+  if (sc->timing && !sc->ev0) {
+    HIP_TRY(hipEventCreate(&sc->ev0));
+    HIP_TRY(hipEventCreate(&sc->ev1));
+  }
   return CARVE_OK;
 }
 
@@ -826,45 +1198,23 @@ extern "C" int scan_kernel_ms(carve_scan* sc, float* ms) {
   return CARVE_OK;
 }
 
-namespace {
-int read_count(carve_scan* sc, const uint64_t* d, uint64_t* h) {
-  HIP_TRY(hipMemcpyAsync(sc->h_count, d, 8, hipMemcpyDeviceToHost, sc->stream));
-  HIP_TRY(hipStreamSynchronize(sc->stream));
-  *h = sc->h_count[0];
-  return CARVE_OK;
-}
-
-// Device memory the kernels can write directly (else: staging + copy).
-bool is_device_memory(const void* p) {
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-    (void)hipGetLastError();   // plain host memory: clear the sticky error
-    return false;
-  }
-  return a.type == hipMemoryTypeDevice;
-}
-}  // namespace
-
 extern "C" int flagged_sectors(carve_scan* sc, uint64_t* out, uint64_t cap, uint64_t* n_out) {
   if (!sc || !n_out) return fail(CARVE_EINVAL, "flagged_sectors: null argument");
+  if (sc->batch) return fail(CARVE_EINVAL, "flagged_sectors: a batch object (use batch_flagged_sectors)");
   if (cap && !out) return fail(CARVE_EINVAL, "flagged_sectors: null out with cap > 0");
   hipStream_t s = sc->stream;
   const uint64_t* d_count = sc->count.as<uint64_t>();
   uint64_t n = 0;
-  if (cap && is_device_memory(out)) {
+  if (cap && sc->n_tiles && is_device_memory(out)) {
     // copy min(count, cap) ids on the device, then one synchronization
-    const uint64_t blocks = cdiv(cap < sc->n_sectors ? cap : sc->n_sectors, 256);
-    k_copy_ids<<<(unsigned)(blocks ? (blocks < 4096 ? blocks : 4096) : 1), 256, 0, s>>>(sc->ids.as<uint64_t>(), d_count,
-                                                                                      cap, out);
+    const uint64_t most = cap < sc->max_sectors ? cap : sc->max_sectors;
+    const uint64_t blocks = cdiv(most ? most : 1, 256);
+    k_copy_ids<<<(unsigned)(blocks < 4096 ? blocks : 4096), 256, 0, s>>>(sc->ids.as<uint64_t>(), d_count, cap, out);
     HIP_TRY(hipGetLastError());
-    CARVE_TRY(read_count(sc, d_count, &n));
+    CARVE_TRY(read_u64(sc, d_count, &n));
   } else {
-    CARVE_TRY(read_count(sc, d_count, &n));
-    const uint64_t k = n < cap ? n : cap;
-    if (k) {
-      HIP_TRY(hipMemcpyAsync(out, sc->ids.p, k * 8, hipMemcpyDefault, s));
-      HIP_TRY(hipStreamSynchronize(s));
-    }
+    CARVE_TRY(read_u64(sc, d_count, &n));
+    CARVE_TRY(copy_ids(sc, 0, n, out, cap));
   }
   *n_out = n;
   if (n > cap) return fail(CARVE_ETRUNC, "flagged_sectors: %llu flagged, capacity %llu", (unsigned long long)n,
@@ -875,59 +1225,88 @@ extern "C" int flagged_sectors(carve_scan* sc, uint64_t* out, uint64_t cap, uint
 extern "C" int confirm_matches(const carve_index* idx, carve_scan* sc, carve_match* out, uint64_t cap,
                                uint64_t* n_out) {
   if (!idx || !sc || !n_out) return fail(CARVE_EINVAL, "confirm_matches: null argument");
+  if (sc->batch) return fail(CARVE_EINVAL, "confirm_matches: a batch object (use batch_confirm_matches)");
   if (cap && !out) return fail(CARVE_EINVAL, "confirm_matches: null out with cap > 0");
   if (sc->idx != idx) return fail(CARVE_EINVAL, "confirm_matches: scan was made with another index");
-  hipStream_t s = sc->stream;
-  *n_out = 0;
-  if (sc->n_sectors == 0) return CARVE_OK;
-  const uint32_t any = sc->tau_mode == CARVE_TAU_ANY ? 1u : 0u;
-  const uint64_t* d_count = sc->count.as<uint64_t>();
-  // The number of flagged sectors is read once here; the kernels below are
-  // sized from it and nothing else waits on the host until the end.
-  uint64_t nf = 0;
-  CARVE_TRY(read_count(sc, d_count, &nf));
-  if (nf == 0) return CARVE_OK;
-  CARVE_TRY(sc->n_match.reserve(nf * 4));
-  CARVE_TRY(sc->match_mask.reserve(nf * 8));
-  CARVE_TRY(sc->out_off.reserve((nf + 1) * 8));
-  const ConfirmView cv = idx->cview();
-  const uint64_t per_block = kBlockThreads / kConfirmLanes;
-  k_confirm_count<<<resident_grid(k_confirm_count, kBlockThreads, cdiv(nf, per_block)), kBlockThreads, 0, s>>>(
-      sc->image, sc->ids.as<uint64_t>(), nf, sc->hit_slot.as<uint32_t>(), sc->tau0, any, cv,
-      sc->n_match.as<uint32_t>(), sc->match_mask.as<uint64_t>());
-  uint64_t* d_total = sc->count.as<uint64_t>() + 1;
-  CARVE_TRY(scan_counts<uint64_t>(sc->n_match.as<uint32_t>(), sc->out_off.as<uint64_t>(), nf, d_total, sc->cws, s));
-  const bool direct = cap && is_device_memory(out);
-  carve_match* dst = out;
-  uint64_t dst_cap = cap;
-  if (!direct) {   // host output: stage on the device, copy after the count is known
-    uint64_t guess = sc->matches.bytes / sizeof(carve_match);
-    if (guess < nf) guess = nf;
-    if (guess > cap) guess = cap;
-    CARVE_TRY(sc->matches.reserve((guess ? guess : 1) * sizeof(carve_match)));
-    dst = sc->matches.as<carve_match>();
-    dst_cap = guess;
-  }
-  k_confirm_emit<<<cdiv(nf, 256), 256, 0, s>>>(sc->image, sc->ids.as<uint64_t>(), nf, sc->hit_slot.as<uint32_t>(),
-                                              sc->tau0, any, cv, sc->match_mask.as<uint64_t>(),
-                                              sc->out_off.as<uint64_t>(), dst, dst_cap);
-  HIP_TRY(hipGetLastError());
-  uint64_t nm = 0;
-  CARVE_TRY(read_count(sc, d_total, &nm));
-  *n_out = nm;
-  const uint64_t k = nm < cap ? nm : cap;
-  if (!direct && k) {
-    if (k > dst_cap) {   // the staging guess was short: emit again into a large enough buffer
-      CARVE_TRY(sc->matches.reserve(k * sizeof(carve_match)));
-      k_confirm_emit<<<cdiv(nf, 256), 256, 0, s>>>(sc->image, sc->ids.as<uint64_t>(), nf, sc->hit_slot.as<uint32_t>(),
-                                                  sc->tau0, any, cv, sc->match_mask.as<uint64_t>(),
-                                                  sc->out_off.as<uint64_t>(), sc->matches.as<carve_match>(), k);
-      HIP_TRY(hipGetLastError());
-    }
-    HIP_TRY(hipMemcpyAsync(out, sc->matches.p, k * sizeof(carve_match), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  }
-  if (nm > cap) return fail(CARVE_ETRUNC, "confirm_matches: %llu matches, capacity %llu", (unsigned long long)nm,
-                            (unsigned long long)cap);
+  return confirm_all(idx, sc, one_image(sc), out, cap, n_out);
+}
+
+namespace {
+int read_img_off(carve_batch* b) {
+  CARVE_TRY(b->h_img_off.reserve((b->n_images + 1) * 8));
+  HIP_TRY(hipMemcpyAsync(b->h_img_off.p, b->img_off.p, (b->n_images + 1) * 8, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
   return CARVE_OK;
+}
+}  // namespace
+
+extern "C" int batch_flag_counts(carve_batch* b, uint64_t* counts, uint32_t n_images) {
+  if (!b || (n_images && !counts)) return fail(CARVE_EINVAL, "batch_flag_counts: null argument");
+  if (n_images != b->n_images) return fail(CARVE_EINVAL, "batch_flag_counts: the batch has %u images", b->n_images);
+  if (!n_images) return CARVE_OK;
+  CARVE_TRY(read_img_off(b));
+  const uint64_t* off = b->h_img_off.as<uint64_t>();
+  for (uint32_t i = 0; i < n_images; ++i) counts[i] = off[i + 1] - off[i];
+  return CARVE_OK;
+}
+
+extern "C" int batch_flagged_sectors(carve_batch* b, uint32_t image, uint64_t* out, uint64_t cap, uint64_t* n_out) {
+  if (!b || !n_out) return fail(CARVE_EINVAL, "batch_flagged_sectors: null argument");
+  if (image >= b->n_images) return fail(CARVE_EINVAL, "batch_flagged_sectors: image %u of %u", image, b->n_images);
+  if (cap && !out) return fail(CARVE_EINVAL, "batch_flagged_sectors: null out with cap > 0");
+  CARVE_TRY(read_img_off(b));
+  const uint64_t* off = b->h_img_off.as<uint64_t>();
+  const uint64_t n = off[image + 1] - off[image];
+  CARVE_TRY(copy_ids(b, off[image], n, out, cap));
+  *n_out = n;
+  if (n > cap) return fail(CARVE_ETRUNC, "batch_flagged_sectors: %llu flagged, capacity %llu",
+                           (unsigned long long)n, (unsigned long long)cap);
+  return CARVE_OK;
+}
+
+extern "C" int batch_confirm_matches(const carve_index* idx, carve_batch* b, carve_batch_match* out, uint64_t cap,
+                                     uint64_t* n_out) {
+  if (!idx || !b || !n_out) return fail(CARVE_EINVAL, "batch_confirm_matches: null argument");
+  if (cap && !out) return fail(CARVE_EINVAL, "batch_confirm_matches: null out with cap > 0");
+  if (b->idx != idx) return fail(CARVE_EINVAL, "batch_confirm_matches: batch was made with another index");
+  return confirm_all(idx, b, many_images(b), out, cap, n_out);
+}
+
+extern "C" int autotune_scan(carve_index* idx, const void* sample_image, uint64_t n_bytes, void* stream,
+                             carve_scan_config* best) {
+  if (!idx) return fail(CARVE_EINVAL, "autotune_scan: null index");
+  if (n_bytes < kSectorBytes) return fail(CARVE_EINVAL, "autotune_scan: the sample needs at least one sector");
+  CARVE_TRY(validate_image(sample_image, n_bytes, 0, CARVE_TAU_PER_CLUSTER, "autotune_scan", -1));
+  const carve_scan_config saved = idx->cfg;
+  carve_scan* sc = nullptr;
+  carve_scan_config winner = saved;
+  float winner_ms = 1e30f;
+  const uint32_t blocks[] = {0, 3, 2};
+  const uint32_t chunks[] = {1, 2, 4, 8, 16};
+  int rc = CARVE_OK;
+  for (uint32_t bpc : blocks) {
+    for (uint32_t ch : chunks) {
+      idx->cfg = carve_scan_config{bpc, ch, {0, 0}};
+      float total = 0.f;
+      for (int rep = 0; rep < 4 && rc == CARVE_OK; ++rep) {
+        rc = scan_image(idx, sample_image, n_bytes, 0, CARVE_TAU_PER_CLUSTER, stream, &sc);
+        if (rc == CARVE_OK && rep == 0) rc = scan_set_timing(sc, 1);   // the first run only warms up
+        float ms = 0.f;
+        if (rc == CARVE_OK && rep > 0) {
+          rc = scan_kernel_ms(sc, &ms);
+          total += ms;
+        }
+      }
+      if (rc != CARVE_OK) break;
+      if (total < winner_ms) {
+        winner_ms = total;
+        winner = idx->cfg;
+      }
+    }
+    if (rc != CARVE_OK) break;
+  }
+  free_scan(sc);
+  idx->cfg = rc == CARVE_OK ? winner : saved;
+  if (rc == CARVE_OK && best) *best = winner;
+  return rc;
 }

@@ -1,0 +1,136 @@
+"""Batched scans: many uneven images in one launch give exactly the results of
+scanning each image alone (and of the CPU oracle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import assert_same_matches, gpu_flags_and_matches
+from paper_0901_1307_amd import carve
+
+pytestmark = pytest.mark.gpu
+SECTOR = 512
+
+
+@pytest.fixture(scope="module")
+def setup():
+    cfg = synth.scaled(synth.CONFIGS["mid"], n_master_sectors=20000, n_disk_sectors=1, n_files=40)
+    ms = synth.master_set(cfg, device="cuda")
+    idx = carve.build_master_index(ms.sectors, ms.file_offsets)
+    # uneven images: empty, sub-sector, one sector, ragged tails, a few thousand tiles
+    sizes = [0, 100, 512, 511 + 512 * 3, 64 * 512, 64 * 512 + 7, 1 << 20, 5 * (1 << 20) + 4096 + 13, 3 << 20]
+    images = []
+    for i, nb in enumerate(sizes):
+        n = max(nb // SECTOR, 1)
+        c = synth.scaled(cfg, n_master_sectors=cfg.n_master_sectors, n_disk_sectors=n,
+                         p_master_cluster=0.05 * (i % 3), tail_bytes=0)
+        img = synth.disk_image(c, ms, device="cuda", image_id=i).data
+        buf = torch.zeros(max(nb, 16), dtype=torch.uint8, device="cuda")
+        k = min(nb, img.numel())
+        buf[:k] = img[:k]
+        images.append((buf[:nb] if nb else buf[:0], i % 8, carve.CARVE_TAU_ANY if i % 4 == 3 else 0))
+    return ms, idx, images
+
+
+def _alone(idx, images):
+    out = []
+    for t, tau0, mode in images:
+        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
+        out.append((f, m))
+    return out
+
+
+def _check_batch(idx, b, alone):
+    counts = carve.batch_flag_counts(b)
+    assert counts.tolist() == [len(f) for f, _ in alone]
+    for i, (f, _) in enumerate(alone):
+        assert np.array_equal(carve.batch_flagged_sectors(b, i).numpy().astype(np.uint64), f)
+    bm = carve.batch_confirm_matches(idx, b)
+    want = [(i, int(r["disk_sector"]), int(r["file_id"]), int(r["sector_in_file"]))
+            for i, (_, m) in enumerate(alone) for r in m]
+    got = list(zip(bm["image"].tolist(), bm["disk_sector"].tolist(), bm["file_id"].tolist(),
+                   bm["sector_in_file"].tolist()))
+    assert got == want
+
+
+def test_batch_equals_images_alone(setup):
+    ms, idx, images = setup
+    alone = _alone(idx, images)
+    assert sum(len(f) for f, _ in alone) > 100
+    b = carve.scan_batch(idx, images)
+    _check_batch(idx, b, alone)
+    # and the oracle agrees with the images alone
+    ox = oracle.Index(ms.sectors.cpu().numpy(), ms.file_offsets, threads=oracle.default_threads())
+    for (t, tau0, mode), (f, m) in zip(images, alone):
+        host = t.cpu().numpy()
+        wf = ox.flag_image(host, tau0, mode == carve.CARVE_TAU_ANY, threads=4)
+        assert np.array_equal(f, wf)
+        assert_same_matches(m, ox.confirm_image(host, wf, tau0, mode == carve.CARVE_TAU_ANY))
+
+
+@pytest.mark.parametrize("blocks_per_cu,tiles_per_chunk", [(0, 1), (1, 1), (2, 4), (3, 16), (0, 64)])
+def test_batch_launch_shapes(setup, blocks_per_cu, tiles_per_chunk):
+    """The launch shape never changes a result."""
+    ms, idx, images = setup
+    base = idx.scan_config()
+    alone = _alone(idx, images)
+    try:
+        idx.set_scan_config(blocks_per_cu, tiles_per_chunk)
+        _check_batch(idx, carve.scan_batch(idx, images), alone)
+        for (t, tau0, mode), (f, _) in zip(images, alone):
+            g, _, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
+            assert np.array_equal(g, f)
+    finally:
+        idx.set_scan_config(base["blocks_per_cu"], base["tiles_per_chunk"])
+
+
+def test_autotune_keeps_results(setup):
+    ms, idx, images = setup
+    alone = _alone(idx, images)
+    best = idx.autotune(images[-1][0])
+    assert idx.scan_config() == best
+    _check_batch(idx, carve.scan_batch(idx, images), alone)
+
+
+def test_batch_reuse_and_graph_replay(setup):
+    """A reused batch with unchanged descriptors enqueues only kernels, so it can
+    be captured in a HIP graph; every replay equals the eager result."""
+    ms, idx, images = setup
+    alone = _alone(idx, images)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = carve.scan_batch(idx, images)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            carve.scan_batch(idx, images, batch=b)
+    for rep in range(4):
+        # eager work between replays, then the replay and its check
+        carve.scan_batch(idx, images[::-1] if rep % 2 else images[:3], batch=carve.Batch())
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _check_batch(idx, b, alone)
+
+
+def test_batch_rejects_bad_descriptor(setup):
+    ms, idx, images = setup
+    bad = list(images)
+    t = bad[6][0]
+    bad[6] = (t[1:], 0, 0)                     # misaligned
+    with pytest.raises(carve.CarveError) as e:
+        carve.scan_batch(idx, bad)
+    assert e.value.code == carve.CARVE_EINVAL and "image 6" in str(e.value)
+    bad[6] = (images[6][0], 9, 0)              # tau0 out of range
+    with pytest.raises(carve.CarveError):
+        carve.scan_batch(idx, bad)
+    # a good batch still works afterwards
+    _check_batch(idx, carve.scan_batch(idx, images), _alone(idx, images))
+
+
+def test_empty_batch(setup):
+    ms, idx, images = setup
+    b = carve.scan_batch(idx, [])
+    assert carve.batch_flag_counts(b).size == 0
+    assert len(carve.batch_confirm_matches(idx, b)) == 0
