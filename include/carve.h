@@ -207,8 +207,11 @@ int scan_batch(const carve_index* idx, const carve_image_desc* images, uint32_t 
 /* batch_flag_counts -- flagged sectors per image (host array of n_images). Synchronizes. */
 int batch_flag_counts(carve_batch* b, uint64_t* counts, uint32_t n_images);
 
-/* batch_flagged_sectors -- flagged_sectors for image `image` of the batch. Synchronizes. */
+/* batch_flagged_sectors -- flagged_sectors for image `image` of the batch, or,
+ * with image == CARVE_ALL_IMAGES, the ids of every image one after the other
+ * in image order (split them with batch_flag_counts). Synchronizes. */
 int batch_flagged_sectors(carve_batch* b, uint32_t image, uint64_t* out, uint64_t cap, uint64_t* n_out);
+#define CARVE_ALL_IMAGES 0xFFFFFFFFu
 
 /*
  * batch_confirm_matches -- confirm_matches for every image of the batch,
@@ -225,6 +228,67 @@ int scan_set_timing(carve_scan* sc, int enable);
  * scan, in milliseconds (synchronizes on its end event). EINVAL if the last
  * scan was not timed. */
 int scan_kernel_ms(carve_scan* sc, float* ms);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop over one resident index: scan jobs (disk-image chunks or
+ * flow buffers) are queued, admitted in arrival order while the image bytes
+ * admitted and not yet completed stay within a budget, and launched as one
+ * batch per free stream lane, so jobs that arrive while others run join the
+ * next batch (continuous batching) and batches on different lanes overlap on
+ * the device. Each job is scanned and, optionally, confirmed exactly as
+ * scan_image + confirm_matches would do it alone. Not thread-safe: one
+ * thread drives a server.
+ */
+typedef struct carve_server carve_server;
+
+typedef struct {
+  uint32_t n_streams;          /* stream lanes (concurrent batches); 0 = 4 */
+  uint32_t max_jobs_per_batch; /* 0 = 4096 */
+  uint64_t budget_bytes;       /* image bytes admitted and not completed; 0 = 32 GiB */
+  uint32_t confirm;            /* non-zero: confirm each job's flagged sectors */
+  uint32_t reserved[3];        /* must be zero */
+} carve_server_params;
+
+typedef struct {
+  uint64_t job_id;
+  uint64_t n_flagged;
+  uint64_t n_confirmed;        /* 0 when the server does not confirm */
+  int32_t status;              /* CARVE_OK or the error of its batch */
+  uint32_t reserved;
+} carve_job_done;
+
+typedef struct {
+  uint64_t queued_jobs, running_jobs, done_jobs;   /* done: completed and not yet released */
+  uint64_t in_flight_bytes;                        /* admitted, not completed */
+  uint64_t batches_launched, jobs_completed;
+  double host_launch_s;                            /* host time spent admitting and launching */
+  double host_retire_s;                            /* host time spent collecting results */
+} carve_server_stats;
+
+/* server_create -- idx must outlive the server. params: host or NULL. */
+int server_create(const carve_index* idx, const carve_server_params* params, carve_server** out);
+
+/* server_submit -- queue a job (host descriptor, image BORROWED until the job is
+ * released). EINVAL for a bad descriptor, EUNSUPPORTED when the job alone exceeds
+ * the budget. *job_id receives its id. Does not launch anything. */
+int server_submit(carve_server* s, const carve_image_desc* job, uint64_t* job_id);
+
+/* server_poll -- non-blocking progress: retire finished batches, admit queued
+ * jobs into free lanes and launch them. Completed jobs are reported once,
+ * in `done` (host, cap entries); *n_done receives how many were written (the
+ * rest are reported by later calls). */
+int server_poll(carve_server* s, carve_job_done* done, uint32_t cap, uint32_t* n_done);
+
+/* server_job_flags / server_job_matches -- results of a completed job
+ * (host buffers; ETRUNC + full count when short, EINVAL if not completed). */
+int server_job_flags(carve_server* s, uint64_t job_id, uint64_t* out, uint64_t cap, uint64_t* n_out);
+int server_job_matches(carve_server* s, uint64_t job_id, carve_match* out, uint64_t cap, uint64_t* n_out);
+
+/* server_release -- forget a completed job's results. */
+int server_release(carve_server* s, uint64_t job_id);
+
+int server_stats(const carve_server* s, carve_server_stats* out);
+void server_free(carve_server* s);  /* NULL is a no-op; waits for running batches */
 
 void free_index(carve_index* idx);  /* NULL is a no-op; the caller ensures no scan is running */
 void free_scan(carve_scan* sc);     /* NULL is a no-op; waits for the scan's stream */

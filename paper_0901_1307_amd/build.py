@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "carve.hip")
+SRCS = [os.path.join(HERE, "csrc", "carve.hip"), os.path.join(HERE, "csrc", "carve_server.hip")]
 LIB = os.path.join(HERE, "libcarve.so")
 ARCH = "gfx950"
 
@@ -23,7 +23,7 @@ HIPCC_FLAGS = [
 def build(verbose: bool = False, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *extra, SRC, "-o", tmp]
+    cmd = [hipcc, *HIPCC_FLAGS, *extra, *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -28,7 +28,9 @@ BATCH_MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sect
 EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_matches", "sector_signatures",
            "index_stats", "index_set_scan_config", "index_get_scan_config", "autotune_scan", "scan_batch",
            "batch_flag_counts", "batch_flagged_sectors", "batch_confirm_matches", "scan_set_timing",
-           "scan_kernel_ms", "free_index", "free_scan", "free_batch", "carve_last_error")
+           "scan_kernel_ms", "server_create", "server_submit", "server_poll", "server_job_flags",
+           "server_job_matches", "server_release", "server_stats", "server_free", "free_index", "free_scan",
+           "free_batch", "carve_last_error")
 
 
 class CarveError(RuntimeError):
@@ -38,6 +40,7 @@ class CarveError(RuntimeError):
 
 
 CARVE_BLOOM_OFF = 0xFFFFFFFF
+CARVE_ALL_IMAGES = 0xFFFFFFFF
 
 
 class _IndexParams(ctypes.Structure):
@@ -53,6 +56,23 @@ class _ScanConfig(ctypes.Structure):
 class _ImageDesc(ctypes.Structure):
     _fields_ = [("image", ctypes.c_void_p), ("n_bytes", ctypes.c_uint64), ("tau0", ctypes.c_uint32),
                 ("tau_mode", ctypes.c_uint32)]
+
+
+class _ServerParams(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_uint32), ("max_jobs_per_batch", ctypes.c_uint32),
+                ("budget_bytes", ctypes.c_uint64), ("confirm", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+
+class _JobDone(ctypes.Structure):
+    _fields_ = [("job_id", ctypes.c_uint64), ("n_flagged", ctypes.c_uint64), ("n_confirmed", ctypes.c_uint64),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("queued_jobs", ctypes.c_uint64), ("running_jobs", ctypes.c_uint64), ("done_jobs", ctypes.c_uint64),
+                ("in_flight_bytes", ctypes.c_uint64), ("batches_launched", ctypes.c_uint64),
+                ("jobs_completed", ctypes.c_uint64), ("host_launch_s", ctypes.c_double),
+                ("host_retire_s", ctypes.c_double)]
 
 
 class _IndexStats(ctypes.Structure):
@@ -102,6 +122,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.batch_flagged_sectors.argtypes = [P, U32, P, U64, PU64]
     lib.batch_confirm_matches.restype = I32
     lib.batch_confirm_matches.argtypes = [P, P, P, U64, PU64]
+    lib.server_create.restype = I32
+    lib.server_create.argtypes = [P, ctypes.POINTER(_ServerParams), PP]
+    lib.server_submit.restype = I32
+    lib.server_submit.argtypes = [P, ctypes.POINTER(_ImageDesc), PU64]
+    lib.server_poll.restype = I32
+    lib.server_poll.argtypes = [P, ctypes.POINTER(_JobDone), U32, ctypes.POINTER(ctypes.c_uint32)]
+    lib.server_job_flags.restype = I32
+    lib.server_job_flags.argtypes = [P, U64, P, U64, PU64]
+    lib.server_job_matches.restype = I32
+    lib.server_job_matches.argtypes = [P, U64, P, U64, PU64]
+    lib.server_release.restype = I32
+    lib.server_release.argtypes = [P, U64]
+    lib.server_stats.restype = I32
+    lib.server_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
+    lib.server_free.restype = None
+    lib.server_free.argtypes = [P]
     lib.free_batch.restype = None
     lib.free_batch.argtypes = [P]
     lib.scan_set_timing.restype = I32
@@ -406,3 +442,75 @@ def batch_confirm_matches(index: Index, batch: Batch, out: Optional[torch.Tensor
     if rc == CARVE_ETRUNC:
         raise CarveError(rc, f"{n.value} matches do not fit in {cap}")
     return int(n.value)
+
+
+class Server:
+    """Continuous-batching request loop over one resident index (native runtime).
+
+    submit() queues a job; poll() makes progress without blocking and returns
+    the jobs completed since the last call as (job_id, n_flagged, n_confirmed,
+    status) tuples; flags()/matches() fetch a completed job's results."""
+
+    def __init__(self, index: Index, n_streams: int = 4, max_jobs_per_batch: int = 0, budget_bytes: int = 0,
+                 confirm: bool = True):
+        lib = load_library()
+        p = _ServerParams(n_streams, max_jobs_per_batch, budget_bytes, int(confirm))
+        h = ctypes.c_void_p()
+        _check(lib.server_create(index.handle, ctypes.byref(p), ctypes.byref(h)))
+        self.handle = h.value
+        self.index = index
+        self._keep = {}
+        self._done = (_JobDone * 4096)()
+
+    def submit(self, image: torch.Tensor, tau0: int = 0, tau_mode: int = CARVE_TAU_PER_CLUSTER) -> int:
+        t = _dev_u8(image, "image")
+        d = _ImageDesc(t.data_ptr() if t.numel() else None, t.numel(), int(tau0), int(tau_mode))
+        jid = ctypes.c_uint64()
+        _check(load_library().server_submit(self.handle, ctypes.byref(d), ctypes.byref(jid)))
+        self._keep[jid.value] = t
+        return int(jid.value)
+
+    def poll(self):
+        n = ctypes.c_uint32()
+        _check(load_library().server_poll(self.handle, self._done, len(self._done), ctypes.byref(n)))
+        return [(int(r.job_id), int(r.n_flagged), int(r.n_confirmed), int(r.status))
+                for r in self._done[:n.value]]
+
+    def flags(self, job_id: int) -> np.ndarray:
+        lib = load_library()
+        n = ctypes.c_uint64()
+        _check(lib.server_job_flags(self.handle, job_id, None, 0, ctypes.byref(n)), allow_trunc=True)
+        out = np.zeros(int(n.value), dtype=np.uint64)
+        if out.size:
+            _check(lib.server_job_flags(self.handle, job_id, out.ctypes.data, out.size, ctypes.byref(n)))
+        return out
+
+    def matches(self, job_id: int) -> np.ndarray:
+        lib = load_library()
+        n = ctypes.c_uint64()
+        _check(lib.server_job_matches(self.handle, job_id, None, 0, ctypes.byref(n)), allow_trunc=True)
+        out = np.zeros(int(n.value), dtype=MATCH_DTYPE)
+        if out.size:
+            _check(lib.server_job_matches(self.handle, job_id, out.ctypes.data, out.size, ctypes.byref(n)))
+        return out
+
+    def release(self, job_id: int):
+        _check(load_library().server_release(self.handle, job_id))
+        self._keep.pop(job_id, None)
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(load_library().server_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        h, self.handle = self.handle, None
+        if h:
+            load_library().server_free(h)
+        self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -867,6 +867,10 @@ int copy_ids(carve_scan* sc, uint64_t first, uint64_t n, uint64_t* out, uint64_t
 // ================================================================ C ABI
 extern "C" const char* carve_last_error(void) { return g_err.c_str(); }
 
+extern "C" __attribute__((visibility("hidden"))) int carve_fail_msg(int code, const char* msg) {
+  return fail(code, "%s", msg);
+}
+
 extern "C" int sector_signatures(const void* sectors, uint64_t n_sectors, uint64_t* sigs, void* stream) {
   if (n_sectors == 0) return CARVE_OK;
   if (!sectors || !sigs) return fail(CARVE_EINVAL, "sector_signatures: null pointer");
@@ -1252,12 +1256,20 @@ extern "C" int batch_flag_counts(carve_batch* b, uint64_t* counts, uint32_t n_im
 
 extern "C" int batch_flagged_sectors(carve_batch* b, uint32_t image, uint64_t* out, uint64_t cap, uint64_t* n_out) {
   if (!b || !n_out) return fail(CARVE_EINVAL, "batch_flagged_sectors: null argument");
-  if (image >= b->n_images) return fail(CARVE_EINVAL, "batch_flagged_sectors: image %u of %u", image, b->n_images);
+  const bool all = image == CARVE_ALL_IMAGES;
+  if (!all && image >= b->n_images) return fail(CARVE_EINVAL, "batch_flagged_sectors: image %u of %u", image,
+                                                b->n_images);
   if (cap && !out) return fail(CARVE_EINVAL, "batch_flagged_sectors: null out with cap > 0");
-  CARVE_TRY(read_img_off(b));
-  const uint64_t* off = b->h_img_off.as<uint64_t>();
-  const uint64_t n = off[image + 1] - off[image];
-  CARVE_TRY(copy_ids(b, off[image], n, out, cap));
+  uint64_t first = 0, n = 0;
+  if (all) {
+    if (b->n_tiles) CARVE_TRY(read_u64(b, b->count.as<uint64_t>(), &n));
+  } else {
+    CARVE_TRY(read_img_off(b));
+    const uint64_t* off = b->h_img_off.as<uint64_t>();
+    first = off[image];
+    n = off[image + 1] - off[image];
+  }
+  CARVE_TRY(copy_ids(b, first, n, out, cap));
   *n_out = n;
   if (n > cap) return fail(CARVE_ETRUNC, "batch_flagged_sectors: %llu flagged, capacity %llu",
                            (unsigned long long)n, (unsigned long long)cap);

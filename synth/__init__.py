@@ -15,6 +15,7 @@ from .workloads import (  # noqa: F401
     master_set,
     master_sectors,
     scaled,
+    served_job_slices,
     served_job_specs,
     words,
 )

@@ -387,3 +387,19 @@ def served_job_specs(seed: int = 1, rate: float = 2000.0, duration: float = 60.0
     sizes = torch.exp(lo + (hi - lo) * w[1::2][:n])
     sizes = (sizes / SECTOR).floor().to(torch.int64).clamp(min=1) * SECTOR
     return [(float(t[i]), int(sizes[i]), int(sizes[i]) < any_tau_below) for i in range(n)]
+
+
+def served_job_slices(specs, pool_sectors: int, seed: int = 1):
+    """First pool sector of each served job: cluster-aligned for disk-image
+    chunks (their first sector sits at cluster position 0), any sector for
+    flow buffers. specs: served_job_specs() output."""
+    k = _key(seed, "served-slices")
+    w = words(k, torch.arange(len(specs), dtype=torch.int64))
+    out = []
+    for (t, size, flow), r in zip(specs, w.tolist()):
+        room = max(1, pool_sectors - (size + SECTOR - 1) // SECTOR)
+        first = r % room
+        if not flow:
+            first -= first % CLUSTER
+        out.append(first)
+    return out

@@ -1,0 +1,111 @@
+"""The serving loop: every job's result in the mix equals the job scanned and
+confirmed alone; admission respects the byte budget."""
+import random
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import assert_same_matches, gpu_flags_and_matches
+from paper_0901_1307_amd import carve
+
+pytestmark = pytest.mark.gpu
+SECTOR = 512
+
+
+@pytest.fixture(scope="module")
+def pool():
+    cfg = synth.scaled(synth.CONFIGS["served"], n_master_sectors=100_000, n_disk_sectors=1 << 19, n_files=300)
+    ms = synth.master_set(cfg, device="cuda")
+    img = synth.disk_image(cfg, ms, device="cuda").data        # 256 MiB pool
+    idx = carve.build_master_index(ms.sectors, ms.file_offsets)
+    return ms, idx, img
+
+
+def _jobs(img, n, seed, max_bytes=8 << 20):
+    rng = random.Random(seed)
+    jobs = []
+    for _ in range(n):
+        size = int(np.exp(rng.uniform(np.log(64 << 10), np.log(max_bytes)))) // SECTOR * SECTOR + rng.choice([0, 77])
+        flow = size < (1 << 20)
+        first = rng.randrange(0, img.numel() // SECTOR - size // SECTOR - 1)
+        if not flow and rng.random() < 0.5:
+            first -= first % 8                                    # cluster-aligned chunk
+        t = img[first * SECTOR: first * SECTOR + size]
+        jobs.append((t, 0 if flow else first % 8, carve.CARVE_TAU_ANY if flow else carve.CARVE_TAU_PER_CLUSTER))
+    return jobs
+
+
+def _drain(srv, ids):
+    done = {}
+    while len(done) < len(ids):
+        for jid, nf, nc, st in srv.poll():
+            assert st == carve.CARVE_OK
+            done[jid] = (nf, nc)
+    return done
+
+
+@pytest.mark.parametrize("n_streams,budget", [(4, 0), (2, 24 << 20), (1, 0)])
+def test_served_equals_alone(pool, n_streams, budget):
+    ms, idx, img = pool
+    jobs = _jobs(img, 60, seed=n_streams)
+    srv = carve.Server(idx, n_streams=n_streams, budget_bytes=budget)
+    ids = [srv.submit(t, tau0, mode) for t, tau0, mode in jobs]
+    done = _drain(srv, ids)
+    st = srv.stats()
+    assert st["jobs_completed"] == len(jobs) and st["in_flight_bytes"] == 0
+    assert st["batches_launched"] >= 1
+    total_flags = 0
+    for jid, (t, tau0, mode) in zip(ids, jobs):
+        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
+        assert done[jid] == (len(f), len(m))
+        assert np.array_equal(srv.flags(jid), f)
+        assert_same_matches(srv.matches(jid), m)
+        total_flags += len(f)
+        srv.release(jid)
+    assert total_flags > 0
+    srv.close()
+
+
+def test_jobs_arriving_while_others_run(pool):
+    """Jobs submitted between polls join later batches; results are unchanged."""
+    ms, idx, img = pool
+    jobs = _jobs(img, 80, seed=9)
+    srv = carve.Server(idx, n_streams=3)
+    ids, done = [], {}
+    for k, (t, tau0, mode) in enumerate(jobs):
+        ids.append(srv.submit(t, tau0, mode))
+        if k % 3 == 0:
+            for jid, nf, nc, st in srv.poll():
+                done[jid] = (nf, nc)
+    done.update(_drain(srv, [i for i in ids if i not in done]))
+    assert srv.stats()["batches_launched"] > 1
+    for jid, (t, tau0, mode) in zip(ids, jobs):
+        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
+        assert np.array_equal(srv.flags(jid), f)
+        assert_same_matches(srv.matches(jid), m)
+    srv.close()
+
+
+def test_budget_and_errors(pool):
+    ms, idx, img = pool
+    srv = carve.Server(idx, n_streams=2, budget_bytes=1 << 20)
+    with pytest.raises(carve.CarveError) as e:
+        srv.submit(img[: 2 << 20])                               # larger than the whole budget
+    assert e.value.code == carve.CARVE_EUNSUPPORTED
+    with pytest.raises(carve.CarveError):
+        srv.submit(img[1: 1 + 4096])                             # misaligned
+    with pytest.raises(carve.CarveError):
+        srv.flags(12345)                                         # no such job
+    ids = [srv.submit(img[k << 19: (k + 1) << 19]) for k in range(6)]   # 512 KiB each: 2 fit the budget
+    polls = 0
+    done = {}
+    while len(done) < len(ids):
+        st = srv.stats()
+        assert st["in_flight_bytes"] <= 1 << 20
+        for jid, nf, nc, s_ in srv.poll():
+            done[jid] = nf
+        polls += 1
+    assert srv.stats()["batches_launched"] >= 3
+    srv.close()
