@@ -59,8 +59,8 @@ typedef enum {
 typedef struct {
   uint32_t sig_kind;           /* carve_sig_kind; 0 = djb2-64 */
   float max_load;              /* hash-table load factor ceiling in (0, 0.9]; 0 = 0.5 */
-  uint32_t bloom_bits_per_key; /* prefilter in front of the table: 0 = automatic (on when a filter of
-                                  >= 6 bits per distinct signature fits in 2 MiB, so it stays in L2),
+  uint32_t bloom_bits_per_key; /* prefilter in front of the table: 0 = automatic (at least 4 bits per
+                                  distinct signature, then as many as a 4 MiB filter and 16 bits allow),
                                   CARVE_BLOOM_OFF = none, else 4..64 bits per signature */
   uint32_t reserved[5];        /* must be zero */
 } carve_index_params;
@@ -166,6 +166,15 @@ int flagged_sectors(carve_scan* sc, uint64_t* out, uint64_t cap, uint64_t* n_out
 int confirm_matches(const carve_index* idx, carve_scan* sc, carve_match* out, uint64_t cap, uint64_t* n_out);
 
 /*
+ * confirm_enqueue -- enqueue the confirmation of the last scan on its stream
+ * without waiting (the flagged count stays on the device); a later
+ * confirm_matches then only copies the records out. Lets the whole hot path be
+ * enqueued, or captured in a HIP graph, ahead of any readback. Calling
+ * confirm_matches without it enqueues the work itself.
+ */
+int confirm_enqueue(const carve_index* idx, carve_scan* sc);
+
+/*
  * sector_signatures -- djb2-64 signature (Eq. (1), Section 4) of each of
  * n_sectors packed sectors. sectors: device, 16-B aligned; sigs: device,
  * n_sectors values. Asynchronous on `stream`.
@@ -219,6 +228,9 @@ int batch_flagged_sectors(carve_batch* b, uint32_t image, uint64_t* out, uint64_
  */
 int batch_confirm_matches(const carve_index* idx, carve_batch* b, carve_batch_match* out, uint64_t cap,
                           uint64_t* n_out);
+
+/* batch_confirm_enqueue -- confirm_enqueue for a batch. */
+int batch_confirm_enqueue(const carve_index* idx, carve_batch* b);
 
 /* scan_set_timing -- when enable != 0, later scan_image calls bracket the
  * signature/probe kernel with HIP events on the scan's stream. */

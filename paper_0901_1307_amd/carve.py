@@ -28,7 +28,7 @@ BATCH_MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sect
 EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_matches", "sector_signatures",
            "index_stats", "index_set_scan_config", "index_get_scan_config", "autotune_scan", "scan_batch",
            "batch_flag_counts", "batch_flagged_sectors", "batch_confirm_matches", "scan_set_timing",
-           "scan_kernel_ms", "server_create", "server_submit", "server_poll", "server_job_flags",
+           "scan_kernel_ms", "confirm_enqueue", "batch_confirm_enqueue", "server_create", "server_submit", "server_poll", "server_job_flags",
            "server_job_matches", "server_release", "server_stats", "server_free", "free_index", "free_scan",
            "free_batch", "carve_last_error")
 
@@ -138,6 +138,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.server_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
     lib.server_free.restype = None
     lib.server_free.argtypes = [P]
+    lib.confirm_enqueue.restype = I32
+    lib.confirm_enqueue.argtypes = [P, P]
+    lib.batch_confirm_enqueue.restype = I32
+    lib.batch_confirm_enqueue.argtypes = [P, P]
     lib.free_batch.restype = None
     lib.free_batch.argtypes = [P]
     lib.scan_set_timing.restype = I32
@@ -514,3 +518,12 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def confirm_enqueue(index: Index, scan) -> None:
+    """Enqueue the confirmation of the last scan (or batch) without waiting."""
+    lib = load_library()
+    if isinstance(scan, Batch):
+        _check(lib.batch_confirm_enqueue(index.handle, scan.handle))
+    else:
+        _check(lib.confirm_enqueue(index.handle, scan.handle))

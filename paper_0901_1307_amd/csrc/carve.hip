@@ -151,6 +151,14 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
 }
 
 // -------------------------------------------------------- prefix sums
+// An item count known on the host (dev == null) or read on the device, so work
+// sized by a count the host has not seen can be enqueued without waiting.
+struct Count {
+  uint64_t v;
+  const uint64_t* dev;
+  __device__ __forceinline__ uint64_t get() const { return dev ? *dev : v; }
+};
+
 struct U32Items {
   const uint32_t* v;
   __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return v[i]; }
@@ -161,8 +169,9 @@ struct PopcountItems {
 };
 
 template <class Items>
-__global__ __launch_bounds__(kBlockThreads) void k_reduce(Items items, uint64_t n, uint64_t* __restrict__ blk_sums) {
+__global__ __launch_bounds__(kBlockThreads) void k_reduce(Items items, Count count, uint64_t* __restrict__ blk_sums) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
+  const uint64_t n = count.get();
   const uint64_t base = (uint64_t)blockIdx.x * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
   uint64_t s = 0;
 #pragma unroll
@@ -223,8 +232,9 @@ struct EmitOffsets {
 };
 
 template <class Emit>
-__global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, uint64_t n, const uint64_t* __restrict__ blk_off) {
+__global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, Count count, const uint64_t* __restrict__ blk_off) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
+  const uint64_t n = count.get();
   const uint64_t base = (uint64_t)blockIdx.x * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
   uint64_t c[kItemsPerThread];
   uint64_t s = 0;
@@ -243,8 +253,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, uint64_t n, con
 }
 
 template <class T>
-__global__ void k_write_total(T* out, uint64_t n, const uint64_t* total) {
-  out[n] = (T)*total;
+__global__ void k_write_total(T* out, Count n, const uint64_t* total) {
+  out[n.get()] = (T)*total;
 }
 
 // Batches: first flagged-id position of each image (img_off[n] = total), from
@@ -420,10 +430,11 @@ __device__ __forceinline__ Flagged flagged(const Src& src, const uint64_t* ids, 
 template <class Src>
 __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const uint64_t* __restrict__ ids,
                                                                 const uint32_t* __restrict__ img_of,
-                                                                uint64_t n_flagged,
+                                                                Count count,
                                                                 const uint32_t* __restrict__ hit_slot, ConfirmView cv,
                                                                 uint32_t* __restrict__ n_match,
                                                                 uint64_t* __restrict__ match_mask) {
+  const uint64_t n_flagged = count.get();
   const uint32_t l = lane_id();
   const uint32_t g = l / kConfirmLanes, gl = l % kConfirmLanes;
   const uint64_t per_block = kBlockThreads / kConfirmLanes;
@@ -483,28 +494,30 @@ __device__ __forceinline__ void put_record(carve_batch_match* out, uint64_t pos,
   out[pos] = r;
 }
 
-// Thread per flagged sector: its confirmed matches, in candidate (= file,
-// sector-in-file) order, at its offset of the output; records past `cap` are
-// counted but not written.
+// Thread per flagged sector (grid-stride): its confirmed matches, in
+// candidate (= file, sector-in-file) order, at its offset of the output;
+// records past `cap` are counted but not written.
 template <class Src, class Rec>
 __global__ void k_confirm_emit(Src src, const uint64_t* __restrict__ ids, const uint32_t* __restrict__ img_of,
-                               uint64_t n_flagged, const uint32_t* __restrict__ hit_slot, ConfirmView cv,
+                               Count count, const uint32_t* __restrict__ hit_slot, ConfirmView cv,
                                const uint64_t* __restrict__ match_mask, const uint64_t* __restrict__ out_off,
                                Rec* __restrict__ out, uint64_t cap) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_flagged) return;
-  uint64_t pos = out_off[i];
-  if (pos >= cap) return;
-  const Flagged f = flagged(src, ids, img_of, hit_slot, i);
-  const uint64_t mask = match_mask[i];
-  uint32_t rank = 0;
-  for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e && pos < cap; ++c) {
-    const uint32_t m = cv.cand[c];
-    if (!compatible(cv, m, f.tau, f.any_tau)) continue;
-    const bool eq = rank < 64 ? ((mask >> rank) & 1u) != 0
-                              : sectors_equal(f.bytes, cv.masters + (uint64_t)m * kSectorBytes);
-    ++rank;
-    if (eq) put_record(out, pos++, f.j, cv.m_file[m], cv.m_k[m], f.image);
+  const uint64_t n_flagged = count.get();
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_flagged;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t pos = out_off[i];
+    if (pos >= cap) continue;
+    const Flagged f = flagged(src, ids, img_of, hit_slot, i);
+    const uint64_t mask = match_mask[i];
+    uint32_t rank = 0;
+    for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e && pos < cap; ++c) {
+      const uint32_t m = cv.cand[c];
+      if (!compatible(cv, m, f.tau, f.any_tau)) continue;
+      const bool eq = rank < 64 ? ((mask >> rank) & 1u) != 0
+                                : sectors_equal(f.bytes, cv.masters + (uint64_t)m * kSectorBytes);
+      ++rank;
+      if (eq) put_record(out, pos++, f.j, cv.m_file[m], cv.m_k[m], f.image);
+    }
   }
 }
 
@@ -616,17 +629,19 @@ int device_cus() {
 }
 
 // Exclusive scan of n u32 counts into out[0..n] (out[n] = total); total also
-// left in *d_total. ws holds the block sums and offsets.
+// left in *d_total. ws holds the block sums and offsets. With n_dev, the count
+// is read on the device and n is only its upper bound.
 template <class T>
-int scan_counts(const uint32_t* in, T* out, uint64_t n, uint64_t* d_total, DevBuf& ws, hipStream_t s) {
+int scan_counts(const uint32_t* in, T* out, uint64_t n, uint64_t* d_total, DevBuf& ws, hipStream_t s,
+                const uint64_t* n_dev = nullptr) {
   const uint64_t nb = cdiv(n ? n : 1, kItemsPerBlock);
   CARVE_TRY(ws.reserve(2 * nb * sizeof(uint64_t)));
   uint64_t* sums = ws.as<uint64_t>();
   uint64_t* offs = sums + nb;
-  k_reduce<<<nb, kBlockThreads, 0, s>>>(U32Items{in}, n, sums);
+  k_reduce<<<nb, kBlockThreads, 0, s>>>(U32Items{in}, Count{n, n_dev}, sums);
   k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, nb, offs, d_total);
-  k_apply<<<nb, kBlockThreads, 0, s>>>(EmitOffsets<T>{in, out}, n, offs);
-  k_write_total<T><<<1, 1, 0, s>>>(out, n, d_total);
+  k_apply<<<nb, kBlockThreads, 0, s>>>(EmitOffsets<T>{in, out}, Count{n, n_dev}, offs);
+  k_write_total<T><<<1, 1, 0, s>>>(out, Count{n, n_dev}, d_total);
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
@@ -687,7 +702,9 @@ struct carve_scan {
   DevBuf bitmap, ws, ids, img_of, count, hit_slot, img_off;   // hit_slot: matched slot of each flagged sector
   HostBuf h_small, h_img_off;                                 // pinned readbacks
   // confirmation
-  DevBuf n_match, match_mask, out_off, matches, cws;
+  DevBuf n_match, match_mask, out_off, matches, cws;   // matches: records, rec_cap of them
+  bool confirm_enqueued = false;
+  uint64_t rec_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timing = false, timed = false;
 };
@@ -760,11 +777,11 @@ int launch_scan(carve_scan* sc, const Src& src) {
   const uint64_t nb = cdiv(n_words, kItemsPerBlock);
   uint64_t* sums = sc->ws.as<uint64_t>();
   uint64_t* offs = sums + nb;
-  k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{sc->bitmap.as<uint64_t>()}, n_words, sums);
+  k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{sc->bitmap.as<uint64_t>()}, Count{n_words, nullptr}, sums);
   k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, nb, offs, d_count);
   k_apply<<<nb, kBlockThreads, 0, s>>>(
       EmitIds<Src>{src, sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr},
-      n_words, offs);
+      Count{n_words, nullptr}, offs);
   if constexpr (std::is_same<Src, ManyImages>::value) {
     k_image_offsets<<<cdiv(sc->n_images + 1, 256), 256, 0, s>>>(src, sc->bitmap.as<uint64_t>(), offs, d_count,
                                                                 sc->img_off.as<uint64_t>());
@@ -793,59 +810,69 @@ int reserve_scan(carve_scan* sc) {
   return CARVE_OK;
 }
 
-// Confirmation of every flagged sector of the scan into `out` (host or device).
+// Enqueue the confirmation of every flagged sector of the scan. The number of
+// flagged sectors is not read back: the kernels take it from the device, and
+// buffers are sized for the most there can be, so nothing here waits.
+template <class Src, class Rec>
+int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src) {
+  hipStream_t s = sc->stream;
+  sc->confirm_enqueued = true;
+  sc->rec_cap = 0;
+  if (sc->n_tiles == 0) return CARVE_OK;
+  const uint64_t cap_f = sc->n_tiles * kTileSectors;   // flagged sectors are at most this many
+  const uint64_t* d_count = sc->count.as<uint64_t>();
+  CARVE_TRY(sc->n_match.reserve(cap_f * 4));
+  CARVE_TRY(sc->match_mask.reserve(cap_f * 8));
+  CARVE_TRY(sc->out_off.reserve((cap_f + 1) * 8));
+  // records: room for about one per eighth of the sectors (more are counted
+  // and produced again, with their exact count, when they are copied out)
+  uint64_t rec_cap = sc->matches.bytes / sizeof(Rec);
+  if (rec_cap < cap_f / 8 + 4096) rec_cap = cap_f / 8 + 4096;
+  CARVE_TRY(sc->matches.reserve(rec_cap * sizeof(Rec)));
+  sc->rec_cap = rec_cap;
+  const ConfirmView cv = idx->cview();
+  const uint32_t* img_of = sc->batch ? sc->img_of.as<uint32_t>() : nullptr;
+  const uint64_t per_block = kBlockThreads / kConfirmLanes;
+  const Count nf{cap_f, d_count};
+  k_confirm_count<Src><<<resident_grid(k_confirm_count<Src>, kBlockThreads, cdiv(cap_f, per_block)), kBlockThreads,
+                         0, s>>>(src, sc->ids.as<uint64_t>(), img_of, nf, sc->hit_slot.as<uint32_t>(), cv,
+                                 sc->n_match.as<uint32_t>(), sc->match_mask.as<uint64_t>());
+  uint64_t* d_total = sc->count.as<uint64_t>() + 1;
+  CARVE_TRY(scan_counts<uint64_t>(sc->n_match.as<uint32_t>(), sc->out_off.as<uint64_t>(), cap_f, d_total, sc->cws, s,
+                                  d_count));
+  k_confirm_emit<Src, Rec><<<resident_grid(k_confirm_emit<Src, Rec>, 256, cdiv(cap_f, 256)), 256, 0, s>>>(
+      src, sc->ids.as<uint64_t>(), img_of, nf, sc->hit_slot.as<uint32_t>(), cv, sc->match_mask.as<uint64_t>(),
+      sc->out_off.as<uint64_t>(), sc->matches.as<Rec>(), rec_cap);
+  HIP_TRY(hipGetLastError());
+  return CARVE_OK;
+}
+
+// Confirmed records of the scan into `out` (host or device), enqueueing the
+// confirmation first unless it already is. One small readback (the count),
+// then the copy.
 template <class Src, class Rec>
 int confirm_all(const carve_index* idx, carve_scan* sc, const Src& src, Rec* out, uint64_t cap, uint64_t* n_out) {
   hipStream_t s = sc->stream;
   *n_out = 0;
+  if (!sc->confirm_enqueued) CARVE_TRY((confirm_enqueue_impl<Src, Rec>(idx, sc, src)));
   if (sc->n_tiles == 0) return CARVE_OK;
-  const uint64_t* d_count = sc->count.as<uint64_t>();
-  // The number of flagged sectors is read once here; the kernels below are
-  // sized from it and nothing else waits on the host until the end.
-  uint64_t nf = 0;
-  CARVE_TRY(read_u64(sc, d_count, &nf));
-  if (nf == 0) return CARVE_OK;
-  CARVE_TRY(sc->n_match.reserve(nf * 4));
-  CARVE_TRY(sc->match_mask.reserve(nf * 8));
-  CARVE_TRY(sc->out_off.reserve((nf + 1) * 8));
-  const ConfirmView cv = idx->cview();
-  const uint32_t* img_of = sc->batch ? sc->img_of.as<uint32_t>() : nullptr;
-  const uint64_t per_block = kBlockThreads / kConfirmLanes;
-  k_confirm_count<Src><<<resident_grid(k_confirm_count<Src>, kBlockThreads, cdiv(nf, per_block)), kBlockThreads, 0,
-                         s>>>(src, sc->ids.as<uint64_t>(), img_of, nf, sc->hit_slot.as<uint32_t>(), cv,
-                              sc->n_match.as<uint32_t>(), sc->match_mask.as<uint64_t>());
-  uint64_t* d_total = sc->count.as<uint64_t>() + 1;
-  CARVE_TRY(scan_counts<uint64_t>(sc->n_match.as<uint32_t>(), sc->out_off.as<uint64_t>(), nf, d_total, sc->cws, s));
-  const bool direct = cap && is_device_memory(out);
-  Rec* dst = out;
-  uint64_t dst_cap = cap;
-  if (!direct) {   // host output: stage on the device, copy after the count is known
-    uint64_t guess = sc->matches.bytes / sizeof(Rec);
-    if (guess < nf) guess = nf;
-    if (guess > cap) guess = cap;
-    CARVE_TRY(sc->matches.reserve((guess ? guess : 1) * sizeof(Rec)));
-    dst = sc->matches.as<Rec>();
-    dst_cap = guess;
-  }
-  auto emit = [&](Rec* to, uint64_t to_cap) {
-    k_confirm_emit<Src, Rec><<<cdiv(nf, 256), 256, 0, s>>>(src, sc->ids.as<uint64_t>(), img_of, nf,
-                                                          sc->hit_slot.as<uint32_t>(), cv,
-                                                          sc->match_mask.as<uint64_t>(), sc->out_off.as<uint64_t>(),
-                                                          to, to_cap);
-  };
-  emit(dst, dst_cap);
-  HIP_TRY(hipGetLastError());
   uint64_t nm = 0;
-  CARVE_TRY(read_u64(sc, d_total, &nm));
+  CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>() + 1, &nm));
   *n_out = nm;
   const uint64_t k = nm < cap ? nm : cap;
-  if (!direct && k) {
-    if (k > dst_cap) {   // the staging guess was short: emit again into a large enough buffer
+  if (k) {
+    if (k > sc->rec_cap) {   // more records than the room enqueued: produce them again, all of them
+      uint64_t nf = 0;
+      CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>(), &nf));
       CARVE_TRY(sc->matches.reserve(k * sizeof(Rec)));
-      emit(sc->matches.as<Rec>(), k);
+      sc->rec_cap = k;
+      k_confirm_emit<Src, Rec><<<resident_grid(k_confirm_emit<Src, Rec>, 256, cdiv(nf, 256)), 256, 0, s>>>(
+          src, sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr, Count{nf, nullptr},
+          sc->hit_slot.as<uint32_t>(), idx->cview(), sc->match_mask.as<uint64_t>(), sc->out_off.as<uint64_t>(),
+          sc->matches.as<Rec>(), k);
       HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipMemcpyAsync(out, sc->matches.p, k * sizeof(Rec), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(out, sc->matches.p, k * sizeof(Rec), hipMemcpyDefault, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
   if (nm > cap) return fail(CARVE_ETRUNC, "confirm: %llu matches, capacity %llu", (unsigned long long)nm,
@@ -1015,7 +1042,8 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   {   // distinct signatures = non-empty candidate lists
     const uint64_t nb = cdiv(n_lists, kItemsPerBlock);
     if ((rc = ws.reserve(2 * nb * 8))) return bail2(rc);
-    k_reduce<<<nb, kBlockThreads, 0, s>>>(NonEmptyLists{ix->cand_off.as<uint32_t>()}, n_lists, ws.as<uint64_t>());
+    k_reduce<<<nb, kBlockThreads, 0, s>>>(NonEmptyLists{ix->cand_off.as<uint32_t>()}, Count{n_lists, nullptr},
+                                          ws.as<uint64_t>());
     k_scan_blocks<<<1, kBlockThreads, 0, s>>>(ws.as<uint64_t>(), nb, ws.as<uint64_t>() + nb, d_total + 1);
     BUILD_TRY(hipGetLastError());
   }
@@ -1032,12 +1060,16 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   ix->zero_sig_mask = zmask;
   ix->n_unique = h_unique;
   {   // prefilter: words of 64 bits, a power of two of them
-    constexpr uint64_t kAutoBytes = 2ull << 20;
+    // Automatic size (measured on 1M, 4M and 16M signatures): at least 4 bits
+    // per signature, then as large as 4 MiB and 16 bits per signature allow.
+    // A filter word per sector costs less traffic than a bucket line even
+    // where the filter no longer fits in L2.
+    constexpr uint64_t kAutoBytes = 4ull << 20;
     const uint64_t keys_n = h_unique ? h_unique : 1;
     uint32_t lw = 0;
-    if (p.bloom_bits_per_key == 0) {   // largest filter within kAutoBytes, if it gives >= 6 bits per key
+    if (p.bloom_bits_per_key == 0) {
+      while ((64ull << lw) < 4 * keys_n) ++lw;
       while ((8ull << (lw + 1)) <= kAutoBytes && (64ull << lw) < 16 * keys_n) ++lw;
-      if ((64ull << lw) < 6 * keys_n) lw = 0;
     } else if (p.bloom_bits_per_key != CARVE_BLOOM_OFF) {
       while ((64ull << lw) < (uint64_t)p.bloom_bits_per_key * keys_n) ++lw;
     }
@@ -1122,6 +1154,7 @@ extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_
   sc->desc[0] = ImageDesc{(const uint8_t*)image, n_sectors, 0, tau0, tau_mode == CARVE_TAU_ANY ? 1u : 0u};
   sc->desc[1].tile_begin = sc->n_tiles;
   sc->timed = false;
+  sc->confirm_enqueued = false;
   int rc = reserve_scan(sc);
   if (rc == CARVE_OK) rc = launch_scan(sc, one_image(sc));
   if (rc != CARVE_OK) {
@@ -1164,6 +1197,7 @@ extern "C" int scan_batch(const carve_index* idx, const carve_image_desc* images
   b->max_sectors = max_sectors;
   b->desc = desc;
   b->timed = false;
+  b->confirm_enqueued = false;
   int rc;
   if ((rc = reserve_scan(b))) return bail(rc);
   if (!same_desc(desc, b->uploaded)) {
@@ -1233,6 +1267,19 @@ extern "C" int confirm_matches(const carve_index* idx, carve_scan* sc, carve_mat
   if (cap && !out) return fail(CARVE_EINVAL, "confirm_matches: null out with cap > 0");
   if (sc->idx != idx) return fail(CARVE_EINVAL, "confirm_matches: scan was made with another index");
   return confirm_all(idx, sc, one_image(sc), out, cap, n_out);
+}
+
+extern "C" int confirm_enqueue(const carve_index* idx, carve_scan* sc) {
+  if (!idx || !sc) return fail(CARVE_EINVAL, "confirm_enqueue: null argument");
+  if (sc->batch) return fail(CARVE_EINVAL, "confirm_enqueue: a batch object (use batch_confirm_enqueue)");
+  if (sc->idx != idx) return fail(CARVE_EINVAL, "confirm_enqueue: scan was made with another index");
+  return confirm_enqueue_impl<OneImage, carve_match>(idx, sc, one_image(sc));
+}
+
+extern "C" int batch_confirm_enqueue(const carve_index* idx, carve_batch* b) {
+  if (!idx || !b) return fail(CARVE_EINVAL, "batch_confirm_enqueue: null argument");
+  if (b->idx != idx) return fail(CARVE_EINVAL, "batch_confirm_enqueue: batch was made with another index");
+  return confirm_enqueue_impl<ManyImages, carve_batch_match>(idx, b, many_images(b));
 }
 
 namespace {

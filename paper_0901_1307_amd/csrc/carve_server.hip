@@ -185,6 +185,9 @@ int launch(carve_server* s, Lane& ln) {
   }
   if (ln.jobs.empty()) return CARVE_OK;
   int rc = scan_batch(s->idx, s->descs.data(), (uint32_t)s->descs.size(), ln.stream, &ln.batch);
+  // confirmation queued right behind the scan: at retirement only copies remain,
+  // and no lane's readback waits for kernels queued behind another lane's scan
+  if (rc == CARVE_OK && s->p.confirm) rc = batch_confirm_enqueue(s->idx, ln.batch);
   if (rc == CARVE_OK && hipEventRecord(ln.done, ln.stream) != hipSuccess)
     rc = carve_fail_msg(CARVE_EDEVICE, "server: event record failed");
   if (rc != CARVE_OK) {   // the jobs fail with the batch's error

@@ -102,9 +102,12 @@ def test_batch_reuse_and_graph_replay(setup):
     with torch.cuda.stream(stream):
         b = carve.scan_batch(idx, images)
         torch.cuda.synchronize()
+        carve.confirm_enqueue(idx, b)
+        torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=stream):
+        with torch.cuda.graph(g, stream=stream):   # the whole hot path: scan and confirmation
             carve.scan_batch(idx, images, batch=b)
+            carve.confirm_enqueue(idx, b)
     for rep in range(4):
         # eager work between replays, then the replay and its check
         carve.scan_batch(idx, images[::-1] if rep % 2 else images[:3], batch=carve.Batch())

@@ -315,3 +315,34 @@ def test_invalid_arguments():
         carve.confirm_matches(idx, sc, rec)
     assert e.value.code == carve.CARVE_ETRUNC
     assert len(carve.confirm_matches(idx, sc)) == 4
+
+
+def test_confirm_enqueue_then_copy(tiny_gpu):
+    """Confirmation enqueued right after the scan, copied later, equals the direct path."""
+    cfg, ms, img, idx = tiny_gpu
+    f, m, sc = gpu_flags_and_matches(idx, img.data)
+    carve.scan_image(idx, img.data, scan=sc)
+    carve.confirm_enqueue(idx, sc)
+    assert_same_matches(carve.confirm_matches(idx, sc), m)
+    assert np.array_equal(carve.flagged_sectors(sc).numpy().astype(np.uint64), f)
+
+
+@pytest.mark.parametrize("any_tau", [False, True])
+def test_more_matches_than_enqueued_room(any_tau):
+    """Records beyond the room reserved at enqueue time are produced again on copy."""
+    rng = random.Random(13)
+    masters, offsets = [], [0]
+    for f in range(100):
+        sec = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(10)]
+        sec[3] = bytes(SECTOR)
+        masters += sec
+        offsets.append(len(masters))
+    idx = carve.build_master_index(dev_bytes(b"".join(masters)), offsets)
+    img = torch.zeros(1000 * SECTOR, dtype=torch.uint8, device="cuda")
+    sc = carve.scan_image(idx, img, tau_mode=carve.CARVE_TAU_ANY if any_tau else 0)
+    carve.confirm_enqueue(idx, sc)
+    got = carve.confirm_matches(idx, sc)
+    wf, wm = oracle_flags_and_matches(np.frombuffer(b"".join(masters), np.uint8), offsets,
+                                      np.zeros(1000 * SECTOR, np.uint8), any_tau=any_tau)
+    assert len(wm) == (100_000 if any_tau else 12_500)
+    assert_same_matches(got, wm)
