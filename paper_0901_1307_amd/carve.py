@@ -24,12 +24,16 @@ CARVE_TAU_PER_CLUSTER, CARVE_TAU_ANY = 0, 1
 MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4")])
 BATCH_MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4"),
                               ("image", "<u4"), ("reserved", "<u4")])
+# carve_image_desc and carve_job_done as numpy records (bulk submission and polling)
+IMAGE_DESC_DTYPE = np.dtype([("image", "<u8"), ("n_bytes", "<u8"), ("tau0", "<u4"), ("tau_mode", "<u4")])
+JOB_DONE_DTYPE = np.dtype([("job_id", "<u8"), ("n_flagged", "<u8"), ("n_confirmed", "<u8"), ("status", "<i4"),
+                           ("reserved", "<u4")])
 
 EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_matches", "sector_signatures",
            "index_stats", "index_set_scan_config", "index_get_scan_config", "autotune_scan", "scan_batch",
            "batch_flag_counts", "batch_flagged_sectors", "batch_confirm_matches", "scan_set_timing",
-           "scan_kernel_ms", "confirm_enqueue", "batch_confirm_enqueue", "server_create", "server_submit", "server_poll", "server_job_flags",
-           "server_job_matches", "server_release", "server_stats", "server_free", "free_index", "free_scan",
+           "scan_kernel_ms", "confirm_enqueue", "batch_confirm_enqueue", "server_create", "server_submit", "server_submit_many", "server_poll", "server_job_flags",
+           "server_job_matches", "server_release", "server_release_many", "server_stats", "server_free", "free_index", "free_scan",
            "free_batch", "carve_last_error")
 
 
@@ -134,6 +138,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.server_job_matches.argtypes = [P, U64, P, U64, PU64]
     lib.server_release.restype = I32
     lib.server_release.argtypes = [P, U64]
+    lib.server_submit_many.restype = I32
+    lib.server_submit_many.argtypes = [P, P, U32, P]
+    lib.server_release_many.restype = I32
+    lib.server_release_many.argtypes = [P, P, U32]
     lib.server_stats.restype = I32
     lib.server_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
     lib.server_free.restype = None
@@ -474,11 +482,26 @@ class Server:
         self._keep[jid.value] = t
         return int(jid.value)
 
+    def submit_many(self, descs: np.ndarray) -> np.ndarray:
+        """Queue every row of an IMAGE_DESC_DTYPE array (see image_descs) in one
+        call; returns the job ids. The caller keeps the images alive until the
+        jobs are released."""
+        descs = np.ascontiguousarray(descs, dtype=IMAGE_DESC_DTYPE)
+        ids = np.empty(len(descs), dtype=np.uint64)
+        _check(load_library().server_submit_many(self.handle, descs.ctypes.data, len(descs), ids.ctypes.data))
+        return ids
+
     def poll(self):
         n = ctypes.c_uint32()
         _check(load_library().server_poll(self.handle, self._done, len(self._done), ctypes.byref(n)))
         return [(int(r.job_id), int(r.n_flagged), int(r.n_confirmed), int(r.status))
                 for r in self._done[:n.value]]
+
+    def poll_array(self) -> np.ndarray:
+        """poll() as a JOB_DONE_DTYPE array."""
+        n = ctypes.c_uint32()
+        _check(load_library().server_poll(self.handle, self._done, len(self._done), ctypes.byref(n)))
+        return np.frombuffer(self._done, dtype=JOB_DONE_DTYPE, count=n.value).copy()
 
     def flags(self, job_id: int) -> np.ndarray:
         lib = load_library()
@@ -502,6 +525,13 @@ class Server:
         _check(load_library().server_release(self.handle, job_id))
         self._keep.pop(job_id, None)
 
+    def release_many(self, job_ids) -> None:
+        ids = np.ascontiguousarray(job_ids, dtype=np.uint64)
+        _check(load_library().server_release_many(self.handle, ids.ctypes.data, len(ids)))
+        if self._keep:
+            for j in ids.tolist():
+                self._keep.pop(j, None)
+
     def stats(self) -> dict:
         st = _ServerStats()
         _check(load_library().server_stats(self.handle, ctypes.byref(st)))
@@ -518,6 +548,15 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def image_descs(jobs) -> np.ndarray:
+    """IMAGE_DESC_DTYPE array from (uint8 device tensor, tau0, tau_mode) tuples."""
+    out = np.zeros(len(jobs), dtype=IMAGE_DESC_DTYPE)
+    for i, (t, tau0, mode) in enumerate(jobs):
+        t = _dev_u8(t, "image")
+        out[i] = (t.data_ptr() if t.numel() else 0, t.numel(), int(tau0), int(mode))
+    return out
 
 
 def confirm_enqueue(index: Index, scan) -> None:

@@ -30,6 +30,7 @@
 
 #include "../../include/carve.h"
 #include "carve_device.h"
+#include "carve_internal.h"
 
 using namespace carve;
 
@@ -258,21 +259,50 @@ __global__ void k_write_total(T* out, Count n, const uint64_t* total) {
 }
 
 // Batches: first flagged-id position of each image (img_off[n] = total), from
-// the block offsets of the compaction and the words before each boundary.
+// the block offsets of the compaction and the words of the image's block that
+// precede its first tile. One wave per image: its lanes popcount those words
+// (at most kItemsPerBlock - 1) in strides of the wave, then add up.
 __global__ void k_image_offsets(ManyImages src, const uint64_t* __restrict__ words,
                                 const uint64_t* __restrict__ blk_off, const uint64_t* __restrict__ total,
                                 uint64_t* __restrict__ img_off) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;   // uniform in the wave
+  const uint32_t lane = threadIdx.x % kWave;
   if (i > src.n) return;
   const uint64_t w = src.d[i].tile_begin;
   if (w >= src.d[src.n].tile_begin) {
-    img_off[i] = *total;
+    if (lane == 0) img_off[i] = *total;
     return;
   }
   const uint64_t b = w / kItemsPerBlock;
-  uint64_t pos = blk_off[b];
-  for (uint64_t k = b * kItemsPerBlock; k < w; ++k) pos += (uint64_t)__popcll(words[k]);
-  img_off[i] = pos;
+  uint32_t c = 0;
+  for (uint64_t k = b * kItemsPerBlock + lane; k < w; k += kWave) c += (uint32_t)__popcll(words[k]);
+  for (int o = kWave / 2; o; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
+  if (lane == 0) img_off[i] = blk_off[b] + c;
+}
+
+// Batches, for callers that cannot wait: totals, per-image offsets, ids and
+// records written straight into host-visible memory, each up to its capacity.
+// Records are copied as 64-bit words (a record is three of them).
+__global__ void k_stage_out(const uint64_t* __restrict__ counts, int with_matches, uint32_t n_images,
+                            const uint64_t* __restrict__ img_off, const uint64_t* __restrict__ ids,
+                            const uint64_t* __restrict__ rec_words, uint64_t rec_room, uint64_t* totals,
+                            uint64_t* h_off, uint64_t* h_ids, uint64_t ids_cap, uint64_t* h_rec_words,
+                            uint64_t rec_cap) {
+  static_assert(sizeof(carve_batch_match) == 24, "a batch record is three 64-bit words");
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t nf = counts[0];
+  const uint64_t nm = with_matches ? counts[1] : 0;
+  if (t == 0) {
+    totals[0] = nf;
+    totals[1] = nm;
+  }
+  for (uint64_t i = t; i <= n_images; i += stride) h_off[i] = img_off[i];
+  const uint64_t kf = nf < ids_cap ? nf : ids_cap;
+  for (uint64_t i = t; i < kf; i += stride) h_ids[i] = ids[i];
+  uint64_t km = nm < rec_room ? nm : rec_room;
+  if (km > rec_cap) km = rec_cap;
+  for (uint64_t i = t; i < 3 * km; i += stride) h_rec_words[i] = rec_words[i];
 }
 
 // A fill kernel rather than hipMemsetAsync, so the scan sequence can be
@@ -783,8 +813,9 @@ int launch_scan(carve_scan* sc, const Src& src) {
       EmitIds<Src>{src, sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr},
       Count{n_words, nullptr}, offs);
   if constexpr (std::is_same<Src, ManyImages>::value) {
-    k_image_offsets<<<cdiv(sc->n_images + 1, 256), 256, 0, s>>>(src, sc->bitmap.as<uint64_t>(), offs, d_count,
-                                                                sc->img_off.as<uint64_t>());
+    const uint64_t per_block = kBlockThreads / kWave;
+    k_image_offsets<<<cdiv(sc->n_images + 1, per_block), kBlockThreads, 0, s>>>(
+        src, sc->bitmap.as<uint64_t>(), offs, d_count, sc->img_off.as<uint64_t>());
   }
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
@@ -813,6 +844,22 @@ int reserve_scan(carve_scan* sc) {
 // Enqueue the confirmation of every flagged sector of the scan. The number of
 // flagged sectors is not read back: the kernels take it from the device, and
 // buffers are sized for the most there can be, so nothing here waits.
+// Confirmation buffers for up to cap_f flagged sectors. Records: room for
+// about one per eighth of the sectors (more are counted and produced again,
+// with their exact count, when they are copied out). Returns the record room.
+template <class Rec>
+int reserve_confirm(carve_scan* sc, uint64_t cap_f, uint64_t* rec_room) {
+  CARVE_TRY(sc->n_match.reserve(cap_f * 4));
+  CARVE_TRY(sc->match_mask.reserve(cap_f * 8));
+  CARVE_TRY(sc->out_off.reserve((cap_f + 1) * 8));
+  CARVE_TRY(sc->cws.reserve(2 * cdiv(cap_f ? cap_f : 1, kItemsPerBlock) * sizeof(uint64_t)));
+  uint64_t rec_cap = sc->matches.bytes / sizeof(Rec);
+  if (rec_cap < cap_f / 8 + 4096) rec_cap = cap_f / 8 + 4096;
+  CARVE_TRY(sc->matches.reserve(rec_cap * sizeof(Rec)));
+  *rec_room = rec_cap;
+  return CARVE_OK;
+}
+
 template <class Src, class Rec>
 int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src) {
   hipStream_t s = sc->stream;
@@ -821,14 +868,8 @@ int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src)
   if (sc->n_tiles == 0) return CARVE_OK;
   const uint64_t cap_f = sc->n_tiles * kTileSectors;   // flagged sectors are at most this many
   const uint64_t* d_count = sc->count.as<uint64_t>();
-  CARVE_TRY(sc->n_match.reserve(cap_f * 4));
-  CARVE_TRY(sc->match_mask.reserve(cap_f * 8));
-  CARVE_TRY(sc->out_off.reserve((cap_f + 1) * 8));
-  // records: room for about one per eighth of the sectors (more are counted
-  // and produced again, with their exact count, when they are copied out)
-  uint64_t rec_cap = sc->matches.bytes / sizeof(Rec);
-  if (rec_cap < cap_f / 8 + 4096) rec_cap = cap_f / 8 + 4096;
-  CARVE_TRY(sc->matches.reserve(rec_cap * sizeof(Rec)));
+  uint64_t rec_cap = 0;
+  CARVE_TRY(reserve_confirm<Rec>(sc, cap_f, &rec_cap));
   sc->rec_cap = rec_cap;
   const ConfirmView cv = idx->cview();
   const uint32_t* img_of = sc->batch ? sc->img_of.as<uint32_t>() : nullptr;
@@ -894,7 +935,7 @@ int copy_ids(carve_scan* sc, uint64_t first, uint64_t n, uint64_t* out, uint64_t
 // ================================================================ C ABI
 extern "C" const char* carve_last_error(void) { return g_err.c_str(); }
 
-extern "C" __attribute__((visibility("hidden"))) int carve_fail_msg(int code, const char* msg) {
+CARVE_HIDDEN int carve_fail_msg(int code, const char* msg) {
   return fail(code, "%s", msg);
 }
 
@@ -1329,6 +1370,63 @@ extern "C" int batch_confirm_matches(const carve_index* idx, carve_batch* b, car
   if (cap && !out) return fail(CARVE_EINVAL, "batch_confirm_matches: null out with cap > 0");
   if (b->idx != idx) return fail(CARVE_EINVAL, "batch_confirm_matches: batch was made with another index");
   return confirm_all(idx, b, many_images(b), out, cap, n_out);
+}
+
+// ------------------------------------------------------------ server hooks
+CARVE_HIDDEN int carve_batch_reserve(const carve_index* idx, carve_batch** io, uint64_t n_sectors,
+                                     uint32_t n_images, void* stream) {
+  if (!idx || !io) return fail(CARVE_EINVAL, "carve_batch_reserve: null argument");
+  carve_batch* b = *io;
+  const bool created = !b;
+  if (created) {
+    b = new carve_batch();
+    b->batch = true;
+    (void)hipGetDevice(&b->device);
+    b->stream = (hipStream_t)stream;
+    b->idx = idx;
+  }
+  // every image may end in a partial tile
+  const uint64_t tiles = cdiv(n_sectors, kTileSectors) + n_images;
+  const uint64_t keep_tiles = b->n_tiles;
+  const uint32_t keep_images = b->n_images;
+  b->n_tiles = tiles;
+  b->n_images = n_images;
+  uint64_t room = 0;
+  const size_t desc_bytes = ((size_t)n_images + 1) * sizeof(ImageDesc);
+  int rc = reserve_scan(b);
+  if (rc == CARVE_OK) rc = reserve_confirm<carve_batch_match>(b, tiles * kTileSectors, &room);
+  if (rc == CARVE_OK) rc = b->d_desc.reserve(desc_bytes);
+  if (rc == CARVE_OK) rc = b->h_desc.reserve(desc_bytes);
+  b->n_tiles = keep_tiles;
+  b->n_images = keep_images;
+  if (rc != CARVE_OK) {
+    if (created) free_batch(b);
+    return rc;
+  }
+  *io = b;
+  return CARVE_OK;
+}
+
+CARVE_HIDDEN int carve_batch_stage_out(carve_batch* b, int with_matches, const carve_stage_out* st,
+                                       uint64_t* match_room) {
+  if (!b || !st || !match_room || !st->totals || !st->img_off || (st->ids_cap && !st->ids) ||
+      (st->match_cap && !st->matches))
+    return fail(CARVE_EINVAL, "carve_batch_stage_out: null argument");
+  if (with_matches && !b->confirm_enqueued)
+    return fail(CARVE_EINVAL, "carve_batch_stage_out: confirmation was not enqueued");
+  // an empty tile space writes no counts: stage zeros (the offsets are zero-filled)
+  const bool counted = b->n_tiles != 0;
+  if (!counted) k_fill_u64<<<1, 64, 0, b->stream>>>(b->count.as<uint64_t>(), 2, 0);
+  const uint64_t room = with_matches && counted ? b->rec_cap : 0;
+  *match_room = room;
+  const uint64_t most = st->ids_cap + 3 * st->match_cap + b->n_images + 1;
+  const uint64_t want = cdiv(most, 256);
+  k_stage_out<<<(unsigned)(want < 1024 ? (want ? want : 1) : 1024), 256, 0, b->stream>>>(
+      b->count.as<uint64_t>(), with_matches, b->n_images, b->img_off.as<uint64_t>(), b->ids.as<uint64_t>(),
+      b->matches.as<uint64_t>(), room, st->totals, st->img_off, st->ids, st->ids_cap, (uint64_t*)st->matches,
+      st->match_cap);
+  HIP_TRY(hipGetLastError());
+  return CARVE_OK;
 }
 
 extern "C" int autotune_scan(carve_index* idx, const void* sample_image, uint64_t n_bytes, void* stream,

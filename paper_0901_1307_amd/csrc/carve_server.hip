@@ -5,11 +5,18 @@
 // A lane is a HIP stream with its own batch object and completion event.
 // server_poll first retires lanes whose event has completed, then fills every
 // free lane with the queued jobs that fit the budget, oldest first, as one
-// batch. A retired batch's flagged ids and confirmed matches are copied in two
-// transfers into pinned host buffers that its jobs share (each job keeps its
-// slice) and that are recycled once every job of the batch is released.
+// batch. Behind a batch's scan the lane enqueues its confirmation and a
+// stage-out kernel that writes the batch's counts, flagged ids and confirmed
+// matches straight into pinned host buffers, so retiring a batch reads host
+// memory and waits on nothing: no lane's readback queues behind another lane's
+// scan. The buffers are shared by the batch's jobs (each keeps its slice) and
+// recycled once every job of the batch is released. Each lane's device
+// workspace is sized at creation for its share of the budget, so serving
+// allocates and frees nothing (both synchronize the whole device) unless a
+// batch outgrows it.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <chrono>
@@ -19,13 +26,17 @@
 #include <vector>
 
 #include "../../include/carve.h"
-
-// Records a message for carve_last_error() (defined with the other entry points).
-extern "C" __attribute__((visibility("hidden"))) int carve_fail_msg(int code, const char* msg);
+#include "carve_internal.h"
 
 namespace {
 
-// Pinned host array, grown on demand.
+uint64_t pow2_at_least(uint64_t n) {
+  uint64_t p = 1024;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Pinned host array, grown on demand to a power of two.
 template <class T>
 struct Pinned {
   T* p = nullptr;
@@ -35,7 +46,7 @@ struct Pinned {
     if (p) (void)hipHostFree(p);
     p = nullptr;
     cap = 0;
-    const size_t want = n < 1024 ? 1024 : n + n / 2;
+    const size_t want = pow2_at_least(n);
     if (hipHostMalloc((void**)&p, want * sizeof(T), hipHostMallocDefault) != hipSuccess) return false;
     cap = want;
     return true;
@@ -69,7 +80,14 @@ struct Lane {
   std::vector<uint64_t> jobs;
   uint64_t bytes = 0;
   bool busy = false;
+  Pinned<uint64_t> stage;         // [0] flagged, [1] matches, then n_images + 1 id offsets
+  std::shared_ptr<Results> res;   // ids and records of the batch in flight
+  uint64_t match_room = 0;        // records the device held for the stage-out
 };
+
+// Results room for a batch of `sectors` sectors: one flagged sector in eight
+// (more take the synchronous path at retirement).
+uint64_t results_room(uint64_t sectors) { return sectors / 8 + 4096; }
 
 double seconds_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -92,17 +110,30 @@ struct carve_server {
   std::vector<uint64_t> counts;
   std::vector<std::unique_ptr<Results>> spare;   // recycled result buffers
 
-  std::shared_ptr<Results> new_results() {
+  // Recycled buffers with room for `n` ids and records: the smallest spare
+  // that fits, else the largest spare grown (or a new one).
+  std::shared_ptr<Results> new_results(uint64_t n, int* rc) {
+    size_t pick = spare.size();
+    for (size_t i = 0; i < spare.size(); ++i) {
+      const Results& r = *spare[i];
+      if (r.ids.cap >= n && r.matches.cap >= n && (pick == spare.size() || r.ids.cap < spare[pick]->ids.cap)) pick = i;
+    }
+    if (pick == spare.size())
+      for (size_t i = 0; i < spare.size(); ++i)
+        if (pick == spare.size() || spare[i]->ids.cap > spare[pick]->ids.cap) pick = i;
     Results* r;
-    if (!spare.empty()) {
-      r = spare.back().release();
-      spare.pop_back();
+    if (pick < spare.size()) {
+      r = spare[pick].release();
+      spare.erase(spare.begin() + (ptrdiff_t)pick);
     } else {
       r = new Results();
     }
+    if (!r->ids.reserve(n) || !r->matches.reserve(n))
+      *rc = carve_fail_msg(CARVE_ENOMEM, "server: pinned allocation failed");
     return std::shared_ptr<Results>(r, [this](Results* x) { spare.emplace_back(x); });
   }
   ~carve_server() {
+    for (Lane& ln : lanes) ln.res.reset();
     jobs.clear();   // returns every Results to `spare`
     for (auto& r : spare) {
       r->ids.release();
@@ -114,42 +145,37 @@ struct carve_server {
 namespace {
 
 // Retire a lane whose batch has completed: per-job results, budget back.
+// The stage-out has already put everything in host memory unless a result
+// outgrew its room; only then are ids or records fetched synchronously.
 int retire(carve_server* s, Lane& ln) {
   const auto t0 = std::chrono::steady_clock::now();
   const uint32_t n = (uint32_t)ln.jobs.size();
   int rc = CARVE_OK;
-  std::shared_ptr<Results> res = s->new_results();
-  s->counts.assign(n, 0);
-  if (n) rc = batch_flag_counts(ln.batch, s->counts.data(), n);
-  uint64_t total = 0;
-  for (uint64_t c : s->counts) total += c;
-  uint64_t got = 0;
-  if (rc == CARVE_OK && total) {
+  std::shared_ptr<Results> res = std::move(ln.res);
+  const uint64_t* st = ln.stage.p;
+  const uint64_t total = st[0];
+  const uint64_t* off = st + 2;
+  uint64_t nm = s->p.confirm ? st[1] : 0;
+  if (total > res->ids.cap) {
+    uint64_t got = 0;
     if (!res->ids.reserve(total)) rc = carve_fail_msg(CARVE_ENOMEM, "server: pinned allocation failed");
-    else rc = batch_flagged_sectors(ln.batch, CARVE_ALL_IMAGES, res->ids.p, total, &got);
+    else rc = batch_flagged_sectors(ln.batch, CARVE_ALL_IMAGES, res->ids.p, res->ids.cap, &got);
   }
-  uint64_t nm = 0;
-  if (rc == CARVE_OK && s->p.confirm && total) {
-    // about one match per flagged sector: room for that avoids a second pass
-    if (!res->matches.reserve(total + total / 8 + 64)) rc = carve_fail_msg(CARVE_ENOMEM, "server: pinned allocation failed");
-    if (rc == CARVE_OK) rc = batch_confirm_matches(s->idx, ln.batch, res->matches.p, res->matches.cap, &nm);
-    if (rc == CARVE_ETRUNC) {
-      if (!res->matches.reserve(nm)) rc = carve_fail_msg(CARVE_ENOMEM, "server: pinned allocation failed");
-      else rc = batch_confirm_matches(s->idx, ln.batch, res->matches.p, res->matches.cap, &nm);
-    }
+  const uint64_t staged = ln.match_room < res->matches.cap ? ln.match_room : res->matches.cap;
+  if (rc == CARVE_OK && nm > staged) {
+    if (!res->matches.reserve(nm)) rc = carve_fail_msg(CARVE_ENOMEM, "server: pinned allocation failed");
+    else rc = batch_confirm_matches(s->idx, ln.batch, res->matches.p, res->matches.cap, &nm);
   }
-  // slices: the ids of image i follow those of images 0..i-1; matches are
-  // ordered by image
-  uint64_t at = 0, m = 0;
+  // slices: the ids of image i are [off[i], off[i+1]); matches are ordered by image
+  uint64_t m = 0;
   for (uint32_t i = 0; i < n; ++i) {
     Job& j = s->jobs[ln.jobs[i]];
     j.state = 3;
     j.status = rc;
     if (rc == CARVE_OK) {
       j.res = res;
-      j.flag_at = at;
-      j.n_flags = s->counts[i];
-      at += s->counts[i];
+      j.flag_at = off[i];
+      j.n_flags = off[i + 1] - off[i];
       j.match_at = m;
       while (m < nm && res->matches.p[m].image == i) ++m;
       j.n_matches = m - j.match_at;
@@ -185,12 +211,19 @@ int launch(carve_server* s, Lane& ln) {
   }
   if (ln.jobs.empty()) return CARVE_OK;
   int rc = scan_batch(s->idx, s->descs.data(), (uint32_t)s->descs.size(), ln.stream, &ln.batch);
-  // confirmation queued right behind the scan: at retirement only copies remain,
-  // and no lane's readback waits for kernels queued behind another lane's scan
   if (rc == CARVE_OK && s->p.confirm) rc = batch_confirm_enqueue(s->idx, ln.batch);
+  if (rc == CARVE_OK) ln.res = s->new_results(results_room(ln.bytes / 512), &rc);
+  if (rc == CARVE_OK && !ln.stage.reserve(ln.jobs.size() + 3))
+    rc = carve_fail_msg(CARVE_ENOMEM, "server: pinned allocation failed");
+  if (rc == CARVE_OK) {
+    const carve_stage_out st{ln.stage.p, ln.stage.p + 2, ln.res->ids.p, ln.res->ids.cap, ln.res->matches.p,
+                             ln.res->matches.cap};
+    rc = carve_batch_stage_out(ln.batch, s->p.confirm ? 1 : 0, &st, &ln.match_room);
+  }
   if (rc == CARVE_OK && hipEventRecord(ln.done, ln.stream) != hipSuccess)
     rc = carve_fail_msg(CARVE_EDEVICE, "server: event record failed");
   if (rc != CARVE_OK) {   // the jobs fail with the batch's error
+    ln.res.reset();
     for (uint64_t id : ln.jobs) {
       Job& j = s->jobs[id];
       j.state = 3;
@@ -220,10 +253,13 @@ extern "C" int server_create(const carve_index* idx, const carve_server_params* 
   if (!p.max_jobs_per_batch) p.max_jobs_per_batch = 4096;
   if (!p.budget_bytes) p.budget_bytes = 32ull << 30;
   if (p.n_streams > 64) return carve_fail_msg(CARVE_EINVAL, "server_create: at most 64 streams");
+  if (p.max_jobs_per_batch > 65536) return carve_fail_msg(CARVE_EINVAL, "server_create: at most 65536 jobs per batch");
   carve_server* s = new carve_server();
   s->idx = idx;
   s->p = p;
   s->lanes.resize(p.n_streams);
+  // each lane sized for its share of the budget (a larger single job grows it)
+  const uint64_t share_sectors = p.budget_bytes / p.n_streams / 512;
   for (Lane& ln : s->lanes) {
     // default-priority streams only
     if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -231,25 +267,66 @@ extern "C" int server_create(const carve_index* idx, const carve_server_params* 
       server_free(s);
       return carve_fail_msg(CARVE_EDEVICE, "server_create: stream or event creation failed");
     }
+    int rc = carve_batch_reserve(idx, &ln.batch, share_sectors, p.max_jobs_per_batch, ln.stream);
+    if (rc == CARVE_OK && !ln.stage.reserve((uint64_t)p.max_jobs_per_batch + 3))
+      rc = carve_fail_msg(CARVE_ENOMEM, "server_create: pinned allocation failed");
+    if (rc == CARVE_OK) ln.res = s->new_results(results_room(share_sectors), &rc);
+    if (rc != CARVE_OK) {
+      server_free(s);
+      return rc;
+    }
   }
+  for (Lane& ln : s->lanes) ln.res.reset();   // warm buffers wait in the spare pool
   *out = s;
   return CARVE_OK;
 }
 
-extern "C" int server_submit(carve_server* s, const carve_image_desc* job, uint64_t* job_id) {
-  if (!s || !job || !job_id) return carve_fail_msg(CARVE_EINVAL, "server_submit: null argument");
-  if (job->tau0 > 7 || (job->tau_mode != CARVE_TAU_PER_CLUSTER && job->tau_mode != CARVE_TAU_ANY))
-    return carve_fail_msg(CARVE_EINVAL, "server_submit: bad tau0 or tau_mode");
-  if ((job->n_bytes >= 512 && !job->image) || (uintptr_t)job->image % 16)
-    return carve_fail_msg(CARVE_EINVAL, "server_submit: null or misaligned image");
-  const uint64_t bytes = job->n_bytes - job->n_bytes % 512;
-  if (bytes > s->p.budget_bytes) return carve_fail_msg(CARVE_EUNSUPPORTED, "server_submit: job exceeds the budget");
+namespace {
+// Checks one job descriptor; `which` >= 0 names it in the message.
+int check_job(const carve_server* s, const carve_image_desc* job, long which) {
+  char msg[128];
+  const char* why = nullptr;
+  int code = CARVE_EINVAL;
+  if (job->tau0 > 7 || (job->tau_mode != CARVE_TAU_PER_CLUSTER && job->tau_mode != CARVE_TAU_ANY)) {
+    why = "bad tau0 or tau_mode";
+  } else if ((job->n_bytes >= 512 && !job->image) || (uintptr_t)job->image % 16) {
+    why = "null or misaligned image";
+  } else if (job->n_bytes - job->n_bytes % 512 > s->p.budget_bytes) {
+    why = "job exceeds the budget";
+    code = CARVE_EUNSUPPORTED;
+  }
+  if (!why) return CARVE_OK;
+  if (which >= 0) snprintf(msg, sizeof msg, "server_submit: %s (job %ld)", why, which);
+  else snprintf(msg, sizeof msg, "server_submit: %s", why);
+  return carve_fail_msg(code, msg);
+}
+
+uint64_t enqueue_job(carve_server* s, const carve_image_desc* job) {
   const uint64_t id = s->next_id++;
   Job& j = s->jobs[id];
   j.desc = *job;
-  j.bytes = bytes;
+  j.bytes = job->n_bytes - job->n_bytes % 512;
   s->queue.push_back(id);
-  *job_id = id;
+  return id;
+}
+}  // namespace
+
+extern "C" int server_submit(carve_server* s, const carve_image_desc* job, uint64_t* job_id) {
+  if (!s || !job || !job_id) return carve_fail_msg(CARVE_EINVAL, "server_submit: null argument");
+  const int rc = check_job(s, job, -1);
+  if (rc != CARVE_OK) return rc;
+  *job_id = enqueue_job(s, job);
+  return CARVE_OK;
+}
+
+extern "C" int server_submit_many(carve_server* s, const carve_image_desc* jobs, uint32_t n, uint64_t* job_ids) {
+  if (!s || (n && (!jobs || !job_ids))) return carve_fail_msg(CARVE_EINVAL, "server_submit_many: null argument");
+  for (uint32_t i = 0; i < n; ++i) {
+    const int rc = check_job(s, &jobs[i], (long)i);
+    if (rc != CARVE_OK) return rc;
+  }
+  s->jobs.reserve(s->jobs.size() + n);
+  for (uint32_t i = 0; i < n; ++i) job_ids[i] = enqueue_job(s, &jobs[i]);
   return CARVE_OK;
 }
 
@@ -320,6 +397,15 @@ extern "C" int server_release(carve_server* s, uint64_t job_id) {
   return CARVE_OK;
 }
 
+extern "C" int server_release_many(carve_server* s, const uint64_t* job_ids, uint32_t n) {
+  if (!s || (n && !job_ids)) return carve_fail_msg(CARVE_EINVAL, "server_release_many: null argument");
+  for (uint32_t i = 0; i < n; ++i) {
+    const int rc = server_release(s, job_ids[i]);
+    if (rc != CARVE_OK) return rc;
+  }
+  return CARVE_OK;
+}
+
 extern "C" int server_stats(const carve_server* s, carve_server_stats* out) {
   if (!s || !out) return carve_fail_msg(CARVE_EINVAL, "server_stats: null argument");
   carve_server_stats st{};
@@ -340,6 +426,7 @@ extern "C" void server_free(carve_server* s) {
   for (Lane& ln : s->lanes) {
     if (ln.stream) (void)hipStreamSynchronize(ln.stream);
     free_batch(ln.batch);
+    ln.stage.release();
     if (ln.done) (void)hipEventDestroy(ln.done);
     if (ln.stream) (void)hipStreamDestroy(ln.stream);
   }

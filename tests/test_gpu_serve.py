@@ -109,3 +109,63 @@ def test_budget_and_errors(pool):
         polls += 1
     assert srv.stats()["batches_launched"] >= 3
     srv.close()
+
+
+def test_results_beyond_staged_room():
+    """Every sector flagged, many matches each: more than the room staged at
+    launch, so retirement fetches the rest; results still equal the jobs alone."""
+    rng = random.Random(5)
+    masters, offsets = [], [0]
+    for f in range(40):
+        sec = [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(10)]
+        sec[3] = bytes(SECTOR)
+        masters += sec
+        offsets.append(len(masters))
+    ms = torch.tensor(list(b"".join(masters)), dtype=torch.uint8, device="cuda")
+    idx = carve.build_master_index(ms, offsets)
+    zeros = torch.zeros(4 << 20, dtype=torch.uint8, device="cuda")
+    jobs = [(zeros[: n * SECTOR], n % 8, carve.CARVE_TAU_ANY if n % 2 else carve.CARVE_TAU_PER_CLUSTER)
+            for n in (1, 7, 64, 999, 4096, 8191)]
+    srv = carve.Server(idx, n_streams=2, budget_bytes=64 << 20)
+    ids = [srv.submit(t, tau0, mode) for t, tau0, mode in jobs]
+    done = _drain(srv, ids)
+    for jid, (t, tau0, mode) in zip(ids, jobs):
+        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
+        if mode == carve.CARVE_TAU_ANY:
+            assert len(f) == t.numel() // SECTOR
+        assert done[jid] == (len(f), len(m))
+        assert np.array_equal(srv.flags(jid), f)
+        assert_same_matches(srv.matches(jid), m)
+    srv.close()
+
+
+def test_bulk_submit_poll_release(pool):
+    ms, idx, img = pool
+    jobs = _jobs(img, 50, seed=21)
+    srv = carve.Server(idx, n_streams=3)
+    bad = carve.image_descs(jobs[:5])
+    bad[3]["tau0"] = 9
+    with pytest.raises(carve.CarveError) as e:
+        srv.submit_many(bad)                                     # all or nothing
+    assert e.value.code == carve.CARVE_EINVAL and "job 3" in str(e.value)
+    assert srv.stats()["queued_jobs"] == 0
+    ids = srv.submit_many(carve.image_descs(jobs))
+    assert len(ids) == len(jobs) and (np.diff(ids.astype(np.int64)) == 1).all()
+    done = {}
+    while len(done) < len(jobs):
+        d = srv.poll_array()
+        for r in d:
+            assert r["status"] == carve.CARVE_OK
+            done[int(r["job_id"])] = (int(r["n_flagged"]), int(r["n_confirmed"]))
+    for jid, (t, tau0, mode) in zip(ids.tolist(), jobs):
+        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
+        assert done[jid] == (len(f), len(m))
+        assert np.array_equal(srv.flags(jid), f)
+        assert_same_matches(srv.matches(jid), m)
+    with pytest.raises(carve.CarveError):
+        srv.release_many(np.array([ids[0], 987654321], dtype=np.uint64))   # stops at the unknown id
+    srv.release_many(ids[1:])
+    with pytest.raises(carve.CarveError):
+        srv.flags(int(ids[0]))                                   # released by the first call
+    assert srv.stats()["done_jobs"] == 0
+    srv.close()
