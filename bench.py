@@ -27,7 +27,9 @@ sys.path.insert(0, ROOT)
 METRIC = "disk GB/s scanned (bit-exact flags) and % HBM roofline; p99 latency served"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SECTOR_ALG = 512 + 1.0 / 8.0   # read the sector once, write one flag bit
-KERNEL_SOURCES = ("paper_0901_1307_amd/csrc/carve.hip", "paper_0901_1307_amd/csrc/carve_device.h")
+# the scan kernel's code and its compiler flags: the traffic counters stay valid while these are unchanged
+KERNEL_SOURCES = ("paper_0901_1307_amd/csrc/carve_scan_kernel.h", "paper_0901_1307_amd/csrc/carve_device.h",
+                  "paper_0901_1307_amd/build.py")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_scan_mid.json")
 
 

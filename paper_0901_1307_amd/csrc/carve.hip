@@ -31,125 +31,17 @@
 #include "../../include/carve.h"
 #include "carve_device.h"
 #include "carve_internal.h"
+#include "carve_scan_kernel.h"
 
 using namespace carve;
 
 namespace {
 
-constexpr int kScanThreads = 256;
-constexpr int kScanWaves = kScanThreads / (int)kWave;
 constexpr int kBlockThreads = 256;
 constexpr int kItemsPerThread = 8;
 constexpr int kItemsPerBlock = kBlockThreads * kItemsPerThread;   // 2048
 
-enum { kFlags = 0, kSigs = 1 };
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be placed
-
-// ------------------------------------------------------------ images
-// One image of a scan. tile_begin: its first tile in the scan's tile space.
-struct ImageDesc {
-  const uint8_t* base;
-  uint64_t n_sectors;
-  uint64_t tile_begin;
-  uint32_t tau0;      // cluster position of the image's first sector
-  uint32_t any_tau;   // 1: match at any cluster position
-};
-
-// Where a tile's sectors are.
-struct TileRef {
-  const uint8_t* base;   // its first sector
-  uint32_t n_valid;      // 1..64 sectors
-  uint32_t tau_first;    // cluster position of its first sector
-  uint32_t any_tau;
-  uint32_t image;
-};
-
-__device__ __forceinline__ TileRef tile_of(const ImageDesc& d, uint64_t g, uint32_t image) {
-  const uint64_t first = (g - d.tile_begin) * kTileSectors;
-  const uint64_t rem = d.n_sectors - first;
-  return TileRef{d.base + first * kSectorBytes, rem >= kTileSectors ? kTileSectors : (uint32_t)rem,
-                 (uint32_t)((first + d.tau0) & (kClusterSectors - 1)), d.any_tau, image};
-}
-
-// A scan of one image: the descriptor travels by value.
-struct OneImage {
-  ImageDesc d;
-  __device__ __forceinline__ uint64_t n_tiles() const { return (d.n_sectors + kTileSectors - 1) / kTileSectors; }
-  // `cursor` is the image of the previous lookup (tiles are visited in increasing order)
-  __device__ __forceinline__ TileRef tile(uint64_t g, uint32_t&) const { return tile_of(d, g, 0); }
-  __device__ __forceinline__ const ImageDesc& image(uint32_t) const { return d; }
-  __device__ __forceinline__ uint32_t image_of_tile(uint64_t) const { return 0; }
-};
-
-// A batch: descriptors in device memory, n + 1 of them (the last one only
-// carries the total tile count in tile_begin).
-struct ManyImages {
-  const ImageDesc* __restrict__ d;
-  uint32_t n;
-  __device__ __forceinline__ uint64_t n_tiles() const { return d[n].tile_begin; }
-  __device__ __forceinline__ TileRef tile(uint64_t g, uint32_t& cursor) const {
-    while (g >= d[cursor + 1].tile_begin) ++cursor;   // skips empty images too
-    return tile_of(d[cursor], g, cursor);
-  }
-  __device__ __forceinline__ const ImageDesc& image(uint32_t i) const { return d[i]; }
-  __device__ __forceinline__ uint32_t image_of_tile(uint64_t g) const {   // last i with d[i].tile_begin <= g
-    uint32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (d[mid].tile_begin <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-  }
-};
-
-// ------------------------------------------------------------------ scan
-// Persistent grid over the tile space: wave q takes chunks q, q + W, ... of
-// `chunk` consecutive tiles (W = waves in the grid). 4 waves per SIMD (at
-// most 128 VGPRs): the more waves, the more sector loads in flight per CU.
-template <int kMode, class Src>
-__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(
-    Src src, uint32_t chunk, IndexView ix, uint64_t wt, uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
-  const uint32_t w = threadIdx.x / kWave;
-  const uint32_t l = lane_id();
-  uint8_t* my = lds + w * kTileLds;
-  const uint64_t n_tiles = src.n_tiles();
-  const uint64_t n_waves = (uint64_t)gridDim.x * kScanWaves;
-  uint64_t g = ((uint64_t)blockIdx.x * kScanWaves + w) * chunk;
-  if (g >= n_tiles) return;
-  auto next_of = [&](uint64_t t) {
-    return ((t + 1) % chunk != 0) ? t + 1 : t + 1 + (n_waves - 1) * chunk;
-  };
-  uint32_t cur = 0;
-  TileRef tr = src.tile(g, cur);
-  PhaseRegs A, B;
-  load_phase<true>(ContiguousRows{tr.base, tr.n_valid}, 0, A);
-  while (true) {
-    const uint64_t gn = next_of(g);
-    const bool more = gn < n_tiles;
-    uint32_t cur_n = cur;
-    const TileRef tn = more ? src.tile(gn, cur_n) : tr;
-    // The next tile's first phase is loaded while this tile's last one is
-    // hashed. Unconditionally (the last tile reloads itself): a load under a
-    // branch would make the compiler wait for every load at the join.
-    const uint64_t h = tile_signature_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, wt, A, B,
-                                                      [&](PhaseRegs& R) {
-                                                        load_phase<true>(ContiguousRows{tn.base, tn.n_valid}, 0, R);
-                                                      });
-    if constexpr (kMode == kFlags) {
-      const uint32_t tau = (tr.tau_first + l) & (kClusterSectors - 1);
-      uint64_t hits = tile_probe(ix, h, tau, tr.any_tau != 0, hit_slot + g * kTileSectors);
-      if (tr.n_valid < kTileSectors) hits &= (1ull << tr.n_valid) - 1ull;
-      if (l == 0) out[g] = hits;
-    } else {
-      if (l < tr.n_valid) out[g * kTileSectors + l] = h;   // one image: tile g holds sectors 64g..
-    }
-    if (!more) break;
-    g = gn;
-    cur = cur_n;
-    tr = tn;
-  }
-}
 
 // -------------------------------------------------------- prefix sums
 // An item count known on the host (dev == null) or read on the device, so work
@@ -173,6 +65,7 @@ template <class Items>
 __global__ __launch_bounds__(kBlockThreads) void k_reduce(Items items, Count count, uint64_t* __restrict__ blk_sums) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
   const uint64_t n = count.get();
+  if ((uint64_t)blockIdx.x * kItemsPerBlock >= n) return;   // the whole block: no items (sum not scanned)
   const uint64_t base = (uint64_t)blockIdx.x * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
   uint64_t s = 0;
 #pragma unroll
@@ -183,11 +76,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce(Items items, Count cou
   if (threadIdx.x == 0) blk_sums[blockIdx.x] = total;
 }
 
-// One block: exclusive offsets of the block sums; total into *total.
-__global__ __launch_bounds__(kBlockThreads) void k_scan_blocks(const uint64_t* __restrict__ blk_sums, uint64_t n_blk,
+// One block: exclusive offsets of the block sums; total into *total. Only
+// the blocks that hold items are scanned (a count read on the device can be
+// far below the capacity the launches were sized for).
+__global__ __launch_bounds__(kBlockThreads) void k_scan_blocks(const uint64_t* __restrict__ blk_sums, Count items,
                                                               uint64_t* __restrict__ blk_off,
                                                               uint64_t* __restrict__ total) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
+  const uint64_t n_blk = (items.get() + kItemsPerBlock - 1) / kItemsPerBlock;
   uint64_t carry = 0;
   for (uint64_t b0 = 0; b0 < n_blk; b0 += kBlockThreads) {
     const uint64_t b = b0 + threadIdx.x;
@@ -236,6 +132,7 @@ template <class Emit>
 __global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, Count count, const uint64_t* __restrict__ blk_off) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
   const uint64_t n = count.get();
+  if ((uint64_t)blockIdx.x * kItemsPerBlock >= n) return;   // the whole block: no items (offset not scanned)
   const uint64_t base = (uint64_t)blockIdx.x * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
   uint64_t c[kItemsPerThread];
   uint64_t s = 0;
@@ -669,7 +566,7 @@ int scan_counts(const uint32_t* in, T* out, uint64_t n, uint64_t* d_total, DevBu
   uint64_t* sums = ws.as<uint64_t>();
   uint64_t* offs = sums + nb;
   k_reduce<<<nb, kBlockThreads, 0, s>>>(U32Items{in}, Count{n, n_dev}, sums);
-  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, nb, offs, d_total);
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n, n_dev}, offs, d_total);
   k_apply<<<nb, kBlockThreads, 0, s>>>(EmitOffsets<T>{in, out}, Count{n, n_dev}, offs);
   k_write_total<T><<<1, 1, 0, s>>>(out, Count{n, n_dev}, d_total);
   HIP_TRY(hipGetLastError());
@@ -808,7 +705,7 @@ int launch_scan(carve_scan* sc, const Src& src) {
   uint64_t* sums = sc->ws.as<uint64_t>();
   uint64_t* offs = sums + nb;
   k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{sc->bitmap.as<uint64_t>()}, Count{n_words, nullptr}, sums);
-  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, nb, offs, d_count);
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n_words, nullptr}, offs, d_count);
   k_apply<<<nb, kBlockThreads, 0, s>>>(
       EmitIds<Src>{src, sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr},
       Count{n_words, nullptr}, offs);
@@ -860,8 +757,12 @@ int reserve_confirm(carve_scan* sc, uint64_t cap_f, uint64_t* rec_room) {
   return CARVE_OK;
 }
 
+// Records go to the scan's own buffer, or (dest != null: device memory of the
+// caller, dest_cap records) straight to their destination; then the scan's
+// buffer holds none and a later copy-out produces them again.
 template <class Src, class Rec>
-int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src) {
+int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src, Rec* dest = nullptr,
+                         uint64_t dest_cap = 0) {
   hipStream_t s = sc->stream;
   sc->confirm_enqueued = true;
   sc->rec_cap = 0;
@@ -870,7 +771,7 @@ int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src)
   const uint64_t* d_count = sc->count.as<uint64_t>();
   uint64_t rec_cap = 0;
   CARVE_TRY(reserve_confirm<Rec>(sc, cap_f, &rec_cap));
-  sc->rec_cap = rec_cap;
+  sc->rec_cap = dest ? 0 : rec_cap;
   const ConfirmView cv = idx->cview();
   const uint32_t* img_of = sc->batch ? sc->img_of.as<uint32_t>() : nullptr;
   const uint64_t per_block = kBlockThreads / kConfirmLanes;
@@ -883,7 +784,7 @@ int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src)
                                   d_count));
   k_confirm_emit<Src, Rec><<<resident_grid(k_confirm_emit<Src, Rec>, 256, cdiv(cap_f, 256)), 256, 0, s>>>(
       src, sc->ids.as<uint64_t>(), img_of, nf, sc->hit_slot.as<uint32_t>(), cv, sc->match_mask.as<uint64_t>(),
-      sc->out_off.as<uint64_t>(), sc->matches.as<Rec>(), rec_cap);
+      sc->out_off.as<uint64_t>(), dest ? dest : sc->matches.as<Rec>(), dest ? dest_cap : rec_cap);
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
@@ -895,13 +796,15 @@ template <class Src, class Rec>
 int confirm_all(const carve_index* idx, carve_scan* sc, const Src& src, Rec* out, uint64_t cap, uint64_t* n_out) {
   hipStream_t s = sc->stream;
   *n_out = 0;
-  if (!sc->confirm_enqueued) CARVE_TRY((confirm_enqueue_impl<Src, Rec>(idx, sc, src)));
+  // not yet enqueued, device destination: records are written there directly
+  const bool direct = !sc->confirm_enqueued && cap && is_device_memory(out);
+  if (!sc->confirm_enqueued) CARVE_TRY((confirm_enqueue_impl<Src, Rec>(idx, sc, src, direct ? out : nullptr, cap)));
   if (sc->n_tiles == 0) return CARVE_OK;
   uint64_t nm = 0;
   CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>() + 1, &nm));
   *n_out = nm;
   const uint64_t k = nm < cap ? nm : cap;
-  if (k) {
+  if (k && !direct) {
     if (k > sc->rec_cap) {   // more records than the room enqueued: produce them again, all of them
       uint64_t nf = 0;
       CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>(), &nf));
@@ -1085,7 +988,8 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
     if ((rc = ws.reserve(2 * nb * 8))) return bail2(rc);
     k_reduce<<<nb, kBlockThreads, 0, s>>>(NonEmptyLists{ix->cand_off.as<uint32_t>()}, Count{n_lists, nullptr},
                                           ws.as<uint64_t>());
-    k_scan_blocks<<<1, kBlockThreads, 0, s>>>(ws.as<uint64_t>(), nb, ws.as<uint64_t>() + nb, d_total + 1);
+    k_scan_blocks<<<1, kBlockThreads, 0, s>>>(ws.as<uint64_t>(), Count{n_lists, nullptr}, ws.as<uint64_t>() + nb,
+                                              d_total + 1);
     BUILD_TRY(hipGetLastError());
   }
   uint32_t h_misc[2] = {0, 0};

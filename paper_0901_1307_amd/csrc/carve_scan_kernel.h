@@ -1,0 +1,123 @@
+// The signature/probe scan kernel and the tile spaces it walks (one image, or
+// a batch of images), Section 3.1: the djb2 signature of each 512-byte sector
+// (Eq. (1), 64-bit) and its lookup among the master signatures of the
+// sector's cluster position. Device code only; included by carve.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "carve_device.h"
+
+namespace carve {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanWaves = kScanThreads / (int)kWave;
+enum { kFlags = 0, kSigs = 1 };
+
+// ------------------------------------------------------------ images
+// One image of a scan. tile_begin: its first tile in the scan's tile space.
+struct ImageDesc {
+  const uint8_t* base;
+  uint64_t n_sectors;
+  uint64_t tile_begin;
+  uint32_t tau0;      // cluster position of the image's first sector
+  uint32_t any_tau;   // 1: match at any cluster position
+};
+
+// Where a tile's sectors are.
+struct TileRef {
+  const uint8_t* base;   // its first sector
+  uint32_t n_valid;      // 1..64 sectors
+  uint32_t tau_first;    // cluster position of its first sector
+  uint32_t any_tau;
+  uint32_t image;
+};
+
+__device__ __forceinline__ TileRef tile_of(const ImageDesc& d, uint64_t g, uint32_t image) {
+  const uint64_t first = (g - d.tile_begin) * kTileSectors;
+  const uint64_t rem = d.n_sectors - first;
+  return TileRef{d.base + first * kSectorBytes, rem >= kTileSectors ? kTileSectors : (uint32_t)rem,
+                 (uint32_t)((first + d.tau0) & (kClusterSectors - 1)), d.any_tau, image};
+}
+
+// A scan of one image: the descriptor travels by value.
+struct OneImage {
+  ImageDesc d;
+  __device__ __forceinline__ uint64_t n_tiles() const { return (d.n_sectors + kTileSectors - 1) / kTileSectors; }
+  // `cursor` is the image of the previous lookup (tiles are visited in increasing order)
+  __device__ __forceinline__ TileRef tile(uint64_t g, uint32_t&) const { return tile_of(d, g, 0); }
+  __device__ __forceinline__ const ImageDesc& image(uint32_t) const { return d; }
+  __device__ __forceinline__ uint32_t image_of_tile(uint64_t) const { return 0; }
+};
+
+// A batch: descriptors in device memory, n + 1 of them (the last one only
+// carries the total tile count in tile_begin).
+struct ManyImages {
+  const ImageDesc* __restrict__ d;
+  uint32_t n;
+  __device__ __forceinline__ uint64_t n_tiles() const { return d[n].tile_begin; }
+  __device__ __forceinline__ TileRef tile(uint64_t g, uint32_t& cursor) const {
+    while (g >= d[cursor + 1].tile_begin) ++cursor;   // skips empty images too
+    return tile_of(d[cursor], g, cursor);
+  }
+  __device__ __forceinline__ const ImageDesc& image(uint32_t i) const { return d[i]; }
+  __device__ __forceinline__ uint32_t image_of_tile(uint64_t g) const {   // last i with d[i].tile_begin <= g
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (d[mid].tile_begin <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  }
+};
+
+// ------------------------------------------------------------------ scan
+// Persistent grid over the tile space: wave q takes chunks q, q + W, ... of
+// `chunk` consecutive tiles (W = waves in the grid). 4 waves per SIMD (at
+// most 128 VGPRs): the more waves, the more sector loads in flight per CU.
+template <int kMode, class Src>
+__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(
+    Src src, uint32_t chunk, IndexView ix, uint64_t wt, uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
+  const uint32_t w = threadIdx.x / kWave;
+  const uint32_t l = lane_id();
+  uint8_t* my = lds + w * kTileLds;
+  const uint64_t n_tiles = src.n_tiles();
+  const uint64_t n_waves = (uint64_t)gridDim.x * kScanWaves;
+  uint64_t g = ((uint64_t)blockIdx.x * kScanWaves + w) * chunk;
+  if (g >= n_tiles) return;
+  auto next_of = [&](uint64_t t) {
+    return ((t + 1) % chunk != 0) ? t + 1 : t + 1 + (n_waves - 1) * chunk;
+  };
+  uint32_t cur = 0;
+  TileRef tr = src.tile(g, cur);
+  PhaseRegs A, B;
+  load_phase<true>(ContiguousRows{tr.base, tr.n_valid}, 0, A);
+  while (true) {
+    const uint64_t gn = next_of(g);
+    const bool more = gn < n_tiles;
+    uint32_t cur_n = cur;
+    const TileRef tn = more ? src.tile(gn, cur_n) : tr;
+    // The next tile's first phase is loaded while this tile's last one is
+    // hashed. Unconditionally (the last tile reloads itself): a load under a
+    // branch would make the compiler wait for every load at the join.
+    const uint64_t h = tile_signature_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, wt, A, B,
+                                                      [&](PhaseRegs& R) {
+                                                        load_phase<true>(ContiguousRows{tn.base, tn.n_valid}, 0, R);
+                                                      });
+    if constexpr (kMode == kFlags) {
+      const uint32_t tau = (tr.tau_first + l) & (kClusterSectors - 1);
+      uint64_t hits = tile_probe(ix, h, tau, tr.any_tau != 0, hit_slot + g * kTileSectors);
+      if (tr.n_valid < kTileSectors) hits &= (1ull << tr.n_valid) - 1ull;
+      if (l == 0) out[g] = hits;
+    } else {
+      if (l < tr.n_valid) out[g * kTileSectors + l] = h;   // one image: tile g holds sectors 64g..
+    }
+    if (!more) break;
+    g = gn;
+    cur = cur_n;
+    tr = tn;
+  }
+}
+
+}  // namespace carve

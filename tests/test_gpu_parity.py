@@ -346,3 +346,25 @@ def test_more_matches_than_enqueued_room(any_tau):
                                       np.zeros(1000 * SECTOR, np.uint8), any_tau=any_tau)
     assert len(wm) == (100_000 if any_tau else 12_500)
     assert_same_matches(got, wm)
+
+
+def test_confirm_into_device_memory(tiny_gpu):
+    """Records emitted straight into a device buffer equal the host copy-out;
+    a later host copy of the same scan produces them again; a short device
+    buffer gets the first records and ETRUNC with the full count."""
+    cfg, ms, img, idx = tiny_gpu
+    f, m, _ = gpu_flags_and_matches(idx, img.data)
+    assert len(m) > 10
+    sc = carve.scan_image(idx, img.data)
+    out = torch.zeros(16 * (len(m) + 5), dtype=torch.uint8, device="cuda")
+    assert carve.confirm_matches(idx, sc, out) == len(m)
+    got = np.frombuffer(out.cpu().numpy().tobytes(), dtype=carve.MATCH_DTYPE)[: len(m)]
+    assert_same_matches(got, m)
+    assert_same_matches(carve.confirm_matches(idx, sc), m)       # host copy after a direct emit
+    carve.scan_image(idx, img.data, scan=sc)
+    short = torch.zeros(16 * 7, dtype=torch.uint8, device="cuda")
+    with pytest.raises(carve.CarveError) as e:
+        carve.confirm_matches(idx, sc, short)
+    assert e.value.code == carve.CARVE_ETRUNC and str(len(m)) in str(e.value)
+    first = np.frombuffer(short.cpu().numpy().tobytes(), dtype=carve.MATCH_DTYPE)
+    assert_same_matches(first, m[:7])
