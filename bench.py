@@ -102,17 +102,22 @@ def cpu_baseline(ms, img, n_sectors: int, target_s: float):
     n = int(min(n_sectors, max(probe, rate * target_s)))
     n -= n % 8
     host = img.data[:n * 512].cpu().numpy()
-    t0 = time.perf_counter()
-    flags = ix.flag_image(host, threads=threads)
-    dt = time.perf_counter() - t0
+    # passes over the sample until about target_s of CPU work (the whole image
+    # can take well under that on many cores)
+    passes, dt = 0, 0.0
+    while passes == 0 or (dt < target_s and passes < 64):
+        t0 = time.perf_counter()
+        flags = ix.flag_image(host, threads=threads)
+        dt += time.perf_counter() - t0
+        passes += 1
     return {
-        "value": round(n * 512 / dt / 1e9, 4),
+        "value": round(passes * n * 512 / dt / 1e9, 4),
         "unit": "GB/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"first {n} sectors ({n * 512 / 2**30:.2f} GiB) of the benchmark image, {len(flags)} flagged; "
-                   f"signatures + sorted-array membership + flag list in {dt:.2f} s on {threads} threads "
-                   f"({cpu_model()}); master sort {t_sort:.2f} s excluded"),
+        "sample": (f"first {n} sectors ({n * 512 / 2**30:.2f} GiB) of the benchmark image, {len(flags)} flagged, "
+                   f"scanned {passes} times; signatures + sorted-array membership + flag list in {dt:.2f} s on "
+                   f"{threads} threads ({cpu_model()}); master sort {t_sort:.2f} s excluded"),
     }
 
 
