@@ -5,10 +5,11 @@ may import this package. It shares no code with the GPU library
 (`paper_0901_1307_amd`), and neither imports the other.
 
 `carve_oracle.c` is the plain C implementation (djb2 of Eq. (1) with the 64-bit
-accumulator of Section 4, per-cluster-position membership of Section 3.1 via a
-sorted array and bisection, byte-for-byte confirmation of Section 3.1, and a
-brute-force all-pairs byte comparison). `spec.py` holds pure-Python forms of
-the signature used to pin the C code.
+accumulator of Section 4, or the 64-bit CRC of Section 2.1 read as
+CRC-64/GO-ISO and computed bit by bit; per-cluster-position membership of
+Section 3.1 via a sorted array and bisection, byte-for-byte confirmation of
+Section 3.1, and a brute-force all-pairs byte comparison). `spec.py` holds
+pure-Python forms of the signatures used to pin the C code.
 """
 from __future__ import annotations
 
@@ -25,6 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 SECTOR = 512
 
 MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4")])
+SIG_DJB2, SIG_CRC64_GO_ISO = 0, 1
 
 
 def build(src: str = _SRC, out: str = _LIB) -> str:
@@ -44,6 +46,13 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_sector_signatures.argtypes = [P, U64, P, I32]
     lib.oracle_build.restype = P
     lib.oracle_build.argtypes = [P, P, U32, I32]
+    if hasattr(lib, "oracle_crc64"):   # copies of an older source (mutation tests) may lack it
+        lib.oracle_crc64.restype = U64
+        lib.oracle_crc64.argtypes = [P, U64]
+        lib.oracle_sector_signatures_kind.restype = None
+        lib.oracle_sector_signatures_kind.argtypes = [P, U64, P, I32, I32]
+        lib.oracle_build_kind.restype = P
+        lib.oracle_build_kind.argtypes = [P, P, U32, I32, I32]
     lib.oracle_free.restype = None
     lib.oracle_free.argtypes = [P]
     lib.oracle_index_size.restype = U64
@@ -95,11 +104,20 @@ def djb2(data, lib=None) -> int:
     return int((lib or load()).oracle_djb2(_ptr(b), b.size))
 
 
-def sector_signatures(sectors, threads: int = 1, lib=None) -> np.ndarray:
+def crc64(data, lib=None) -> int:
+    b = _u8(data).reshape(-1)
+    return int((lib or load()).oracle_crc64(_ptr(b), b.size))
+
+
+def sector_signatures(sectors, threads: int = 1, lib=None, sig_kind: int = SIG_DJB2) -> np.ndarray:
     s = _u8(sectors).reshape(-1)
     n = s.size // SECTOR
     out = np.empty(n, dtype=np.uint64)
-    (lib or load()).oracle_sector_signatures(_ptr(s), n, _ptr(out), threads)
+    lib = lib or load()
+    if sig_kind == SIG_DJB2:
+        lib.oracle_sector_signatures(_ptr(s), n, _ptr(out), threads)
+    else:
+        lib.oracle_sector_signatures_kind(_ptr(s), n, _ptr(out), threads, sig_kind)
     return out
 
 
@@ -122,13 +140,18 @@ def pack_files(files: Sequence[bytes]) -> Tuple[np.ndarray, List[int]]:
 class Index:
     """Sorted (signature, master) entries of a packed master set."""
 
-    def __init__(self, masters, file_offsets: Sequence[int], threads: int = 1, lib=None):
+    def __init__(self, masters, file_offsets: Sequence[int], threads: int = 1, lib=None, sig_kind: int = SIG_DJB2):
         self.lib = lib or load()
         self.masters = _u8(masters).reshape(-1)
         self.offsets = np.ascontiguousarray(file_offsets, dtype=np.uint64)
         assert self.masters.size == int(self.offsets[-1]) * SECTOR
         self.n_files = len(file_offsets) - 1
-        self.h = self.lib.oracle_build(_ptr(self.masters), _ptr(self.offsets), self.n_files, threads)
+        self.sig_kind = sig_kind
+        if sig_kind == SIG_DJB2:
+            self.h = self.lib.oracle_build(_ptr(self.masters), _ptr(self.offsets), self.n_files, threads)
+        else:
+            self.h = self.lib.oracle_build_kind(_ptr(self.masters), _ptr(self.offsets), self.n_files, threads,
+                                                sig_kind)
 
     def __del__(self):
         h, self.h = getattr(self, "h", None), None

@@ -11,6 +11,12 @@
  *   - the signature of a 512-byte sector is djb2 (Eq. (1), Section 2.2) with a
  *     64-bit accumulator (Section 4): h = 5381, then h = h*33 + s for every
  *     byte s (unsigned, in address order), modulo 2^64;
+ *   - or, as the other signature the paper times (Section 2.1, Figs. 10-11),
+ *     a 64-bit CRC. The paper does not give its parameters; the reading taken
+ *     is CRC-64/GO-ISO: generator x^64 + x^4 + x^3 + x + 1, bytes fed least
+ *     significant bit first (reflected in and out), register preset to all
+ *     ones and the result complemented. It is computed bit by bit below, as
+ *     polynomial division, with no table;
  *   - master entries: sector k of master file f sits at cluster position
  *     tau = k mod 8 (Section 3.1, the per-position tables S_tau, with the
  *     8-sector cluster of Section 2);
@@ -49,13 +55,43 @@ typedef struct {
   oracle_entry* e;
   uint64_t n;
   const uint8_t* masters;
+  int sig_kind;      /* ORACLE_SIG_DJB2 or ORACLE_SIG_CRC64_GO_ISO */
 } oracle_index;
+
+enum { ORACLE_SIG_DJB2 = 0, ORACLE_SIG_CRC64_GO_ISO = 1 };
 
 /* ---------------------------------------------------------------- Eq. (1) */
 uint64_t oracle_djb2(const uint8_t* s, uint64_t len) {
   uint64_t h = 5381u;
   for (uint64_t i = 0; i < len; i++) h = h * 33u + (uint64_t)s[i];
   return h;
+}
+
+/* ------------------------------------------------------ CRC-64 (Sec. 2.1) */
+/* Generator polynomial without its x^64 term, most significant bit = x^63. */
+#define CRC64_GO_ISO_POLY 0x000000000000001Bull
+
+static uint64_t reverse64(uint64_t x) {
+  uint64_t r = 0;
+  for (int i = 0; i < 64; i++) r |= ((x >> i) & 1u) << (63 - i);
+  return r;
+}
+
+/* Reflected CRC: each input byte enters least significant bit first, so the
+ * register shifts right, its bit 0 is the coefficient that leaves next, and
+ * the generator is applied in bit-reversed form (bit 63 = x^0, bit 0 = x^63). */
+uint64_t oracle_crc64(const uint8_t* s, uint64_t len) {
+  const uint64_t poly_reflected = reverse64(CRC64_GO_ISO_POLY);
+  uint64_t crc = ~0ull;                       /* preset to all ones */
+  for (uint64_t i = 0; i < len; i++) {
+    crc ^= (uint64_t)s[i];
+    for (int b = 0; b < 8; b++) crc = (crc & 1u) ? (crc >> 1) ^ poly_reflected : crc >> 1;
+  }
+  return ~crc;                                /* complemented result */
+}
+
+static uint64_t signature(int kind, const uint8_t* s) {
+  return kind == ORACLE_SIG_CRC64_GO_ISO ? oracle_crc64(s, SECTOR_BYTES) : oracle_djb2(s, SECTOR_BYTES);
 }
 
 /* --------------------------------------------------------------- threads */
@@ -95,17 +131,23 @@ static void parallel_for(uint64_t n, int threads, void (*fn)(void*, uint64_t, ui
 typedef struct {
   const uint8_t* data;
   uint64_t* out;
+  int kind;
 } sig_ctx;
 
 static void sig_range(void* p, uint64_t lo, uint64_t hi, int t) {
   (void)t;
   sig_ctx* c = (sig_ctx*)p;
-  for (uint64_t i = lo; i < hi; i++) c->out[i] = oracle_djb2(c->data + i * SECTOR_BYTES, SECTOR_BYTES);
+  for (uint64_t i = lo; i < hi; i++) c->out[i] = signature(c->kind, c->data + i * SECTOR_BYTES);
+}
+
+void oracle_sector_signatures_kind(const uint8_t* data, uint64_t n_sectors, uint64_t* out, int threads,
+                                   int kind) {
+  sig_ctx c = {data, out, kind};
+  parallel_for(n_sectors, threads, sig_range, &c);
 }
 
 void oracle_sector_signatures(const uint8_t* data, uint64_t n_sectors, uint64_t* out, int threads) {
-  sig_ctx c = {data, out};
-  parallel_for(n_sectors, threads, sig_range, &c);
+  oracle_sector_signatures_kind(data, n_sectors, out, threads, ORACLE_SIG_DJB2);
 }
 
 /* ------------------------------------------------------------ the index */
@@ -122,6 +164,7 @@ typedef struct {
   const uint64_t* file_offsets;
   uint32_t n_files;
   oracle_entry* e;
+  int kind;
 } build_ctx;
 
 static void build_range(void* p, uint64_t lo, uint64_t hi, int t) {
@@ -130,7 +173,7 @@ static void build_range(void* p, uint64_t lo, uint64_t hi, int t) {
   uint32_t f = 0;
   for (uint64_t m = lo; m < hi; m++) {
     while (f + 1 < c->n_files && c->file_offsets[f + 1] <= m) f++;
-    c->e[m].sig = oracle_djb2(c->masters + m * SECTOR_BYTES, SECTOR_BYTES);
+    c->e[m].sig = signature(c->kind, c->masters + m * SECTOR_BYTES);
     c->e[m].master = m;
     c->e[m].file = f;
     c->e[m].k = (uint32_t)(m - c->file_offsets[f]);
@@ -139,16 +182,22 @@ static void build_range(void* p, uint64_t lo, uint64_t hi, int t) {
 
 /* masters: n = file_offsets[n_files] packed sectors; file f owns sectors
  * [file_offsets[f], file_offsets[f+1]). The masters buffer must outlive the index. */
-void* oracle_build(const uint8_t* masters, const uint64_t* file_offsets, uint32_t n_files, int threads) {
+void* oracle_build_kind(const uint8_t* masters, const uint64_t* file_offsets, uint32_t n_files, int threads,
+                        int kind) {
   oracle_index* ix = (oracle_index*)calloc(1, sizeof(oracle_index));
   ix->n = n_files ? file_offsets[n_files] : 0;
   ix->masters = masters;
+  ix->sig_kind = kind;
   ix->e = (oracle_entry*)malloc(sizeof(oracle_entry) * (ix->n ? ix->n : 1));
-  build_ctx c = {masters, file_offsets, n_files, ix->e};
+  build_ctx c = {masters, file_offsets, n_files, ix->e, kind};
   /* file lookup walks forward from 0 in each range: fine for tests */
   parallel_for(ix->n, threads, build_range, &c);
   qsort(ix->e, ix->n, sizeof(oracle_entry), entry_cmp);
   return ix;
+}
+
+void* oracle_build(const uint8_t* masters, const uint64_t* file_offsets, uint32_t n_files, int threads) {
+  return oracle_build_kind(masters, file_offsets, n_files, threads, ORACLE_SIG_DJB2);
 }
 
 void oracle_free(void* p) {
@@ -195,7 +244,7 @@ static void flag_range(void* p, uint64_t lo, uint64_t hi, int t) {
   flag_ctx* c = (flag_ctx*)p;
   for (uint64_t i = lo; i < hi; i++) {
     uint64_t j = c->ids ? c->ids[i] : i;
-    uint64_t h = oracle_djb2(c->image + i * SECTOR_BYTES, SECTOR_BYTES);
+    uint64_t h = signature(c->ix->sig_kind, c->image + i * SECTOR_BYTES);
     c->flag[i] = (uint8_t)is_flagged(c->ix, h, j, c->tau0, c->any_tau);
   }
 }
@@ -236,7 +285,7 @@ int64_t oracle_confirm(void* p, const uint8_t* sectors, const uint64_t* ids, uin
   uint64_t cnt = 0;
   for (uint64_t i = 0; i < n; i++) {
     const uint8_t* s = sectors + i * SECTOR_BYTES;
-    uint64_t h = oracle_djb2(s, SECTOR_BYTES);
+    uint64_t h = signature(ix->sig_kind, s);
     for (uint64_t q = lower_bound(ix, h); q < ix->n && ix->e[q].sig == h; q++) {
       const oracle_entry* e = &ix->e[q];
       if (!tau_ok(e, ids[i], tau0, any_tau)) continue;

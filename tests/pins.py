@@ -100,6 +100,70 @@ SIGNATURE_PINS = [pin_golden, pin_constant_sectors, pin_closed_form, pin_mod32, 
                   pin_crafted, pin_batch_signatures]
 
 
+# ------------------------------------------------- CRC-64 (Section 2.1 reading)
+def crc_catalogue():
+    out = []
+    with open(os.path.join(GOLDEN, "crc64_catalogue.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            hx, name, val = line.split()[:3]
+            out.append((bytes.fromhex(hx), name, int(val, 16)))
+    return out
+
+
+CRC_PARAMS = {"CRC-64/GO-ISO": spec.CRC64_GO_ISO, "CRC-64/XZ": spec.CRC64_XZ}
+
+
+def pin_crc_catalogue(lib):
+    """The oracle's CRC-64 gives the published CRC-64/GO-ISO check value."""
+    for data, name, want in crc_catalogue():
+        if name == "CRC-64/GO-ISO":
+            got = oracle.crc64(data, lib=lib)
+            assert got == want, (hex(got), hex(want))
+
+
+def pin_crc_division(lib, n=24, seed=13):
+    """Special and random sectors: the oracle equals the polynomial-division
+    definition (itself checked against zlib and the catalogue)."""
+    rng = random.Random(seed)
+    secs = [bytes(SECTOR), b"\xff" * SECTOR, bytes(i & 255 for i in range(SECTOR))]
+    secs += [bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(n)]
+    for s in secs:
+        assert oracle.crc64(s, lib=lib) == spec.crc_polydiv(s)
+
+
+def pin_crc_affine(lib, n=16, seed=14):
+    """A CRC with fixed length is affine over GF(2): crc(a^b^c) = crc(a)^crc(b)^crc(c)."""
+    rng = random.Random(seed)
+    for _ in range(n):
+        a, b, c = (bytes(rng.getrandbits(8) for _ in range(SECTOR)) for _ in range(3))
+        x = bytes(p ^ q ^ r for p, q, r in zip(a, b, c))
+        assert oracle.crc64(x, lib=lib) == oracle.crc64(a, lib=lib) ^ oracle.crc64(b, lib=lib) ^ oracle.crc64(c, lib=lib)
+
+
+def pin_crc_collisions(lib, seed=15):
+    """Flipping the bits of x^k P(x) keeps the CRC."""
+    rng = random.Random(seed)
+    s = bytes(rng.getrandbits(8) for _ in range(SECTOR))
+    for k in (0, 7, 1000, 4096 - 65):
+        t = spec.crc_collide(s, k)
+        assert t != s and oracle.crc64(t, lib=lib) == oracle.crc64(s, lib=lib)
+
+
+def pin_crc_sector_signatures(lib, seed=16):
+    """The threaded per-sector routine with the CRC kind equals the one-sector routine."""
+    rng = np.random.default_rng(seed)
+    secs = rng.integers(0, 256, size=(129, SECTOR), dtype=np.uint8)
+    got = oracle.sector_signatures(secs, threads=3, lib=lib, sig_kind=oracle.SIG_CRC64_GO_ISO)
+    for i in range(0, 129, 8):
+        assert int(got[i]) == spec.crc_bytewise(secs[i].tobytes())
+
+
+SIGNATURE_PINS += [pin_crc_catalogue, pin_crc_division, pin_crc_affine, pin_crc_collisions,
+                   pin_crc_sector_signatures]
+
+
 # ----------------------------------------------------------- sets of results
 def small_case(seed=3, n_disk=700, tail=77):
     """A tiny master set with uneven file sizes and a disk image with planted
@@ -201,5 +265,45 @@ def pin_edges(lib):
     assert [int(x) for x in cix.flag_image(np.frombuffer(bytes(disk), np.uint8))] == [13]
 
 
-SET_PINS = [pin_sets_vs_definition, pin_edges]
+def crc_small_case(seed=4, n_disk=400):
+    """The small case's layout with CRC collisions crafted in place of the djb2 ones."""
+    image, masters, offsets, truth = small_case(seed, n_disk=n_disk, tail=33)
+    rng = random.Random(seed + 100)
+    img = bytearray(image)
+    replaced = set()
+    for c in range(0, n_disk // 8, 5):
+        f = rng.randrange(len(offsets) - 1)
+        k = rng.randrange(offsets[f + 1] - offsets[f])
+        j = 8 * c + k % 8                                  # the master's cluster position
+        img[j * SECTOR:(j + 1) * SECTOR] = spec.crc_collide(masters[offsets[f] + k], rng.randrange(4000))
+        replaced.add(j)
+    return bytes(img), masters, offsets, [t for t in truth if t[0] not in replaced]
+
+
+def pin_crc_sets(lib, seed=4):
+    """With the CRC signature: flags equal the definition (byte-wise CRC and
+    Python sets), confirmed matches equal the all-pairs byte comparison, and
+    the crafted CRC collisions are flagged without being confirmed."""
+    image, masters, offsets, truth = crc_small_case(seed)
+    mflat = np.frombuffer(b"".join(masters), np.uint8)
+    sig_cache = {}
+
+    def sig(b):
+        if b not in sig_cache:
+            sig_cache[b] = spec.crc_bytewise(b)
+        return sig_cache[b]
+
+    ix = oracle.Index(mflat, offsets, threads=2, lib=lib, sig_kind=oracle.SIG_CRC64_GO_ISO)
+    img = np.frombuffer(image, np.uint8)
+    for tau0, any_tau in ((0, False), (5, False), (0, True)):
+        flags = [int(x) for x in ix.flag_image(img, tau0, any_tau, threads=2)]
+        assert flags == spec.flagged_by_definition(image, masters, offsets, tau0, any_tau, sig=sig), (tau0, any_tau)
+        conf = _as_tuples(ix.confirm_image(img, flags, tau0, any_tau))
+        assert conf == spec.brute_force_matches(image, masters, offsets, tau0, any_tau)
+        if tau0 == 0 and not any_tau:
+            assert set(truth) <= set(conf)
+            assert len(set(flags) - set(j for j, _, _ in conf)) > 0
+
+
+SET_PINS = [pin_sets_vs_definition, pin_edges, pin_crc_sets]
 ALL_PINS = SIGNATURE_PINS + SET_PINS

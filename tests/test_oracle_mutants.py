@@ -33,6 +33,14 @@ MUTANTS = {
                       "if (memcmp(s, ix->masters + e->master * SECTOR_BYTES, 8) != 0) continue;"),
     "last-sector-dropped": ("for (uint64_t j = 0; j < n; j++)\n    if (flag[j])",
                             "for (uint64_t j = 0; j + 1 < n; j++)\n    if (flag[j])"),
+    "crc-poly-1a": ("#define CRC64_GO_ISO_POLY 0x000000000000001Bull", "#define CRC64_GO_ISO_POLY 0x000000000000001Aull"),
+    "crc-poly-unreflected": ("const uint64_t poly_reflected = reverse64(CRC64_GO_ISO_POLY);",
+                             "const uint64_t poly_reflected = CRC64_GO_ISO_POLY;"),
+    "crc-zero-preset": ("uint64_t crc = ~0ull;", "uint64_t crc = 0;"),
+    "crc-no-final-complement": ("return ~crc;", "return crc;"),
+    "crc-byte-at-top": ("crc ^= (uint64_t)s[i];", "crc ^= (uint64_t)s[i] << 56;"),
+    "crc-kind-ignored": ("return kind == ORACLE_SIG_CRC64_GO_ISO ? oracle_crc64(s, SECTOR_BYTES) : oracle_djb2(s, SECTOR_BYTES);",
+                         "return oracle_djb2(s, SECTOR_BYTES);"),
 }
 
 
