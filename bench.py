@@ -85,14 +85,14 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(ms, img, n_sectors: int, target_s: float):
+def cpu_baseline(ms, img, n_sectors: int, target_s: float, sig_kind: int = 0):
     """The oracle, as it is, on the host cores: signatures + membership + flag
     list over the first sectors of the same image (the master sort is timed
     apart and excluded)."""
     import oracle
     threads = oracle.default_threads()
     t0 = time.perf_counter()
-    ix = oracle.Index(ms.sectors.cpu().numpy(), ms.file_offsets, threads=threads)
+    ix = oracle.Index(ms.sectors.cpu().numpy(), ms.file_offsets, threads=threads, sig_kind=sig_kind)
     t_sort = time.perf_counter() - t0
     probe = min(n_sectors, 1 << 17)               # 64 MiB to size the sample
     host = img.data[:probe * 512].cpu().numpy()
@@ -367,6 +367,8 @@ def main():
     ap.add_argument("--workload", default="plain", choices=["plain", "batched", "served"],
                     help="plain: one image (the headline line); batched: 256 uneven images in one launch; "
                          "served: Poisson stream of scan jobs through the continuous-batching server")
+    ap.add_argument("--sig", default="djb2", choices=["djb2", "crc64"],
+                    help="plain: sector signature (djb2-64 of Eq. (1), or the CRC-64 of Section 2.1)")
     ap.add_argument("--images", type=int, default=256, help="batched: number of images")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
@@ -405,7 +407,9 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] generated in {time.perf_counter() - t0:.1f} s; building the index")
     t0 = time.perf_counter()
-    idx = carve.build_master_index(ms.sectors, ms.file_offsets)
+    sig_kind = carve.CARVE_SIG_CRC64_ISO if args.sig == "crc64" else carve.CARVE_SIG_DJB2_64
+    sig_name = "CRC-64/GO-ISO" if args.sig == "crc64" else "djb2-64"
+    idx = carve.build_master_index(ms.sectors, ms.file_offsets, sig_kind=sig_kind)
     log(f"[bench] index built in {time.perf_counter() - t0:.2f} s: {idx.stats()}")
 
     n_sectors = cfg.n_disk_sectors
@@ -446,7 +450,7 @@ def main():
     value = image_bytes / (ms_per_step * 1e-3) / 1e9
     k_avg = sum(kernel_ms) / len(kernel_ms)
     achieved = n_sectors * BYTES_PER_SECTOR_ALG / (k_avg * 1e-3) / 1e9
-    traffic, traffic_src = measured_traffic(cfg.name, k_avg)
+    traffic, traffic_src = measured_traffic(cfg.name if args.sig == "djb2" else f"{cfg.name}-{args.sig}", k_avg)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -463,7 +467,8 @@ def main():
         "config": {
             "workload": (f"{cfg.name}: {image_bytes / 2**30:.0f} GiB device-resident disk image "
                          f"({n_sectors} sectors of 512 B) against {cfg.n_master_sectors} master sectors "
-                         f"in {len(ms.file_offsets) - 1} files, djb2-64, per-cluster positions"),
+                         f"in {len(ms.file_offsets) - 1} files, {sig_name}, per-cluster positions"),
+            "signature": sig_name,
             "image_bytes": image_bytes,
             "n_sectors": n_sectors,
             "n_master_sectors": cfg.n_master_sectors,
@@ -490,7 +495,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(ms, img, n_sectors, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(ms, img, n_sectors, args.cpu_seconds, sig_kind)
     print(json.dumps(out), flush=True)
 
 

@@ -48,7 +48,11 @@ typedef enum {
 } carve_status;
 
 typedef enum {
-  CARVE_SIG_DJB2_64 = 0    /* Eq. (1), 64-bit accumulator (Section 4) */
+  CARVE_SIG_DJB2_64 = 0,   /* Eq. (1), 64-bit accumulator (Section 4) */
+  CARVE_SIG_CRC64_ISO = 1  /* the 64-bit CRC of Section 2.1, read as CRC-64/GO-ISO: generator
+                              x^64 + x^4 + x^3 + x + 1, reflected in and out, register preset to
+                              all ones, result complemented (check value of "123456789":
+                              0xb90956c775a41001) */
 } carve_sig_kind;
 
 typedef enum {
@@ -57,7 +61,7 @@ typedef enum {
 } carve_tau_mode;
 
 typedef struct {
-  uint32_t sig_kind;           /* carve_sig_kind; 0 = djb2-64 */
+  uint32_t sig_kind;           /* carve_sig_kind of master and disk sectors; 0 = djb2-64 */
   float max_load;              /* hash-table load factor ceiling in (0, 0.9]; 0 = 0.5 */
   uint32_t bloom_bits_per_key; /* prefilter in front of the table: 0 = automatic (at least 4 bits per
                                   distinct signature, then as many as a 4 MiB filter and 16 bits allow),
@@ -180,6 +184,11 @@ int confirm_enqueue(const carve_index* idx, carve_scan* sc);
  * n_sectors values. Asynchronous on `stream`.
  */
 int sector_signatures(const void* sectors, uint64_t n_sectors, uint64_t* sigs, void* stream);
+
+/* sector_signatures_kind -- sector_signatures for a carve_sig_kind (djb2-64,
+ * Eq. (1); or CRC-64, Section 2.1). EINVAL for an unknown kind. */
+int sector_signatures_kind(uint32_t sig_kind, const void* sectors, uint64_t n_sectors, uint64_t* sigs,
+                           void* stream);
 
 /* index_stats -- sizes of a built index (host struct). */
 int index_stats(const carve_index* idx, carve_index_stats* out);

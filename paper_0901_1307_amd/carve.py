@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcarve.so")
 SECTOR = 512
 
 CARVE_OK, CARVE_EINVAL, CARVE_ENOMEM, CARVE_ETRUNC, CARVE_EDEVICE, CARVE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-CARVE_SIG_DJB2_64 = 0
+CARVE_SIG_DJB2_64, CARVE_SIG_CRC64_ISO = 0, 1
 CARVE_TAU_PER_CLUSTER, CARVE_TAU_ANY = 0, 1
 
 MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4")])
@@ -30,10 +30,11 @@ JOB_DONE_DTYPE = np.dtype([("job_id", "<u8"), ("n_flagged", "<u8"), ("n_confirme
                            ("reserved", "<u4")])
 
 EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_matches", "sector_signatures",
-           "index_stats", "index_set_scan_config", "index_get_scan_config", "autotune_scan", "scan_batch",
-           "batch_flag_counts", "batch_flagged_sectors", "batch_confirm_matches", "scan_set_timing",
-           "scan_kernel_ms", "confirm_enqueue", "batch_confirm_enqueue", "server_create", "server_submit", "server_submit_many", "server_poll", "server_job_flags",
-           "server_job_matches", "server_release", "server_release_many", "server_stats", "server_free", "free_index", "free_scan",
+           "sector_signatures_kind", "index_stats", "index_set_scan_config", "index_get_scan_config",
+           "autotune_scan", "scan_batch", "batch_flag_counts", "batch_flagged_sectors", "batch_confirm_matches",
+           "scan_set_timing", "scan_kernel_ms", "confirm_enqueue", "batch_confirm_enqueue", "server_create",
+           "server_submit", "server_submit_many", "server_poll", "server_job_flags", "server_job_matches",
+           "server_release", "server_release_many", "server_stats", "server_free", "free_index", "free_scan",
            "free_batch", "carve_last_error")
 
 
@@ -110,6 +111,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.confirm_matches.argtypes = [P, P, P, U64, PU64]
     lib.sector_signatures.restype = I32
     lib.sector_signatures.argtypes = [P, U64, P, P]
+    lib.sector_signatures_kind.restype = I32
+    lib.sector_signatures_kind.argtypes = [U32, P, U64, P, P]
     lib.index_stats.restype = I32
     lib.index_stats.argtypes = [P, ctypes.POINTER(_IndexStats)]
     lib.index_set_scan_config.restype = I32
@@ -284,10 +287,12 @@ class Batch:
 
 
 def build_master_index(master_sectors: torch.Tensor, file_sector_offsets: Sequence[int], max_load: float = 0.0,
-                       bloom_bits_per_key: int = 0, stream=None) -> Index:
+                       bloom_bits_per_key: int = 0, stream=None, sig_kind: int = CARVE_SIG_DJB2_64) -> Index:
     """Index of packed master sectors (uint8 device tensor, file after file).
 
-    bloom_bits_per_key: 0 = automatic, CARVE_BLOOM_OFF = no prefilter."""
+    bloom_bits_per_key: 0 = automatic, CARVE_BLOOM_OFF = no prefilter.
+    sig_kind: CARVE_SIG_DJB2_64 or CARVE_SIG_CRC64_ISO (every scan with this
+    index uses the same signature)."""
     lib = load_library()
     m = _dev_u8(master_sectors, "master_sectors")
     off = np.ascontiguousarray(file_sector_offsets, dtype=np.uint64)
@@ -295,7 +300,7 @@ def build_master_index(master_sectors: torch.Tensor, file_sector_offsets: Sequen
         raise ValueError("file_sector_offsets needs at least one entry")
     if m.numel() != int(off[-1]) * SECTOR:
         raise ValueError("master_sectors size does not match file_sector_offsets[-1] sectors")
-    p = _IndexParams(CARVE_SIG_DJB2_64, float(max_load), int(bloom_bits_per_key))
+    p = _IndexParams(int(sig_kind), float(max_load), int(bloom_bits_per_key))
     h = ctypes.c_void_p()
     _check(lib.build_master_index(m.data_ptr() if m.numel() else None, off.ctypes.data, off.size - 1,
                                   ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))
@@ -366,15 +371,17 @@ def confirm_matches(index: Index, scan: Scan, out: Optional[torch.Tensor] = None
     return int(n.value)
 
 
-def sector_signatures(sectors: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """djb2-64 of each whole sector of a device tensor, as int64 (bit pattern of the uint64)."""
+def sector_signatures(sectors: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None,
+                      sig_kind: int = CARVE_SIG_DJB2_64) -> torch.Tensor:
+    """Signature (djb2-64 by default, or CRC-64) of each whole sector of a
+    device tensor, as int64 (bit pattern of the uint64)."""
     lib = load_library()
     s = _dev_u8(sectors, "sectors")
     n = s.numel() // SECTOR
     if out is None:
         out = torch.empty(n, dtype=torch.int64, device=s.device)
-    _check(lib.sector_signatures(s.data_ptr() if n else None, n, out.data_ptr() if n else None,
-                                 _stream_ptr(stream)))
+    _check(lib.sector_signatures_kind(int(sig_kind), s.data_ptr() if n else None, n,
+                                      out.data_ptr() if n else None, _stream_ptr(stream)))
     return out
 
 

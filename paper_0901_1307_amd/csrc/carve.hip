@@ -530,18 +530,27 @@ struct HostBuf {
 
 uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-// Device address of the signature weight table on the current device (0 on failure).
-uint64_t weight_table() {
-  static uint64_t ptr[64] = {};
+// Device address, on the current device, of the table the scan kernel of a
+// signature kind reads: djb2's digit-plane weights or the CRC's slicing
+// tables (0 on failure).
+uint64_t sig_table(uint32_t kind) {
+  static uint64_t ptr[64][2] = {};
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (!ptr[dev]) {
+  if (kind > 1 || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (!ptr[dev][kind]) {
     void* p = nullptr;
-    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_weights)) != hipSuccess) return 0;
-    ptr[dev] = (uint64_t)(uintptr_t)p;
+    const hipError_t e = kind == CARVE_SIG_CRC64_ISO ? hipGetSymbolAddress(&p, HIP_SYMBOL(g_crc_tables))
+                                                     : hipGetSymbolAddress(&p, HIP_SYMBOL(g_weights));
+    if (e != hipSuccess) return 0;
+    ptr[dev][kind] = (uint64_t)(uintptr_t)p;
   }
-  return ptr[dev];
+  return ptr[dev][kind];
 }
+
+// One scan kernel launch for the signature kind chosen at run time.
+template <int kMode, class Src>
+int launch_k_scan(uint32_t kind, const Src& src, uint64_t n_tiles, uint32_t chunk, uint32_t per_cu_cap,
+                  const IndexView& ix, uint64_t wt, uint64_t* out, uint32_t* hit_slot, hipStream_t s);
 
 int device_cus() {
   static int cus = 0;
@@ -586,6 +595,21 @@ int resident_grid(Kernel kernel, int threads, uint64_t want, uint32_t per_cu_cap
   return (int)(want < cap ? (want ? want : 1) : cap);
 }
 
+template <int kMode, class Src>
+int launch_k_scan(uint32_t kind, const Src& src, uint64_t n_tiles, uint32_t chunk, uint32_t per_cu_cap,
+                  const IndexView& ix, uint64_t wt, uint64_t* out, uint32_t* hit_slot, hipStream_t s) {
+  const uint64_t want = cdiv(cdiv(n_tiles, chunk), kScanWaves);
+  if (kind == CARVE_SIG_CRC64_ISO) {
+    const int grid = resident_grid(k_scan<kMode, kSigCrc64, Src>, kScanThreads, want, per_cu_cap);
+    k_scan<kMode, kSigCrc64, Src><<<grid, kScanThreads, 0, s>>>(src, chunk, ix, wt, out, hit_slot);
+  } else {
+    const int grid = resident_grid(k_scan<kMode, kSigDjb2, Src>, kScanThreads, want, per_cu_cap);
+    k_scan<kMode, kSigDjb2, Src><<<grid, kScanThreads, 0, s>>>(src, chunk, ix, wt, out, hit_slot);
+  }
+  HIP_TRY(hipGetLastError());
+  return CARVE_OK;
+}
+
 }  // namespace
 
 // ================================================================ objects
@@ -599,7 +623,8 @@ struct carve_index {
   uint32_t zero_sig_mask = 0;
   uint64_t n_unique = 0;
   uint64_t n_overflow = 0;
-  uint64_t weights = 0;
+  uint64_t weights = 0;     // address of the table of the signature kind (sig_table)
+  uint32_t sig_kind = CARVE_SIG_DJB2_64;
   uint32_t log2_bloom_words = 0;
   carve_scan_config cfg{};
   DevBuf keys, tau_mask, cand_off, cand, m_file, m_k, bloom;   // tau_mask: one byte per slot
@@ -693,10 +718,8 @@ int launch_scan(carve_scan* sc, const Src& src) {
   }
   if (sc->timing) HIP_TRY(hipEventRecord(sc->ev0, s));
   const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
-  const int grid = resident_grid(k_scan<kFlags, Src>, kScanThreads, cdiv(cdiv(n_words, chunk), kScanWaves),
-                                 idx->cfg.blocks_per_cu);
-  k_scan<kFlags, Src><<<grid, kScanThreads, 0, s>>>(src, chunk, idx->view(), idx->weights, sc->bitmap.as<uint64_t>(),
-                                                    sc->hit_slot.as<uint32_t>());
+  CARVE_TRY(launch_k_scan<kFlags>(idx->sig_kind, src, n_words, chunk, idx->cfg.blocks_per_cu, idx->view(),
+                                   idx->weights, sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>(), s));
   if (sc->timing) {
     HIP_TRY(hipEventRecord(sc->ev1, s));
     sc->timed = true;
@@ -842,19 +865,22 @@ CARVE_HIDDEN int carve_fail_msg(int code, const char* msg) {
   return fail(code, "%s", msg);
 }
 
-extern "C" int sector_signatures(const void* sectors, uint64_t n_sectors, uint64_t* sigs, void* stream) {
+extern "C" int sector_signatures_kind(uint32_t sig_kind, const void* sectors, uint64_t n_sectors, uint64_t* sigs,
+                                      void* stream) {
+  if (sig_kind != CARVE_SIG_DJB2_64 && sig_kind != CARVE_SIG_CRC64_ISO)
+    return fail(CARVE_EINVAL, "sector_signatures: unknown sig_kind %u", sig_kind);
   if (n_sectors == 0) return CARVE_OK;
   if (!sectors || !sigs) return fail(CARVE_EINVAL, "sector_signatures: null pointer");
   if ((uintptr_t)sectors % 16) return fail(CARVE_EINVAL, "sector_signatures: sectors not 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const uint64_t wt = weight_table();
-  if (!wt) return fail(CARVE_EDEVICE, "sector_signatures: weight table unavailable");
+  const uint64_t wt = sig_table(sig_kind);
+  if (!wt) return fail(CARVE_EDEVICE, "sector_signatures: signature table unavailable");
   const OneImage src{ImageDesc{(const uint8_t*)sectors, n_sectors, 0, 0, 0}};
-  const uint64_t n_tiles = cdiv(n_sectors, kTileSectors);
-  k_scan<kSigs, OneImage><<<resident_grid(k_scan<kSigs, OneImage>, kScanThreads, cdiv(n_tiles, kScanWaves)),
-                            kScanThreads, 0, s>>>(src, 1, IndexView{}, wt, sigs, nullptr);
-  HIP_TRY(hipGetLastError());
-  return CARVE_OK;
+  return launch_k_scan<kSigs>(sig_kind, src, cdiv(n_sectors, kTileSectors), 1, 0, IndexView{}, wt, sigs, nullptr, s);
+}
+
+extern "C" int sector_signatures(const void* sectors, uint64_t n_sectors, uint64_t* sigs, void* stream) {
+  return sector_signatures_kind(CARVE_SIG_DJB2_64, sectors, n_sectors, sigs, stream);
 }
 
 extern "C" void free_index(carve_index* idx) {
@@ -882,7 +908,8 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
     for (uint32_t r : p.reserved)
       if (r) return fail(CARVE_EINVAL, "build_master_index: reserved params must be zero");
   }
-  if (p.sig_kind != CARVE_SIG_DJB2_64) return fail(CARVE_EUNSUPPORTED, "build_master_index: unknown sig_kind %u", p.sig_kind);
+  if (p.sig_kind != CARVE_SIG_DJB2_64 && p.sig_kind != CARVE_SIG_CRC64_ISO)
+    return fail(CARVE_EUNSUPPORTED, "build_master_index: unknown sig_kind %u", p.sig_kind);
   if (!(p.max_load > 0.f && p.max_load <= 0.9f)) return fail(CARVE_EINVAL, "build_master_index: max_load out of (0, 0.9]");
   if (p.bloom_bits_per_key != 0 && p.bloom_bits_per_key != CARVE_BLOOM_OFF &&
       (p.bloom_bits_per_key < 4 || p.bloom_bits_per_key > 64))
@@ -909,8 +936,9 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   ix->n_masters = n_masters;
   ix->n_files = n_files;
   ix->masters = (const uint8_t*)master_sectors;
-  ix->weights = weight_table();
-  if (!ix->weights) return bail(fail(CARVE_EDEVICE, "build_master_index: weight table unavailable"));
+  ix->sig_kind = p.sig_kind;
+  ix->weights = sig_table(p.sig_kind);
+  if (!ix->weights) return bail(fail(CARVE_EDEVICE, "build_master_index: signature table unavailable"));
   uint32_t lb = 1;
   while (((uint64_t)kBucketSlots << lb) * p.max_load < (double)n_masters) ++lb;
   if (lb > 27) return bail(fail(CARVE_EUNSUPPORTED, "build_master_index: table too large"));   // slots fit 32 bits
@@ -961,11 +989,10 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
     k_master_meta<<<nbk, 256, 0, s>>>(d_off.as<uint64_t>(), n_files, n_masters, ix->m_file.as<uint32_t>(),
                                      ix->m_k.as<uint32_t>());
     const uint64_t n_tiles = cdiv(n_masters, kTileSectors);
-    const uint64_t wt = weight_table();
-    if (!wt) return bail2(fail(CARVE_EDEVICE, "build_master_index: weight table unavailable"));
     const OneImage src{ImageDesc{ix->masters, n_masters, 0, 0, 0}};
-    k_scan<kSigs, OneImage><<<resident_grid(k_scan<kSigs, OneImage>, kScanThreads, cdiv(n_tiles, kScanWaves)),
-                              kScanThreads, 0, s>>>(src, 1, IndexView{}, wt, sig.as<uint64_t>(), nullptr);
+    if ((rc = launch_k_scan<kSigs>(ix->sig_kind, src, n_tiles, 1, 0, IndexView{}, ix->weights, sig.as<uint64_t>(),
+                                   nullptr, s)))
+      return bail2(rc);
     k_insert<<<nbk, 256, 0, s>>>(sig.as<uint64_t>(), ix->m_k.as<uint32_t>(), n_masters, ix->keys.as<uint64_t>(), lb,
                                 mask32.as<uint32_t>(), cnt.as<uint32_t>(), m_slot.as<uint32_t>(), d_overflow,
                                 d_failed);

@@ -222,6 +222,85 @@ __device__ __forceinline__ uint64_t tile_signature_pipelined(const Rows& rows, u
   return finish_signature(acc);
 }
 
+// ---------------------------------------------------------------- CRC-64
+// The other signature of Section 2.1: a 64-bit CRC, read as CRC-64/GO-ISO
+// (generator x^64 + x^4 + x^3 + x + 1, bytes entering least significant bit
+// first, register preset to all ones, result complemented). Computed by
+// slicing by 8: x = crc ^ (next 8 bytes, little-endian); the new register is
+// the xor of T_j[byte j of x], where T_j[v] is the register's change when
+// byte v is followed by 7 - j more bytes (T_0 is the one-byte step). The 16 KB
+// of tables are copied into LDS by each block; lookups are then ds_read_b64.
+enum : int { kSigDjb2 = 0, kSigCrc64 = 1 };   // the values of carve_sig_kind
+
+constexpr uint64_t reflect64(uint64_t x) {
+  uint64_t r = 0;
+  for (int i = 0; i < 64; ++i) r |= ((x >> i) & 1ull) << (63 - i);
+  return r;
+}
+constexpr uint64_t kCrcPoly = 0x1Bull;                        // generator without x^64, bit k = x^k
+constexpr uint64_t kCrcPolyReflected = reflect64(kCrcPoly);   // as the right-shifting register sees it
+
+struct CrcTables {
+  uint64_t t[8][256];
+};
+constexpr CrcTables make_crc_tables() {
+  CrcTables c{};
+  for (uint32_t v = 0; v < 256; ++v) {
+    uint64_t r = v;
+    for (int b = 0; b < 8; ++b) r = (r & 1ull) ? (r >> 1) ^ kCrcPolyReflected : r >> 1;
+    c.t[0][v] = r;
+  }
+  for (int j = 1; j < 8; ++j)
+    for (uint32_t v = 0; v < 256; ++v) c.t[j][v] = (c.t[j - 1][v] >> 8) ^ c.t[0][c.t[j - 1][v] & 0xFFu];
+  return c;
+}
+__device__ CrcTables g_crc_tables = make_crc_tables();
+
+typedef const __attribute__((address_space(3))) uint64_t* LdsTable;
+
+__device__ __forceinline__ uint64_t crc_step8(uint64_t crc, uint32_t w_lo, uint32_t w_hi, LdsTable tab) {
+  const uint32_t lo = (uint32_t)crc ^ w_lo, hi = (uint32_t)(crc >> 32) ^ w_hi;
+  return tab[7 * 256 + (lo & 0xFFu)] ^ tab[6 * 256 + ((lo >> 8) & 0xFFu)] ^ tab[5 * 256 + ((lo >> 16) & 0xFFu)] ^
+         tab[4 * 256 + (lo >> 24)] ^ tab[3 * 256 + (hi & 0xFFu)] ^ tab[2 * 256 + ((hi >> 8) & 0xFFu)] ^
+         tab[1 * 256 + ((hi >> 16) & 0xFFu)] ^ tab[0 * 256 + (hi >> 24)];
+}
+
+// Stage a phase through this wave's LDS area, then run lane l's register over
+// the 128 bytes of its sector, in address order.
+__device__ __forceinline__ void crc_phase(const PhaseRegs& r, uint8_t* lds, LdsTable tab, uint64_t& crc) {
+  __builtin_amdgcn_sched_barrier(0);
+  const uint32_t l = lane_id();
+  const uint32_t col = (l & 7u) * 16u;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) *(u32x4*)(lds + (8u * i + (l >> 3)) * kRowPitch + col) = r.v[i];
+  wave_sync_lds();
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const u32x4 x4 = *(const u32x4*)(lds + l * kRowPitch + c * 16);
+    crc = crc_step8(crc, x4[0], x4[1], tab);
+    crc = crc_step8(crc, x4[2], x4[3], tab);
+  }
+  asm volatile("" : "+v"(crc));
+  wave_sync_lds();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// CRC-64 of every sector of a tile, with the same load pipeline as the djb2 path.
+template <bool kNonTemporal, class Rows, class Prefetch>
+__device__ __forceinline__ uint64_t tile_crc_pipelined(const Rows& rows, uint8_t* lds, LdsTable tab, PhaseRegs& A,
+                                                       PhaseRegs& B, Prefetch&& prefetch) {
+  uint64_t crc = ~0ull;
+  load_phase<kNonTemporal>(rows, 1, B);
+  crc_phase(A, lds, tab, crc);
+  load_phase<kNonTemporal>(rows, 2, A);
+  crc_phase(B, lds, tab, crc);
+  load_phase<kNonTemporal>(rows, 3, B);
+  crc_phase(A, lds, tab, crc);
+  prefetch(A);
+  crc_phase(B, lds, tab, crc);
+  return ~crc;
+}
+
 // ---------------------------------------------------------------- index
 struct IndexView {
   const uint64_t* keys;      // n_buckets * 16 slots, kEmptyKey = free

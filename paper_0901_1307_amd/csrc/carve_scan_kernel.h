@@ -75,10 +75,20 @@ struct ManyImages {
 // Persistent grid over the tile space: wave q takes chunks q, q + W, ... of
 // `chunk` consecutive tiles (W = waves in the grid). 4 waves per SIMD (at
 // most 128 VGPRs): the more waves, the more sector loads in flight per CU.
-template <int kMode, class Src>
+// kSig: kSigDjb2 (wt = the digit-plane weight table) or kSigCrc64 (wt = the
+// slicing tables, copied into LDS first).
+template <int kMode, int kSig, class Src>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(
     Src src, uint32_t chunk, IndexView ix, uint64_t wt, uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
+  LdsTable crc_tab = nullptr;
+  if constexpr (kSig == kSigCrc64) {
+    __shared__ __attribute__((aligned(16))) uint64_t tabs[8 * 256];
+    const u64x2* g = (const u64x2*)wt;
+    for (uint32_t i = threadIdx.x; i < 8 * 256 / 2; i += kScanThreads) ((u64x2*)tabs)[i] = g[i];
+    __syncthreads();   // before any wave of the block can leave
+    crc_tab = (LdsTable)tabs;
+  }
   const uint32_t w = threadIdx.x / kWave;
   const uint32_t l = lane_id();
   uint8_t* my = lds + w * kTileLds;
@@ -101,10 +111,12 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
     // The next tile's first phase is loaded while this tile's last one is
     // hashed. Unconditionally (the last tile reloads itself): a load under a
     // branch would make the compiler wait for every load at the join.
-    const uint64_t h = tile_signature_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, wt, A, B,
-                                                      [&](PhaseRegs& R) {
-                                                        load_phase<true>(ContiguousRows{tn.base, tn.n_valid}, 0, R);
-                                                      });
+    auto prefetch = [&](PhaseRegs& R) { load_phase<true>(ContiguousRows{tn.base, tn.n_valid}, 0, R); };
+    uint64_t h;
+    if constexpr (kSig == kSigCrc64)
+      h = tile_crc_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, crc_tab, A, B, prefetch);
+    else
+      h = tile_signature_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, wt, A, B, prefetch);
     if constexpr (kMode == kFlags) {
       const uint32_t tau = (tr.tau_first + l) & (kClusterSectors - 1);
       uint64_t hits = tile_probe(ix, h, tau, tr.any_tau != 0, hit_slot + g * kTileSectors);

@@ -21,9 +21,10 @@ def gpu_flags_and_matches(index, image: torch.Tensor, tau0=0, any_tau=False, sca
     return flags, matches, sc
 
 
-def oracle_flags_and_matches(masters_host, offsets, image_host, tau0=0, any_tau=False, threads=None):
+def oracle_flags_and_matches(masters_host, offsets, image_host, tau0=0, any_tau=False, threads=None,
+                             sig_kind=oracle.SIG_DJB2):
     th = threads or oracle.default_threads()
-    ix = oracle.Index(masters_host, offsets, threads=th)
+    ix = oracle.Index(masters_host, offsets, threads=th, sig_kind=sig_kind)
     flags = ix.flag_image(image_host, tau0, any_tau, threads=th)
     matches = ix.confirm_image(image_host, flags, tau0, any_tau)
     return flags, matches
