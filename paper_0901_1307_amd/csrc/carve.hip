@@ -530,21 +530,25 @@ struct HostBuf {
 
 uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-// Device address, on the current device, of the table the scan kernel of a
-// signature kind reads: djb2's digit-plane weights or the CRC's slicing
-// tables (0 on failure).
-uint64_t sig_table(uint32_t kind) {
-  static uint64_t ptr[64][2] = {};
+// Device address, on the current device, of djb2's digit-plane weight table
+// (0 on failure).
+uint64_t weight_table() {
+  static uint64_t ptr[64] = {};
   int dev = 0;
-  if (kind > 1 || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (!ptr[dev][kind]) {
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (!ptr[dev]) {
     void* p = nullptr;
-    const hipError_t e = kind == CARVE_SIG_CRC64_ISO ? hipGetSymbolAddress(&p, HIP_SYMBOL(g_crc_tables))
-                                                     : hipGetSymbolAddress(&p, HIP_SYMBOL(g_weights));
-    if (e != hipSuccess) return 0;
-    ptr[dev][kind] = (uint64_t)(uintptr_t)p;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_weights)) != hipSuccess) return 0;
+    ptr[dev] = (uint64_t)(uintptr_t)p;
   }
-  return ptr[dev][kind];
+  return ptr[dev];
+}
+
+// The table argument of the scan kernel for a signature kind: djb2's weights;
+// the CRC needs none. Returns false when the table is unavailable.
+bool sig_table(uint32_t kind, uint64_t* wt) {
+  *wt = kind == CARVE_SIG_CRC64_ISO ? 0 : weight_table();
+  return kind == CARVE_SIG_CRC64_ISO || *wt != 0;
 }
 
 // One scan kernel launch for the signature kind chosen at run time.
@@ -623,7 +627,7 @@ struct carve_index {
   uint32_t zero_sig_mask = 0;
   uint64_t n_unique = 0;
   uint64_t n_overflow = 0;
-  uint64_t weights = 0;     // address of the table of the signature kind (sig_table)
+  uint64_t weights = 0;     // djb2's weight table (0 for the CRC)
   uint32_t sig_kind = CARVE_SIG_DJB2_64;
   uint32_t log2_bloom_words = 0;
   carve_scan_config cfg{};
@@ -873,8 +877,8 @@ extern "C" int sector_signatures_kind(uint32_t sig_kind, const void* sectors, ui
   if (!sectors || !sigs) return fail(CARVE_EINVAL, "sector_signatures: null pointer");
   if ((uintptr_t)sectors % 16) return fail(CARVE_EINVAL, "sector_signatures: sectors not 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const uint64_t wt = sig_table(sig_kind);
-  if (!wt) return fail(CARVE_EDEVICE, "sector_signatures: signature table unavailable");
+  uint64_t wt = 0;
+  if (!sig_table(sig_kind, &wt)) return fail(CARVE_EDEVICE, "sector_signatures: weight table unavailable");
   const OneImage src{ImageDesc{(const uint8_t*)sectors, n_sectors, 0, 0, 0}};
   return launch_k_scan<kSigs>(sig_kind, src, cdiv(n_sectors, kTileSectors), 1, 0, IndexView{}, wt, sigs, nullptr, s);
 }
@@ -937,8 +941,8 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   ix->n_files = n_files;
   ix->masters = (const uint8_t*)master_sectors;
   ix->sig_kind = p.sig_kind;
-  ix->weights = sig_table(p.sig_kind);
-  if (!ix->weights) return bail(fail(CARVE_EDEVICE, "build_master_index: signature table unavailable"));
+  if (!sig_table(p.sig_kind, &ix->weights))
+    return bail(fail(CARVE_EDEVICE, "build_master_index: weight table unavailable"));
   uint32_t lb = 1;
   while (((uint64_t)kBucketSlots << lb) * p.max_load < (double)n_masters) ++lb;
   if (lb > 27) return bail(fail(CARVE_EUNSUPPORTED, "build_master_index: table too large"));   // slots fit 32 bits

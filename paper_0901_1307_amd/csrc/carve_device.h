@@ -225,49 +225,36 @@ __device__ __forceinline__ uint64_t tile_signature_pipelined(const Rows& rows, u
 // ---------------------------------------------------------------- CRC-64
 // The other signature of Section 2.1: a 64-bit CRC, read as CRC-64/GO-ISO
 // (generator x^64 + x^4 + x^3 + x + 1, bytes entering least significant bit
-// first, register preset to all ones, result complemented). Computed by
-// slicing by 8: x = crc ^ (next 8 bytes, little-endian); the new register is
-// the xor of T_j[byte j of x], where T_j[v] is the register's change when
-// byte v is followed by 7 - j more bytes (T_0 is the one-byte step). The 16 KB
-// of tables are copied into LDS by each block; lookups are then ds_read_b64.
+// first, register preset to all ones, result complemented).
+//
+// No table: this generator lets the register absorb a 32-bit word with shifts
+// and xors. In the right-shifting (reflected) register a feedback term enters
+// at bit 59 or above, so within any 32 steps the bits tested are exactly the
+// input bits. Absorbing the little-endian word d (bytes in address order) is
+// then, with x = crc ^ d and u = x mod 2^32,
+//   crc' = (x >> 32) ^ (u << 28) ^ (u << 29) ^ (u << 31) ^ (u << 32),
+// x >> 32 xor the carry-less product of u with the generator's terms below x^64
+// (0x1B: bits 0, 1, 3, 4), placed 28 bits up. About 11 VALU operations per word.
 enum : int { kSigDjb2 = 0, kSigCrc64 = 1 };   // the values of carve_sig_kind
 
-constexpr uint64_t reflect64(uint64_t x) {
-  uint64_t r = 0;
-  for (int i = 0; i < 64; ++i) r |= ((x >> i) & 1ull) << (63 - i);
-  return r;
+// The same, on the register's 32-bit halves (full-rate 32-bit shifts):
+// the low half becomes hi ^ u<<28 ^ u<<29 ^ u<<31, the high half
+// u ^ u>>1 ^ u>>3 ^ u>>4 (the bits the 64-bit shifts carry across).
+// a ^ b ^ c in one instruction: gfx950's three-input bit operation with the
+// truth table of xor3 (0x96: set where an odd number of inputs is set).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
-constexpr uint64_t kCrcPoly = 0x1Bull;                        // generator without x^64, bit k = x^k
-constexpr uint64_t kCrcPolyReflected = reflect64(kCrcPoly);   // as the right-shifting register sees it
 
-struct CrcTables {
-  uint64_t t[8][256];
-};
-constexpr CrcTables make_crc_tables() {
-  CrcTables c{};
-  for (uint32_t v = 0; v < 256; ++v) {
-    uint64_t r = v;
-    for (int b = 0; b < 8; ++b) r = (r & 1ull) ? (r >> 1) ^ kCrcPolyReflected : r >> 1;
-    c.t[0][v] = r;
-  }
-  for (int j = 1; j < 8; ++j)
-    for (uint32_t v = 0; v < 256; ++v) c.t[j][v] = (c.t[j - 1][v] >> 8) ^ c.t[0][c.t[j - 1][v] & 0xFFu];
-  return c;
-}
-__device__ CrcTables g_crc_tables = make_crc_tables();
-
-typedef const __attribute__((address_space(3))) uint64_t* LdsTable;
-
-__device__ __forceinline__ uint64_t crc_step8(uint64_t crc, uint32_t w_lo, uint32_t w_hi, LdsTable tab) {
-  const uint32_t lo = (uint32_t)crc ^ w_lo, hi = (uint32_t)(crc >> 32) ^ w_hi;
-  return tab[7 * 256 + (lo & 0xFFu)] ^ tab[6 * 256 + ((lo >> 8) & 0xFFu)] ^ tab[5 * 256 + ((lo >> 16) & 0xFFu)] ^
-         tab[4 * 256 + (lo >> 24)] ^ tab[3 * 256 + (hi & 0xFFu)] ^ tab[2 * 256 + ((hi >> 8) & 0xFFu)] ^
-         tab[1 * 256 + ((hi >> 16) & 0xFFu)] ^ tab[0 * 256 + (hi >> 24)];
+__device__ __forceinline__ void crc_word(uint32_t& lo, uint32_t& hi, uint32_t d) {
+  const uint32_t u = lo ^ d;
+  lo = xor3(hi, u << 28, u << 29) ^ (u << 31);
+  hi = xor3(u, u >> 1, u >> 3) ^ (u >> 4);
 }
 
 // Stage a phase through this wave's LDS area, then run lane l's register over
 // the 128 bytes of its sector, in address order.
-__device__ __forceinline__ void crc_phase(const PhaseRegs& r, uint8_t* lds, LdsTable tab, uint64_t& crc) {
+__device__ __forceinline__ void crc_phase(const PhaseRegs& r, uint8_t* lds, uint32_t& lo, uint32_t& hi) {
   __builtin_amdgcn_sched_barrier(0);
   const uint32_t l = lane_id();
   const uint32_t col = (l & 7u) * 16u;
@@ -277,28 +264,28 @@ __device__ __forceinline__ void crc_phase(const PhaseRegs& r, uint8_t* lds, LdsT
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const u32x4 x4 = *(const u32x4*)(lds + l * kRowPitch + c * 16);
-    crc = crc_step8(crc, x4[0], x4[1], tab);
-    crc = crc_step8(crc, x4[2], x4[3], tab);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) crc_word(lo, hi, x4[k]);
   }
-  asm volatile("" : "+v"(crc));
+  asm volatile("" : "+v"(lo), "+v"(hi));
   wave_sync_lds();
   __builtin_amdgcn_sched_barrier(0);
 }
 
 // CRC-64 of every sector of a tile, with the same load pipeline as the djb2 path.
 template <bool kNonTemporal, class Rows, class Prefetch>
-__device__ __forceinline__ uint64_t tile_crc_pipelined(const Rows& rows, uint8_t* lds, LdsTable tab, PhaseRegs& A,
-                                                       PhaseRegs& B, Prefetch&& prefetch) {
-  uint64_t crc = ~0ull;
+__device__ __forceinline__ uint64_t tile_crc_pipelined(const Rows& rows, uint8_t* lds, PhaseRegs& A, PhaseRegs& B,
+                                                       Prefetch&& prefetch) {
+  uint32_t lo = ~0u, hi = ~0u;   // preset: all ones
   load_phase<kNonTemporal>(rows, 1, B);
-  crc_phase(A, lds, tab, crc);
+  crc_phase(A, lds, lo, hi);
   load_phase<kNonTemporal>(rows, 2, A);
-  crc_phase(B, lds, tab, crc);
+  crc_phase(B, lds, lo, hi);
   load_phase<kNonTemporal>(rows, 3, B);
-  crc_phase(A, lds, tab, crc);
+  crc_phase(A, lds, lo, hi);
   prefetch(A);
-  crc_phase(B, lds, tab, crc);
-  return ~crc;
+  crc_phase(B, lds, lo, hi);
+  return ~(((uint64_t)hi << 32) | lo);   // complemented
 }
 
 // ---------------------------------------------------------------- index

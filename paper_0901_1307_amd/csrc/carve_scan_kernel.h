@@ -75,20 +75,12 @@ struct ManyImages {
 // Persistent grid over the tile space: wave q takes chunks q, q + W, ... of
 // `chunk` consecutive tiles (W = waves in the grid). 4 waves per SIMD (at
 // most 128 VGPRs): the more waves, the more sector loads in flight per CU.
-// kSig: kSigDjb2 (wt = the digit-plane weight table) or kSigCrc64 (wt = the
-// slicing tables, copied into LDS first).
+// kSig: kSigDjb2 (wt = the digit-plane weight table) or kSigCrc64 (no table;
+// wt unused).
 template <int kMode, int kSig, class Src>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(
     Src src, uint32_t chunk, IndexView ix, uint64_t wt, uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
-  LdsTable crc_tab = nullptr;
-  if constexpr (kSig == kSigCrc64) {
-    __shared__ __attribute__((aligned(16))) uint64_t tabs[8 * 256];
-    const u64x2* g = (const u64x2*)wt;
-    for (uint32_t i = threadIdx.x; i < 8 * 256 / 2; i += kScanThreads) ((u64x2*)tabs)[i] = g[i];
-    __syncthreads();   // before any wave of the block can leave
-    crc_tab = (LdsTable)tabs;
-  }
   const uint32_t w = threadIdx.x / kWave;
   const uint32_t l = lane_id();
   uint8_t* my = lds + w * kTileLds;
@@ -114,7 +106,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
     auto prefetch = [&](PhaseRegs& R) { load_phase<true>(ContiguousRows{tn.base, tn.n_valid}, 0, R); };
     uint64_t h;
     if constexpr (kSig == kSigCrc64)
-      h = tile_crc_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, crc_tab, A, B, prefetch);
+      h = tile_crc_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, A, B, prefetch);
     else
       h = tile_signature_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, wt, A, B, prefetch);
     if constexpr (kMode == kFlags) {
