@@ -60,13 +60,26 @@ typedef enum {
   CARVE_TAU_ANY = 1          /* sector j matches a master sector at any cluster position */
 } carve_tau_mode;
 
+/* How a scan looks a signature up (Section 3.2, Eq. (3), and the occupancy
+ * study of Section 4). Every layout gives the same results. */
+typedef enum {
+  CARVE_LAYOUT_BUCKETED = 0, /* linear probing over 128-byte buckets of 16 keys, home bucket from a
+                                multiplicative hash of the signature (the default) */
+  CARVE_LAYOUT_LINEAR = 1,   /* the paper's table: home slot = the w low bits of the signature,
+                                linear probing slot by slot (Eq. (3)) */
+  CARVE_LAYOUT_SORTED = 2    /* the distinct signatures sorted, binary search */
+} carve_index_layout;
+
 typedef struct {
   uint32_t sig_kind;           /* carve_sig_kind of master and disk sectors; 0 = djb2-64 */
-  float max_load;              /* hash-table load factor ceiling in (0, 0.9]; 0 = 0.5 */
+  float max_load;              /* load factor ceiling of the probed table in (0, 0.9]; 0 = 0.5
+                                  (bucketed: keys per slot; linear: distinct signatures per slot;
+                                  sorted: unused) */
   uint32_t bloom_bits_per_key; /* prefilter in front of the table: 0 = automatic (at least 4 bits per
                                   distinct signature, then as many as a 4 MiB filter and 16 bits allow),
                                   CARVE_BLOOM_OFF = none, else 4..64 bits per signature */
-  uint32_t reserved[5];        /* must be zero */
+  uint32_t layout;             /* carve_index_layout; 0 = bucketed */
+  uint32_t reserved[4];        /* must be zero */
 } carve_index_params;
 
 #define CARVE_BLOOM_OFF 0xFFFFFFFFu

@@ -20,6 +20,7 @@ SECTOR = 512
 CARVE_OK, CARVE_EINVAL, CARVE_ENOMEM, CARVE_ETRUNC, CARVE_EDEVICE, CARVE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CARVE_SIG_DJB2_64, CARVE_SIG_CRC64_ISO = 0, 1
 CARVE_TAU_PER_CLUSTER, CARVE_TAU_ANY = 0, 1
+CARVE_LAYOUT_BUCKETED, CARVE_LAYOUT_LINEAR, CARVE_LAYOUT_SORTED = 0, 1, 2
 
 MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4")])
 BATCH_MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4"),
@@ -50,7 +51,7 @@ CARVE_ALL_IMAGES = 0xFFFFFFFF
 
 class _IndexParams(ctypes.Structure):
     _fields_ = [("sig_kind", ctypes.c_uint32), ("max_load", ctypes.c_float), ("bloom_bits_per_key", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 5)]
+                ("layout", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
 
 
 class _ScanConfig(ctypes.Structure):
@@ -287,12 +288,15 @@ class Batch:
 
 
 def build_master_index(master_sectors: torch.Tensor, file_sector_offsets: Sequence[int], max_load: float = 0.0,
-                       bloom_bits_per_key: int = 0, stream=None, sig_kind: int = CARVE_SIG_DJB2_64) -> Index:
+                       bloom_bits_per_key: int = 0, stream=None, sig_kind: int = CARVE_SIG_DJB2_64,
+                       layout: int = CARVE_LAYOUT_BUCKETED) -> Index:
     """Index of packed master sectors (uint8 device tensor, file after file).
 
     bloom_bits_per_key: 0 = automatic, CARVE_BLOOM_OFF = no prefilter.
     sig_kind: CARVE_SIG_DJB2_64 or CARVE_SIG_CRC64_ISO (every scan with this
-    index uses the same signature)."""
+    index uses the same signature). layout: CARVE_LAYOUT_BUCKETED, _LINEAR
+    (the paper's Eq. (3) table) or _SORTED (binary search); max_load sizes the
+    probed table."""
     lib = load_library()
     m = _dev_u8(master_sectors, "master_sectors")
     off = np.ascontiguousarray(file_sector_offsets, dtype=np.uint64)
@@ -300,7 +304,7 @@ def build_master_index(master_sectors: torch.Tensor, file_sector_offsets: Sequen
         raise ValueError("file_sector_offsets needs at least one entry")
     if m.numel() != int(off[-1]) * SECTOR:
         raise ValueError("master_sectors size does not match file_sector_offsets[-1] sectors")
-    p = _IndexParams(int(sig_kind), float(max_load), int(bloom_bits_per_key))
+    p = _IndexParams(int(sig_kind), float(max_load), int(bloom_bits_per_key), int(layout))
     h = ctypes.c_void_p()
     _check(lib.build_master_index(m.data_ptr() if m.numel() else None, off.ctypes.data, off.size - 1,
                                   ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))

@@ -28,6 +28,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "../../include/carve.h"
 #include "carve_device.h"
 #include "carve_internal.h"
@@ -281,6 +283,38 @@ __global__ void k_bloom_build(const uint64_t* __restrict__ keys, uint64_t n_slot
   uint64_t bits;
   bloom_place(h, log2_words, &w, &bits);
   atomicOr((unsigned long long*)(bloom + w), (unsigned long long)bits);
+}
+
+// Other probe layouts. The distinct signatures of the table with their slots
+// (any order).
+__global__ void k_occupied(const uint64_t* __restrict__ keys, uint64_t n_slots, uint64_t* __restrict__ out_keys,
+                           uint32_t* __restrict__ out_slots, unsigned long long* __restrict__ count) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_slots || keys[t] == kEmptyKey) return;
+  const unsigned long long i = atomicAdd(count, 1ull);
+  out_keys[i] = keys[t];
+  out_slots[i] = (uint32_t)t;
+}
+
+// The paper's table (Eq. (3)): a key goes to the slot given by its w low bits,
+// or the first free slot after it. Keys are distinct, so a slot taken by
+// another key only means: try the next one.
+__global__ void k_insert_linear(const uint64_t* __restrict__ in_keys, const uint32_t* __restrict__ in_slots, uint64_t n,
+                                uint64_t* lin_keys, uint32_t* __restrict__ lin_slot, uint32_t log2_lin) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const uint64_t h = in_keys[t];
+  const uint64_t mask = (1ull << log2_lin) - 1ull;
+  uint64_t s = h & mask;
+  for (uint64_t it = 0; it <= mask; ++it) {
+    const unsigned long long prev =
+        atomicCAS((unsigned long long*)&lin_keys[s], (unsigned long long)kEmptyKey, (unsigned long long)h);
+    if (prev == kEmptyKey) {
+      lin_slot[s] = in_slots[t];
+      return;
+    }
+    s = (s + 1) & mask;
+  }
 }
 
 __global__ void k_narrow_masks(const uint32_t* __restrict__ m32, uint64_t n, uint8_t* __restrict__ m8) {
@@ -554,7 +588,8 @@ bool sig_table(uint32_t kind, uint64_t* wt) {
 // One scan kernel launch for the signature kind chosen at run time.
 template <int kMode, class Src>
 int launch_k_scan(uint32_t kind, const Src& src, uint64_t n_tiles, uint32_t chunk, uint32_t per_cu_cap,
-                  const IndexView& ix, uint64_t wt, uint64_t* out, uint32_t* hit_slot, hipStream_t s);
+                  const IndexView& ix, uint64_t wt, uint64_t* out, uint32_t* hit_slot, hipStream_t s,
+                  uint32_t layout = CARVE_LAYOUT_BUCKETED);
 
 int device_cus() {
   static int cus = 0;
@@ -599,17 +634,34 @@ int resident_grid(Kernel kernel, int threads, uint64_t want, uint32_t per_cu_cap
   return (int)(want < cap ? (want ? want : 1) : cap);
 }
 
+template <int kMode, int kSig, int kLayout, class Src>
+void launch_k_scan_as(const Src& src, uint64_t want, uint32_t chunk, uint32_t per_cu_cap, const IndexView& ix,
+                      uint64_t wt, uint64_t* out, uint32_t* hit_slot, hipStream_t s) {
+  const int grid = resident_grid(k_scan<kMode, kSig, Src, kLayout>, kScanThreads, want, per_cu_cap);
+  k_scan<kMode, kSig, Src, kLayout><<<grid, kScanThreads, 0, s>>>(src, chunk, ix, wt, out, hit_slot);
+}
+
+template <int kMode, int kSig, class Src>
+void launch_k_scan_sig(uint32_t layout, const Src& src, uint64_t want, uint32_t chunk, uint32_t per_cu_cap,
+                       const IndexView& ix, uint64_t wt, uint64_t* out, uint32_t* hit_slot, hipStream_t s) {
+  if constexpr (kMode == kFlags) {
+    if (layout == CARVE_LAYOUT_LINEAR)
+      return launch_k_scan_as<kMode, kSig, kLayoutLinear>(src, want, chunk, per_cu_cap, ix, wt, out, hit_slot, s);
+    if (layout == CARVE_LAYOUT_SORTED)
+      return launch_k_scan_as<kMode, kSig, kLayoutSorted>(src, want, chunk, per_cu_cap, ix, wt, out, hit_slot, s);
+  }
+  launch_k_scan_as<kMode, kSig, kLayoutBucketed>(src, want, chunk, per_cu_cap, ix, wt, out, hit_slot, s);
+}
+
 template <int kMode, class Src>
 int launch_k_scan(uint32_t kind, const Src& src, uint64_t n_tiles, uint32_t chunk, uint32_t per_cu_cap,
-                  const IndexView& ix, uint64_t wt, uint64_t* out, uint32_t* hit_slot, hipStream_t s) {
+                  const IndexView& ix, uint64_t wt, uint64_t* out, uint32_t* hit_slot, hipStream_t s,
+                  uint32_t layout) {
   const uint64_t want = cdiv(cdiv(n_tiles, chunk), kScanWaves);
-  if (kind == CARVE_SIG_CRC64_ISO) {
-    const int grid = resident_grid(k_scan<kMode, kSigCrc64, Src>, kScanThreads, want, per_cu_cap);
-    k_scan<kMode, kSigCrc64, Src><<<grid, kScanThreads, 0, s>>>(src, chunk, ix, wt, out, hit_slot);
-  } else {
-    const int grid = resident_grid(k_scan<kMode, kSigDjb2, Src>, kScanThreads, want, per_cu_cap);
-    k_scan<kMode, kSigDjb2, Src><<<grid, kScanThreads, 0, s>>>(src, chunk, ix, wt, out, hit_slot);
-  }
+  if (kind == CARVE_SIG_CRC64_ISO)
+    launch_k_scan_sig<kMode, kSigCrc64>(layout, src, want, chunk, per_cu_cap, ix, wt, out, hit_slot, s);
+  else
+    launch_k_scan_sig<kMode, kSigDjb2>(layout, src, want, chunk, per_cu_cap, ix, wt, out, hit_slot, s);
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
@@ -632,9 +684,14 @@ struct carve_index {
   uint32_t log2_bloom_words = 0;
   carve_scan_config cfg{};
   DevBuf keys, tau_mask, cand_off, cand, m_file, m_k, bloom;   // tau_mask: one byte per slot
+  uint32_t layout = CARVE_LAYOUT_BUCKETED;
+  DevBuf lin_keys, lin_slot, sorted_keys, sorted_slot;          // probe structures of the other layouts
+  uint32_t log2_lin = 0, n_sorted = 0;
   IndexView view() const {
     return IndexView{keys.as<uint64_t>(), tau_mask.as<uint8_t>(), bloom.bytes ? bloom.as<uint64_t>() : nullptr,
-                     log2_buckets, log2_bloom_words, zero_sig_mask, (uint32_t)n_slots};
+                     log2_buckets, log2_bloom_words, zero_sig_mask, (uint32_t)n_slots,
+                     lin_keys.as<uint64_t>(), lin_slot.as<uint32_t>(), log2_lin, n_sorted,
+                     sorted_keys.as<uint64_t>(), sorted_slot.as<uint32_t>()};
   }
   ConfirmView cview() const {
     return ConfirmView{cand_off.as<uint32_t>(), cand.as<uint32_t>(), m_file.as<uint32_t>(), m_k.as<uint32_t>(),
@@ -723,7 +780,8 @@ int launch_scan(carve_scan* sc, const Src& src) {
   if (sc->timing) HIP_TRY(hipEventRecord(sc->ev0, s));
   const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
   CARVE_TRY(launch_k_scan<kFlags>(idx->sig_kind, src, n_words, chunk, idx->cfg.blocks_per_cu, idx->view(),
-                                   idx->weights, sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>(), s));
+                                   idx->weights, sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>(), s,
+                                   idx->layout));
   if (sc->timing) {
     HIP_TRY(hipEventRecord(sc->ev1, s));
     sc->timed = true;
@@ -896,8 +954,71 @@ extern "C" void free_index(carve_index* idx) {
   idx->m_file.release();
   idx->m_k.release();
   idx->bloom.release();
+  idx->lin_keys.release();
+  idx->lin_slot.release();
+  idx->sorted_keys.release();
+  idx->sorted_slot.release();
   delete idx;
 }
+
+namespace {
+// The probe structure of the linear or sorted layout, from the n_keys
+// distinct signatures held in the finished table's slots (signature 0 has no
+// slot). Built even when there are none, so that a probe always finds a table.
+int build_layout(carve_index* ix, const carve_index_params& p, uint64_t n_keys, hipStream_t s) {
+  struct Temps {
+    DevBuf list_keys, list_slots, counter, tmp;
+    ~Temps() {
+      list_keys.release();
+      list_slots.release();
+      counter.release();
+      tmp.release();
+    }
+  } t;
+  DevBuf &list_keys = t.list_keys, &list_slots = t.list_slots, &counter = t.counter, &tmp = t.tmp;
+  CARVE_TRY(list_keys.reserve((n_keys ? n_keys : 1) * 8));
+  CARVE_TRY(list_slots.reserve((n_keys ? n_keys : 1) * 4));
+  CARVE_TRY(counter.reserve(8));
+  HIP_TRY(hipMemsetAsync(counter.p, 0, 8, s));
+  k_occupied<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, list_keys.as<uint64_t>(),
+                                                    list_slots.as<uint32_t>(),
+                                                    (unsigned long long*)counter.as<uint64_t>());
+  HIP_TRY(hipGetLastError());
+  uint64_t listed = 0;
+  HIP_TRY(hipMemcpyAsync(&listed, counter.p, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (listed != n_keys)
+    return fail(CARVE_EDEVICE, "build_master_index: %llu table keys listed, %llu expected", (unsigned long long)listed,
+                (unsigned long long)n_keys);
+  if (p.layout == CARVE_LAYOUT_LINEAR) {
+    uint32_t w = 1;
+    while ((double)(1ull << w) * p.max_load < (double)n_keys) ++w;
+    if (w > 32) return fail(CARVE_EUNSUPPORTED, "build_master_index: linear table too large");
+    CARVE_TRY(ix->lin_keys.reserve(8ull << w));
+    CARVE_TRY(ix->lin_slot.reserve(4ull << w));
+    HIP_TRY(hipMemsetAsync(ix->lin_keys.p, 0, 8ull << w, s));
+    ix->log2_lin = w;
+    if (n_keys)
+      k_insert_linear<<<cdiv(n_keys, 256), 256, 0, s>>>(list_keys.as<uint64_t>(), list_slots.as<uint32_t>(), n_keys,
+                                                        ix->lin_keys.as<uint64_t>(), ix->lin_slot.as<uint32_t>(), w);
+    HIP_TRY(hipGetLastError());
+  } else if (n_keys) {
+    CARVE_TRY(ix->sorted_keys.reserve(n_keys * 8));
+    CARVE_TRY(ix->sorted_slot.reserve(n_keys * 4));
+    size_t bytes = 0;
+    HIP_TRY(rocprim::radix_sort_pairs(nullptr, bytes, list_keys.as<uint64_t>(), ix->sorted_keys.as<uint64_t>(),
+                                      list_slots.as<uint32_t>(), ix->sorted_slot.as<uint32_t>(), (size_t)n_keys, 0,
+                                      64, s));
+    CARVE_TRY(tmp.reserve(bytes));
+    HIP_TRY(rocprim::radix_sort_pairs(tmp.p, bytes, list_keys.as<uint64_t>(), ix->sorted_keys.as<uint64_t>(),
+                                      list_slots.as<uint32_t>(), ix->sorted_slot.as<uint32_t>(), (size_t)n_keys, 0,
+                                      64, s));
+    ix->n_sorted = (uint32_t)n_keys;
+  }
+  HIP_TRY(hipStreamSynchronize(s));   // before the temporaries are freed
+  return CARVE_OK;
+}
+}  // namespace
 
 extern "C" int build_master_index(const void* master_sectors, const uint64_t* file_sector_offsets, uint32_t n_files,
                                   const carve_index_params* params, void* stream, carve_index** out) {
@@ -915,6 +1036,7 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   if (p.sig_kind != CARVE_SIG_DJB2_64 && p.sig_kind != CARVE_SIG_CRC64_ISO)
     return fail(CARVE_EUNSUPPORTED, "build_master_index: unknown sig_kind %u", p.sig_kind);
   if (!(p.max_load > 0.f && p.max_load <= 0.9f)) return fail(CARVE_EINVAL, "build_master_index: max_load out of (0, 0.9]");
+  if (p.layout > CARVE_LAYOUT_SORTED) return fail(CARVE_EINVAL, "build_master_index: unknown layout %u", p.layout);
   if (p.bloom_bits_per_key != 0 && p.bloom_bits_per_key != CARVE_BLOOM_OFF &&
       (p.bloom_bits_per_key < 4 || p.bloom_bits_per_key > 64))
     return fail(CARVE_EINVAL, "build_master_index: bloom_bits_per_key %u out of 4..64", p.bloom_bits_per_key);
@@ -943,8 +1065,12 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   ix->sig_kind = p.sig_kind;
   if (!sig_table(p.sig_kind, &ix->weights))
     return bail(fail(CARVE_EDEVICE, "build_master_index: weight table unavailable"));
+  ix->layout = p.layout;
+  // the bucketed table holds the candidate lists in every layout; max_load
+  // sizes the layout that is probed
+  const float bucket_load = p.layout == CARVE_LAYOUT_BUCKETED ? p.max_load : 0.5f;
   uint32_t lb = 1;
-  while (((uint64_t)kBucketSlots << lb) * p.max_load < (double)n_masters) ++lb;
+  while (((uint64_t)kBucketSlots << lb) * bucket_load < (double)n_masters) ++lb;
   if (lb > 27) return bail(fail(CARVE_EUNSUPPORTED, "build_master_index: table too large"));   // slots fit 32 bits
   ix->log2_buckets = lb;
   ix->n_slots = (uint64_t)kBucketSlots << lb;
@@ -1060,6 +1186,10 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
         return bail2(fail(CARVE_EDEVICE, "build_master_index: bloom build failed"));
     }
   }
+  if (p.layout != CARVE_LAYOUT_BUCKETED) {
+    // the distinct signatures counted above include signature 0, which has no slot
+    if ((rc = build_layout(ix, p, h_unique - (zmask ? 1 : 0), s))) return bail2(rc);
+  }
   cleanup();
   *out = ix;
   return CARVE_OK;
@@ -1072,7 +1202,8 @@ extern "C" int index_stats(const carve_index* idx, carve_index_stats* out) {
   out->n_buckets = 1ull << idx->log2_buckets;
   out->n_overflow_keys = idx->n_overflow;
   out->device_bytes = idx->keys.bytes + idx->tau_mask.bytes + idx->cand_off.bytes + idx->cand.bytes +
-                      idx->m_file.bytes + idx->m_k.bytes + idx->bloom.bytes;
+                      idx->m_file.bytes + idx->m_k.bytes + idx->bloom.bytes + idx->lin_keys.bytes +
+                      idx->lin_slot.bytes + idx->sorted_keys.bytes + idx->sorted_slot.bytes;
   out->bloom_bytes = idx->bloom.bytes;
   return CARVE_OK;
 }

@@ -297,7 +297,17 @@ struct IndexView {
   uint32_t log2_bloom_words;
   uint32_t zero_sig_mask;    // positions of signature 0, which has no slot in the table
   uint32_t zero_slot;        // candidate-list id of signature 0 (= number of table slots)
+  // other probe layouts, mapping a signature to its slot of the table above
+  const uint64_t* lin_keys;  // linear probing per slot from the signature's low bits: 2^log2_lin keys
+  const uint32_t* lin_slot;  //   and the table slot of each
+  uint32_t log2_lin;
+  uint32_t n_sorted;         // sorted distinct signatures (binary search)
+  const uint64_t* sorted_keys;
+  const uint32_t* sorted_slot;
 };
+
+// Probe layouts (the values of carve_index_layout).
+enum : int { kLayoutBucketed = 0, kLayoutLinear = 1, kLayoutSorted = 2 };
 
 // Register-blocked Bloom filter: a key owns one 64-bit word and sets 4 of
 // its bits. Word and bit positions come from the high half of a second
@@ -336,6 +346,42 @@ __device__ __forceinline__ int64_t find_slot(const IndexView& ix, uint64_t h) {
   return -1;
 }
 
+// The paper's layout (Eq. (3)): home slot = the w low bits of the signature,
+// then the next slots in turn until the key or a free slot. Returns the
+// table slot or -1.
+__device__ __forceinline__ int64_t find_slot_linear(const IndexView& ix, uint64_t h) {
+  const uint64_t mask = (1ull << ix.log2_lin) - 1ull;
+  uint64_t s = h & mask;
+  for (uint64_t it = 0; it <= mask; ++it) {
+    const uint64_t k = ix.lin_keys[s];
+    if (k == h) return (int64_t)ix.lin_slot[s];
+    if (k == kEmptyKey) return -1;
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+// Sorted distinct signatures: lower bound by halving with no data-dependent
+// branch (every lane takes the same ceil(log2 n) steps). Returns the table
+// slot or -1.
+__device__ __forceinline__ int64_t find_slot_sorted(const IndexView& ix, uint64_t h) {
+  uint64_t base = 0, n = ix.n_sorted;
+  if (n == 0) return -1;
+  while (n > 1) {
+    const uint64_t half = n >> 1;
+    base = ix.sorted_keys[base + half] <= h ? base + half : base;
+    n -= half;
+  }
+  return ix.sorted_keys[base] == h ? (int64_t)ix.sorted_slot[base] : -1;
+}
+
+template <int kLayout>
+__device__ __forceinline__ int64_t find_slot_in(const IndexView& ix, uint64_t h) {
+  if constexpr (kLayout == kLayoutLinear) return find_slot_linear(ix, h);
+  else if constexpr (kLayout == kLayoutSorted) return find_slot_sorted(ix, h);
+  else return find_slot(ix, h);
+}
+
 __device__ __forceinline__ bool tau_ok(uint32_t mask, uint32_t tau, bool any_tau) {
   return any_tau ? (mask != 0) : (((mask >> tau) & 1u) != 0);
 }
@@ -349,20 +395,26 @@ __device__ __forceinline__ bool tau_ok(uint32_t mask, uint32_t tau, bool any_tau
 // one memory latency. Returns the tile's hit mask (bit l = sector l); tau is
 // this lane's cluster position. For each hit, the slot that matched is
 // stored in slot_out[sector] (the candidate list that confirmation walks).
+// The linear and sorted layouts probe lane by lane, after the filter if there
+// is one.
+template <int kLayout = kLayoutBucketed>
 __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, uint32_t tau, bool any_tau,
                                                uint32_t* __restrict__ slot_out) {
   const uint32_t l = lane_id();
   // signature 0 cannot be stored in the table (it marks free slots)
   const bool ok_zero = (h == kEmptyKey) && tau_ok(ix.zero_sig_mask, tau, any_tau);
   if (ok_zero) slot_out[l] = ix.zero_slot;
-  if (ix.bloom) {
-    uint32_t w;
-    uint64_t bits;
-    bloom_place(h, ix.log2_bloom_words, &w, &bits);
-    const bool maybe = h != kEmptyKey && (ix.bloom[w] & bits) == bits;
+  if (kLayout != kLayoutBucketed || ix.bloom) {
+    bool maybe = h != kEmptyKey;
+    if (ix.bloom) {
+      uint32_t w;
+      uint64_t bits;
+      bloom_place(h, ix.log2_bloom_words, &w, &bits);
+      maybe = maybe && (ix.bloom[w] & bits) == bits;
+    }
     bool ok = false;
     if (maybe) {
-      const int64_t slot = find_slot(ix, h);
+      const int64_t slot = find_slot_in<kLayout>(ix, h);
       ok = slot >= 0 && tau_ok(ix.tau_mask[slot], tau, any_tau);
       if (ok) slot_out[l] = (uint32_t)slot;
     }

@@ -76,8 +76,8 @@ struct ManyImages {
 // `chunk` consecutive tiles (W = waves in the grid). 4 waves per SIMD (at
 // most 128 VGPRs): the more waves, the more sector loads in flight per CU.
 // kSig: kSigDjb2 (wt = the digit-plane weight table) or kSigCrc64 (no table;
-// wt unused).
-template <int kMode, int kSig, class Src>
+// wt unused). kLayout: the index's probe layout (kFlags only).
+template <int kMode, int kSig, class Src, int kLayout = kLayoutBucketed>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(
     Src src, uint32_t chunk, IndexView ix, uint64_t wt, uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
       h = tile_signature_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, wt, A, B, prefetch);
     if constexpr (kMode == kFlags) {
       const uint32_t tau = (tr.tau_first + l) & (kClusterSectors - 1);
-      uint64_t hits = tile_probe(ix, h, tau, tr.any_tau != 0, hit_slot + g * kTileSectors);
+      uint64_t hits = tile_probe<kLayout>(ix, h, tau, tr.any_tau != 0, hit_slot + g * kTileSectors);
       if (tr.n_valid < kTileSectors) hits &= (1ull << tr.n_valid) - 1ull;
       if (l == 0) out[g] = hits;
     } else {
