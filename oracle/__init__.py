@@ -53,6 +53,15 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         lib.oracle_sector_signatures_kind.argtypes = [P, U64, P, I32, I32]
         lib.oracle_build_kind.restype = P
         lib.oracle_build_kind.argtypes = [P, P, U32, I32, I32]
+    if hasattr(lib, "oracle_build_fragments"):
+        lib.oracle_build_fragments.restype = P
+        lib.oracle_build_fragments.argtypes = [P, P, U32, I32]
+        lib.oracle_fragment_flags.restype = I64
+        lib.oracle_fragment_flags.argtypes = [P, P, U64, P, U64, I32]
+        lib.oracle_fragment_confirm.restype = I64
+        lib.oracle_fragment_confirm.argtypes = [P, P, P, U64, P, U64]
+        lib.oracle_fragment_bruteforce.restype = I64
+        lib.oracle_fragment_bruteforce.argtypes = [P, U64, P, P, U32, P, U64]
     lib.oracle_free.restype = None
     lib.oracle_free.argtypes = [P]
     lib.oracle_index_size.restype = U64
@@ -207,4 +216,74 @@ def bruteforce(image, masters, file_offsets, tau0: int = 0, any_tau: bool = Fals
     if cnt > out.size:
         out = np.zeros(cnt, dtype=MATCH_DTYPE)
         lib.oracle_bruteforce(*args, _ptr(out), cnt, threads)
+    return out[:cnt].copy()
+
+
+# ------------------------------------------------------ fragments (Section 5)
+FRAGMENT = 64
+STRIDE = 4
+
+
+def n_windows(n_bytes: int) -> int:
+    return 0 if n_bytes < FRAGMENT else (n_bytes - FRAGMENT) // STRIDE + 1
+
+
+def pack_fragment_files(files: Sequence[bytes]) -> Tuple[np.ndarray, List[int]]:
+    """Packed whole 64-byte fragments of each file and the CSR of their ranges
+    (a trailing partial fragment is not a fragment)."""
+    parts, offsets = [], [0]
+    for f in files:
+        b = _u8(f).reshape(-1)
+        n = b.size // FRAGMENT
+        parts.append(b[:n * FRAGMENT])
+        offsets.append(offsets[-1] + n)
+    data = np.concatenate(parts) if parts else np.empty(0, np.uint8)
+    return data.reshape(-1, FRAGMENT), offsets
+
+
+class FragmentIndex:
+    """Sorted (signature, fragment) entries of packed master fragments."""
+
+    def __init__(self, fragments, file_offsets: Sequence[int], threads: int = 1, lib=None):
+        self.lib = lib or load()
+        self.fragments = _u8(fragments).reshape(-1)
+        self.offsets = np.ascontiguousarray(file_offsets, dtype=np.uint64)
+        assert self.fragments.size == int(self.offsets[-1]) * FRAGMENT
+        self.n_files = len(file_offsets) - 1
+        self.h = self.lib.oracle_build_fragments(_ptr(self.fragments), _ptr(self.offsets), self.n_files, threads)
+
+    def __del__(self):
+        h, self.h = getattr(self, "h", None), None
+        if h:
+            self.lib.oracle_free(h)
+
+    def flag_windows(self, image, threads: int = 1) -> np.ndarray:
+        img = _u8(image).reshape(-1)
+        out = np.zeros(max(n_windows(img.size), 1), dtype=np.uint64)
+        cnt = self.lib.oracle_fragment_flags(self.h, _ptr(img), img.size, _ptr(out), out.size, threads)
+        return out[:cnt].copy()
+
+    def confirm_windows(self, image, flagged) -> np.ndarray:
+        img = _u8(image).reshape(-1)
+        ids = np.ascontiguousarray(flagged, dtype=np.uint64)
+        out = np.zeros(4 * ids.size + 1024, dtype=MATCH_DTYPE)
+        args = (self.h, _ptr(img), _ptr(ids), ids.size)
+        cnt = self.lib.oracle_fragment_confirm(*args, _ptr(out), out.size)
+        if cnt > out.size:
+            out = np.zeros(cnt, dtype=MATCH_DTYPE)
+            self.lib.oracle_fragment_confirm(*args, _ptr(out), cnt)
+        return out[:cnt].copy()
+
+
+def fragment_bruteforce(image, fragments, file_offsets, lib=None) -> np.ndarray:
+    lib = lib or load()
+    img = _u8(image).reshape(-1)
+    m = _u8(fragments).reshape(-1)
+    off = np.ascontiguousarray(file_offsets, dtype=np.uint64)
+    args = (_ptr(img), img.size, _ptr(m), _ptr(off), len(file_offsets) - 1)
+    out = np.zeros(4 * n_windows(img.size) + 1024, dtype=MATCH_DTYPE)
+    cnt = lib.oracle_fragment_bruteforce(*args, _ptr(out), out.size)
+    if cnt > out.size:
+        out = np.zeros(cnt, dtype=MATCH_DTYPE)
+        lib.oracle_fragment_bruteforce(*args, _ptr(out), cnt)
     return out[:cnt].copy()

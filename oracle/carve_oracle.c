@@ -25,7 +25,12 @@
  *     per-cluster rule of Section 3.1, or any position when the caller asks
  *     for it (buffers with no cluster alignment);
  *   - confirmation (Section 3.1) keeps the (disk sector, master) pairs of a
- *     flagged sector whose 512 bytes are equal.
+ *     flagged sector whose 512 bytes are equal;
+ *   - fragments (Section 5): the unit can instead be a 64-byte fragment. Master
+ *     fragment k of a file is its bytes [64k, 64k + 64); the image is read as
+ *     every 64-byte window that starts on a 4-byte boundary (window j covers
+ *     bytes [4j, 4j + 64)), matched at any position, confirmed by comparing the
+ *     64 bytes.
  * The membership test here is a sorted array searched by bisection, not a
  * hash table: the result is a set, and the oracle only has to be plainly
  * correct. A brute-force all-pairs byte comparison is provided as well.
@@ -56,7 +61,11 @@ typedef struct {
   uint64_t n;
   const uint8_t* masters;
   int sig_kind;      /* ORACLE_SIG_DJB2 or ORACLE_SIG_CRC64_GO_ISO */
+  uint32_t unit;     /* bytes per master unit: a sector (512) or a fragment (64) */
 } oracle_index;
+
+#define FRAGMENT_BYTES 64u
+#define WINDOW_STRIDE 4u
 
 enum { ORACLE_SIG_DJB2 = 0, ORACLE_SIG_CRC64_GO_ISO = 1 };
 
@@ -88,6 +97,10 @@ uint64_t oracle_crc64(const uint8_t* s, uint64_t len) {
     for (int b = 0; b < 8; b++) crc = (crc & 1u) ? (crc >> 1) ^ poly_reflected : crc >> 1;
   }
   return ~crc;                                /* complemented result */
+}
+
+static uint64_t signature_n(int kind, const uint8_t* s, uint64_t len) {
+  return kind == ORACLE_SIG_CRC64_GO_ISO ? oracle_crc64(s, len) : oracle_djb2(s, len);
 }
 
 static uint64_t signature(int kind, const uint8_t* s) {
@@ -165,6 +178,7 @@ typedef struct {
   uint32_t n_files;
   oracle_entry* e;
   int kind;
+  uint32_t unit;
 } build_ctx;
 
 static void build_range(void* p, uint64_t lo, uint64_t hi, int t) {
@@ -173,7 +187,7 @@ static void build_range(void* p, uint64_t lo, uint64_t hi, int t) {
   uint32_t f = 0;
   for (uint64_t m = lo; m < hi; m++) {
     while (f + 1 < c->n_files && c->file_offsets[f + 1] <= m) f++;
-    c->e[m].sig = signature(c->kind, c->masters + m * SECTOR_BYTES);
+    c->e[m].sig = signature_n(c->kind, c->masters + m * c->unit, c->unit);
     c->e[m].master = m;
     c->e[m].file = f;
     c->e[m].k = (uint32_t)(m - c->file_offsets[f]);
@@ -182,22 +196,33 @@ static void build_range(void* p, uint64_t lo, uint64_t hi, int t) {
 
 /* masters: n = file_offsets[n_files] packed sectors; file f owns sectors
  * [file_offsets[f], file_offsets[f+1]). The masters buffer must outlive the index. */
-void* oracle_build_kind(const uint8_t* masters, const uint64_t* file_offsets, uint32_t n_files, int threads,
-                        int kind) {
+static void* build_units(const uint8_t* masters, const uint64_t* file_offsets, uint32_t n_files, int threads,
+                         int kind, uint32_t unit) {
   oracle_index* ix = (oracle_index*)calloc(1, sizeof(oracle_index));
   ix->n = n_files ? file_offsets[n_files] : 0;
   ix->masters = masters;
   ix->sig_kind = kind;
+  ix->unit = unit;
   ix->e = (oracle_entry*)malloc(sizeof(oracle_entry) * (ix->n ? ix->n : 1));
-  build_ctx c = {masters, file_offsets, n_files, ix->e, kind};
+  build_ctx c = {masters, file_offsets, n_files, ix->e, kind, unit};
   /* file lookup walks forward from 0 in each range: fine for tests */
   parallel_for(ix->n, threads, build_range, &c);
   qsort(ix->e, ix->n, sizeof(oracle_entry), entry_cmp);
   return ix;
 }
 
+void* oracle_build_kind(const uint8_t* masters, const uint64_t* file_offsets, uint32_t n_files, int threads,
+                        int kind) {
+  return build_units(masters, file_offsets, n_files, threads, kind, SECTOR_BYTES);
+}
+
 void* oracle_build(const uint8_t* masters, const uint64_t* file_offsets, uint32_t n_files, int threads) {
   return oracle_build_kind(masters, file_offsets, n_files, threads, ORACLE_SIG_DJB2);
+}
+
+/* masters: packed 64-byte fragments; file f owns fragments [file_offsets[f], file_offsets[f+1]). */
+void* oracle_build_fragments(const uint8_t* fragments, const uint64_t* file_offsets, uint32_t n_files, int threads) {
+  return build_units(fragments, file_offsets, n_files, threads, ORACLE_SIG_DJB2, FRAGMENT_BYTES);
 }
 
 void oracle_free(void* p) {
@@ -360,5 +385,89 @@ int64_t oracle_bruteforce(const uint8_t* image, uint64_t n_bytes, const uint8_t*
   free(c.part);
   free(c.part_n);
   free(c.part_cap);
+  return (int64_t)cnt;
+}
+
+/* ---------------------------------------------- fragments (Section 5) */
+static uint64_t n_windows(uint64_t n_bytes) {
+  return n_bytes < FRAGMENT_BYTES ? 0 : (n_bytes - FRAGMENT_BYTES) / WINDOW_STRIDE + 1;
+}
+
+typedef struct {
+  const oracle_index* ix;
+  const uint8_t* image;
+  uint8_t* flag;
+} window_ctx;
+
+static void window_range(void* p, uint64_t lo, uint64_t hi, int t) {
+  (void)t;
+  window_ctx* c = (window_ctx*)p;
+  for (uint64_t j = lo; j < hi; j++) {
+    uint64_t h = signature_n(c->ix->sig_kind, c->image + j * WINDOW_STRIDE, FRAGMENT_BYTES);
+    c->flag[j] = (uint8_t)is_flagged(c->ix, h, 0, 0, 1);
+  }
+}
+
+/* Ascending ids j of the windows (bytes [4j, 4j + 64)) whose signature is
+ * that of a master fragment. Returns the count; writes at most cap. */
+int64_t oracle_fragment_flags(void* p, const uint8_t* image, uint64_t n_bytes, uint64_t* out, uint64_t cap,
+                              int threads) {
+  uint64_t n = n_windows(n_bytes);
+  uint8_t* flag = (uint8_t*)malloc(n ? n : 1);
+  window_ctx c = {(const oracle_index*)p, image, flag};
+  parallel_for(n, threads, window_range, &c);
+  uint64_t cnt = 0;
+  for (uint64_t j = 0; j < n; j++)
+    if (flag[j]) {
+      if (cnt < cap) out[cnt] = j;
+      cnt++;
+    }
+  free(flag);
+  return (int64_t)cnt;
+}
+
+/* For each flagged window (ascending ids), every master fragment with an
+ * equal signature and equal 64 bytes, in master order. */
+int64_t oracle_fragment_confirm(void* p, const uint8_t* image, const uint64_t* ids, uint64_t n, oracle_match* out,
+                                uint64_t cap) {
+  const oracle_index* ix = (const oracle_index*)p;
+  uint64_t cnt = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    const uint8_t* w = image + ids[i] * WINDOW_STRIDE;
+    uint64_t h = signature_n(ix->sig_kind, w, FRAGMENT_BYTES);
+    for (uint64_t q = lower_bound(ix, h); q < ix->n && ix->e[q].sig == h; q++) {
+      const oracle_entry* e = &ix->e[q];
+      if (memcmp(w, ix->masters + e->master * FRAGMENT_BYTES, FRAGMENT_BYTES) != 0) continue;
+      if (cnt < cap) {
+        out[cnt].disk_sector = ids[i];
+        out[cnt].file_id = e->file;
+        out[cnt].sector_in_file = e->k;
+      }
+      cnt++;
+    }
+  }
+  return (int64_t)cnt;
+}
+
+/* Every (window, master fragment) pair with equal bytes, compared byte by
+ * byte with no signature. Window order, then master order. */
+int64_t oracle_fragment_bruteforce(const uint8_t* image, uint64_t n_bytes, const uint8_t* fragments,
+                                   const uint64_t* file_offsets, uint32_t n_files, oracle_match* out, uint64_t cap) {
+  uint64_t n = n_windows(n_bytes);
+  uint64_t n_m = n_files ? file_offsets[n_files] : 0;
+  uint64_t cnt = 0;
+  for (uint64_t j = 0; j < n; j++) {
+    uint32_t f = 0;
+    for (uint64_t m = 0; m < n_m; m++) {
+      while (f + 1 < n_files && file_offsets[f + 1] <= m) f++;
+      if (memcmp(image + j * WINDOW_STRIDE, fragments + m * FRAGMENT_BYTES, FRAGMENT_BYTES) != 0) continue;
+      if (cnt < cap) {
+        out[cnt].disk_sector = j;
+        out[cnt].file_id = f;
+        out[cnt].sector_in_file = (uint32_t)(m - file_offsets[f]);
+      }
+      cnt++;
+    }
+  }
   return (int64_t)cnt;
 }

@@ -215,3 +215,31 @@ def crc_collide(data: bytes, k: int = 0, params=CRC64_GO_ISO) -> bytes:
             t = n_bits - 1 - (deg + k)          # bit t of the stream: byte t // 8, bit t % 8 (LSB first)
             b[t // 8] ^= 1 << (t % 8)
     return bytes(b)
+
+
+# ------------------------------------------------------ fragments (Section 5)
+FRAGMENT = 64
+STRIDE = 4
+
+
+def fragment_windows(image: bytes):
+    """(j, bytes) of every 64-byte window starting on a 4-byte boundary."""
+    for j in range(0, (len(image) - FRAGMENT) // STRIDE + 1 if len(image) >= FRAGMENT else 0):
+        yield j, image[STRIDE * j: STRIDE * j + FRAGMENT]
+
+
+def fragment_flags_by_definition(image: bytes, fragments: Sequence[bytes]) -> List[int]:
+    sigs = {djb2_closed(f) for f in fragments}
+    return [j for j, w in fragment_windows(image) if djb2_closed(w) in sigs]
+
+
+def fragment_matches_by_comparison(image: bytes, fragments: Sequence[bytes], file_offsets: Sequence[int]):
+    """All (window, file, fragment in file) with equal bytes, in window then master order."""
+    owner = []
+    for f in range(len(file_offsets) - 1):
+        for k in range(file_offsets[f + 1] - file_offsets[f]):
+            owner.append((f, k))
+    by_bytes = {}
+    for m, frag in enumerate(fragments):
+        by_bytes.setdefault(bytes(frag), []).append(owner[m])
+    return [(j, f, k) for j, w in fragment_windows(image) for f, k in by_bytes.get(w, [])]

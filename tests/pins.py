@@ -305,5 +305,68 @@ def pin_crc_sets(lib, seed=4):
             assert len(set(flags) - set(j for j, _, _ in conf)) > 0
 
 
-SET_PINS = [pin_sets_vs_definition, pin_edges, pin_crc_sets]
+# ------------------------------------------------- fragments (Section 5)
+def fragment_small_case(seed=21, n_bytes=48 * 1024):
+    """Master files of uneven byte lengths (a trailing partial fragment, a
+    file too short for any), a duplicated fragment and an all-zero one; an
+    image with whole files planted at 4-byte aligned offsets (found) and at
+    offsets that are not (not found unless by chance), crafted djb2 collisions
+    of fragments at aligned offsets, a zero run, and a ragged tail."""
+    rng = random.Random(seed)
+    sizes = [64 * 7 + 13, 64 * 3, 64 * 20 + 63, 64, 10, 64 * 5]
+    files = [bytes(rng.getrandbits(8) for _ in range(n)) for n in sizes]
+    f0 = bytearray(files[0])
+    f0[64 * 2: 64 * 3] = files[2][64 * 5: 64 * 6]          # duplicated fragment
+    files[0] = bytes(f0)
+    f5 = bytearray(files[5])
+    f5[64 * 4: 64 * 5] = bytes(64)                         # all-zero fragment
+    files[5] = bytes(f5)
+    frag_data, offsets = oracle.pack_fragment_files(files)
+    fragments = [frag_data[i].tobytes() for i in range(frag_data.shape[0])]
+    img = bytearray(rng.getrandbits(8) for _ in range(n_bytes + 37))
+    truth = set()
+    pos = 100
+    while pos < n_bytes - 2000:
+        f = rng.choice([0, 1, 2, 3])
+        data = files[f]
+        o = pos + rng.choice([0, 0, 0, 1, 2, 3]) + 4 * rng.randrange(8)
+        img[o:o + len(data)] = data
+        for k in range(len(data) // 64):
+            if (o + 64 * k) % 4 == 0:
+                truth.add(((o + 64 * k) // 4, f, k))
+        pos = o + len(data) + rng.randrange(16, 400)
+    tail = n_bytes - 1900                                  # past the planted files
+    for i in range(12):                                    # flagged, not confirmed
+        o = tail - tail % 4 + 68 * i
+        src = fragments[rng.randrange(len(fragments))]
+        p_ = next(q for q in range(60, 0, -1) if src[q] <= 254 and src[q + 1] >= 33)
+        img[o:o + 64] = spec.collide(src, p_)
+    z = tail - tail % 4 + 68 * 12 + 16
+    img[z:z + 300] = bytes(300)                            # zero run: several aligned zero windows
+    return bytes(img), fragments, frag_data, offsets, truth
+
+
+def pin_fragment_sets(lib, seed=21):
+    """Windows at every 4-byte boundary: flags equal the closed-form
+    definition, confirmed matches equal a pure-Python comparison of every
+    window with every fragment and the C brute force, planted aligned
+    fragments are found, collisions are flagged only; edge sizes."""
+    image, fragments, frag_data, offsets, truth = fragment_small_case(seed)
+    ix = oracle.FragmentIndex(frag_data, offsets, threads=2, lib=lib)
+    img = np.frombuffer(image, np.uint8)
+    flags = [int(x) for x in ix.flag_windows(img, threads=2)]
+    assert flags == spec.fragment_flags_by_definition(image, fragments)
+    conf = _as_tuples(ix.confirm_windows(img, flags))
+    want = spec.fragment_matches_by_comparison(image, fragments, offsets)
+    assert conf == want
+    assert _as_tuples(oracle.fragment_bruteforce(img, frag_data, offsets, lib=lib)) == want
+    assert truth <= set(conf)
+    assert len(set(flags) - set(j for j, _, _ in conf)) >= 12
+    assert sum(1 for j, f, k in conf if f == 5 and k == 4) >= 50     # the zero run
+    for n, want_windows in ((0, 0), (63, 0), (64, 1), (67, 1), (68, 2), (200, 35)):
+        w = ix.flag_windows(np.zeros(n, np.uint8))
+        assert len(w) == (want_windows if n else 0) and list(w) == list(range(len(w)))
+
+
+SET_PINS = [pin_sets_vs_definition, pin_edges, pin_crc_sets, pin_fragment_sets]
 ALL_PINS = SIGNATURE_PINS + SET_PINS

@@ -39,6 +39,10 @@ MUTANTS = {
     "crc-zero-preset": ("uint64_t crc = ~0ull;", "uint64_t crc = 0;"),
     "crc-no-final-complement": ("return ~crc;", "return crc;"),
     "crc-byte-at-top": ("crc ^= (uint64_t)s[i];", "crc ^= (uint64_t)s[i] << 56;"),
+    "window-stride-8": ("#define WINDOW_STRIDE 4u", "#define WINDOW_STRIDE 8u"),
+    "window-63-bytes": ("c->image + j * WINDOW_STRIDE, FRAGMENT_BYTES);", "c->image + j * WINDOW_STRIDE, FRAGMENT_BYTES - 1);"),
+    "last-window-dropped": ("(n_bytes - FRAGMENT_BYTES) / WINDOW_STRIDE + 1;", "(n_bytes - FRAGMENT_BYTES) / WINDOW_STRIDE;"),
+    "fragment-confirm-skips-memcmp": ("      if (memcmp(w, ix->masters + e->master * FRAGMENT_BYTES, FRAGMENT_BYTES) != 0) continue;\n", ""),
     "crc-kind-ignored": ("return kind == ORACLE_SIG_CRC64_GO_ISO ? oracle_crc64(s, SECTOR_BYTES) : oracle_djb2(s, SECTOR_BYTES);",
                          "return oracle_djb2(s, SECTOR_BYTES);"),
 }
