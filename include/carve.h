@@ -203,6 +203,35 @@ int sector_signatures(const void* sectors, uint64_t n_sectors, uint64_t* sigs, v
 int sector_signatures_kind(uint32_t sig_kind, const void* sectors, uint64_t n_sectors, uint64_t* sigs,
                            void* stream);
 
+/* ---------------------------------------------------------------- fragments
+ * Section 5 scans every 64-byte fragment of a disk aligned on a 32-bit
+ * boundary, to find small files (logos, images) embedded in others. Master
+ * fragment k of a file is its bytes [64k, 64k + 64); window j of an image is
+ * its bytes [4j, 4j + 64), for every j with 4j + 64 <= n_bytes. A window is
+ * flagged when its djb2-64 signature (Eq. (1) over the 64 bytes) is that of a
+ * master fragment, at any position (no cluster rule); confirmation compares
+ * the 64 bytes. The scan object is the one of scan_image: flagged_sectors
+ * returns window ids j (byte offset 4j), confirm_matches / confirm_enqueue
+ * records (disk_sector = j, file_id, sector_in_file = fragment index).
+ */
+
+/* build_fragment_index -- as build_master_index, over packed 64-byte master
+ * fragments: master_fragments: device, 16-B aligned, file_fragment_offsets[n_files]
+ * fragments of 64 B; file_fragment_offsets: host CSR (n_files + 1 entries,
+ * [0] = 0) of each file's fragment range. params as build_master_index;
+ * EUNSUPPORTED unless sig_kind is djb2-64 and layout is bucketed. The index
+ * serves scan_fragments only (scan_image, scan_batch, autotune_scan and
+ * server_create reject it with EINVAL). index_stats counts fragments as
+ * master sectors. */
+int build_fragment_index(const void* master_fragments, const uint64_t* file_fragment_offsets, uint32_t n_files,
+                         const carve_index_params* params, void* stream, carve_index** out);
+
+/* scan_fragments -- flag every window of a device-resident image (16-B
+ * aligned; any n_bytes; fewer than 64 bytes gives no window). Asynchronous on
+ * `stream`; *io as scan_image (reused when non-null). EINVAL for a sector
+ * index, a null or misaligned image, or a batch object. */
+int scan_fragments(const carve_index* idx, const void* image, uint64_t n_bytes, void* stream, carve_scan** io);
+
 /* index_stats -- sizes of a built index (host struct). */
 int index_stats(const carve_index* idx, carve_index_stats* out);
 

@@ -36,7 +36,7 @@ EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_match
            "scan_set_timing", "scan_kernel_ms", "confirm_enqueue", "batch_confirm_enqueue", "server_create",
            "server_submit", "server_submit_many", "server_poll", "server_job_flags", "server_job_matches",
            "server_release", "server_release_many", "server_stats", "server_free", "free_index", "free_scan",
-           "free_batch", "carve_last_error")
+           "free_batch", "carve_last_error", "build_fragment_index", "scan_fragments")
 
 
 class CarveError(RuntimeError):
@@ -114,6 +114,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sector_signatures.argtypes = [P, U64, P, P]
     lib.sector_signatures_kind.restype = I32
     lib.sector_signatures_kind.argtypes = [U32, P, U64, P, P]
+    lib.build_fragment_index.restype = I32
+    lib.build_fragment_index.argtypes = [P, P, U32, ctypes.POINTER(_IndexParams), P, PP]
+    lib.scan_fragments.restype = I32
+    lib.scan_fragments.argtypes = [P, P, U64, P, PP]
     lib.index_stats.restype = I32
     lib.index_stats.argtypes = [P, ctypes.POINTER(_IndexStats)]
     lib.index_set_scan_config.restype = I32
@@ -327,6 +331,60 @@ def scan_image(index: Index, image: torch.Tensor, tau0: int = 0, tau_mode: int =
     sc.image = img
     sc.index = index
     return sc
+
+
+FRAGMENT = 64      # bytes of a master fragment and of an image window
+WINDOW_STRIDE = 4  # windows start on 4-byte boundaries
+
+
+def build_fragment_index(master_fragments: torch.Tensor, file_fragment_offsets: Sequence[int], max_load: float = 0.0,
+                         bloom_bits_per_key: int = 0, stream=None) -> Index:
+    """Index of packed 64-byte master fragments (uint8 device tensor, file after
+    file; see pack_fragment_files), for scan_fragments."""
+    lib = load_library()
+    m = _dev_u8(master_fragments, "master_fragments")
+    off = np.ascontiguousarray(file_fragment_offsets, dtype=np.uint64)
+    if off.size < 1:
+        raise ValueError("file_fragment_offsets needs at least one entry")
+    if m.numel() != int(off[-1]) * FRAGMENT:
+        raise ValueError("master_fragments size does not match file_fragment_offsets[-1] fragments")
+    p = _IndexParams(CARVE_SIG_DJB2_64, float(max_load), int(bloom_bits_per_key), CARVE_LAYOUT_BUCKETED)
+    h = ctypes.c_void_p()
+    _check(lib.build_fragment_index(m.data_ptr() if m.numel() else None, off.ctypes.data, off.size - 1,
+                                    ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))
+    return Index(h.value, m, off.tolist())
+
+
+def scan_fragments(index: Index, image: torch.Tensor, stream=None, scan: Optional[Scan] = None,
+                   n_bytes: Optional[int] = None) -> Scan:
+    """Flag every 64-byte window at a 4-byte boundary of a device-resident image;
+    flagged_sectors then returns window ids (byte offset 4j) and
+    confirm_matches the (window, file, fragment) records."""
+    lib = load_library()
+    img = _dev_u8(image, "image")
+    nb = img.numel() if n_bytes is None else int(n_bytes)
+    if nb > img.numel():
+        raise ValueError("n_bytes exceeds the image tensor")
+    sc = scan if scan is not None else Scan()
+    h = ctypes.c_void_p(sc.handle)
+    _check(lib.scan_fragments(index.handle, img.data_ptr() if nb else None, nb, _stream_ptr(stream),
+                              ctypes.byref(h)))
+    sc.handle = h.value
+    sc.image = img
+    sc.index = index
+    return sc
+
+
+def pack_fragment_files(files: Sequence[torch.Tensor]):
+    """Whole 64-byte fragments of each file, packed file after file, and the
+    CSR of their fragment ranges (a trailing partial fragment is not one)."""
+    parts, offsets = [], [0]
+    for f in files:
+        n = f.numel() // FRAGMENT
+        parts.append(f.reshape(-1)[:n * FRAGMENT])
+        offsets.append(offsets[-1] + n)
+    data = torch.cat(parts) if parts else torch.empty(0, dtype=torch.uint8)
+    return data, offsets
 
 
 def flagged_sectors(scan: Scan, out: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -34,6 +34,7 @@
 #include "carve_device.h"
 #include "carve_internal.h"
 #include "carve_scan_kernel.h"
+#include "carve_fragment_kernel.h"
 
 using namespace carve;
 
@@ -381,8 +382,8 @@ __device__ __forceinline__ Flagged flagged(const Src& src, const uint64_t* ids, 
   const uint32_t im = img_of ? img_of[i] : 0u;
   const ImageDesc& d = src.image(im);
   const uint64_t j = ids[i];
-  return Flagged{d.base + j * kSectorBytes, j, im, (uint32_t)((j + d.tau0) & (kClusterSectors - 1)), d.any_tau,
-                 hit_slot[d.tile_begin * kTileSectors + j]};
+  return Flagged{d.base + j * Src::kUnitStride, j, im, (uint32_t)((j + d.tau0) & (kClusterSectors - 1)),
+                 Src::kAnyPosition ? 1u : d.any_tau, hit_slot[d.tile_begin * kTileSectors + j]};
 }
 
 // 16 lanes per flagged sector: compare its 512 bytes with every candidate
@@ -402,16 +403,28 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
   const uint64_t n_groups = (uint64_t)gridDim.x * per_block;
   for (uint64_t i = (uint64_t)blockIdx.x * per_block + threadIdx.x / kConfirmLanes; i < n_flagged; i += n_groups) {
     const Flagged f = flagged(src, ids, img_of, hit_slot, i);
-    const u32x4* d = (const u32x4*)f.bytes + gl;
-    const u32x4 d0 = d[0], d1 = d[kConfirmLanes];
+    // this lane's share of the unit: 2 x 16 B of a sector, or 4 B of a 64-byte window
+    // (windows are only 4-byte aligned)
+    u32x4 d0 = {}, d1 = {};
+    if constexpr (Src::kUnitBytes == kSectorBytes) {
+      const u32x4* d = (const u32x4*)f.bytes + gl;
+      d0 = d[0];
+      d1 = d[kConfirmLanes];
+    } else {
+      d0.x = ((const uint32_t*)f.bytes)[gl];
+    }
     uint32_t cnt = 0, rank = 0;
     uint64_t mask = 0;
     for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e; ++c) {
       const uint32_t m = cv.cand[c];
       if (!compatible(cv, m, f.tau, f.any_tau)) continue;   // same decision in all 16 lanes
-      const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * kSectorBytes) + gl;
-      const u32x4 q0 = q[0], q1 = q[kConfirmLanes];
-      const u32x4 x = (d0 ^ q0) | (d1 ^ q1);
+      u32x4 x;
+      if constexpr (Src::kUnitBytes == kSectorBytes) {
+        const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * kSectorBytes) + gl;
+        x = (d0 ^ q[0]) | (d1 ^ q[kConfirmLanes]);
+      } else {
+        x = u32x4{d0.x ^ ((const uint32_t*)(cv.masters + (uint64_t)m * Src::kUnitBytes))[gl], 0u, 0u, 0u};
+      }
       const uint64_t diff = ballot((x.x | x.y | x.z | x.w) != 0);
       if (((diff >> (g * kConfirmLanes)) & 0xFFFFull) == 0) {
         ++cnt;
@@ -426,13 +439,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
   }
 }
 
-__device__ __forceinline__ bool sectors_equal(const uint8_t* a, const uint8_t* b) {
-  const u32x4* x = (const u32x4*)a;
-  const u32x4* y = (const u32x4*)b;
-  for (int k = 0; k < (int)(kSectorBytes / 16); ++k) {
-    const u32x4 d = x[k] ^ y[k];
-    if (d.x | d.y | d.z | d.w) return false;
-  }
+template <uint32_t kBytes>
+__device__ __forceinline__ bool units_equal(const uint8_t* a, const uint8_t* b) {
+  const uint32_t* x = (const uint32_t*)a;   // 4-byte aligned (windows start on 4-byte boundaries)
+  const uint32_t* y = (const uint32_t*)b;
+  for (uint32_t k = 0; k < kBytes / 4; ++k)
+    if (x[k] != y[k]) return false;
   return true;
 }
 
@@ -475,7 +487,7 @@ __global__ void k_confirm_emit(Src src, const uint64_t* __restrict__ ids, const 
       const uint32_t m = cv.cand[c];
       if (!compatible(cv, m, f.tau, f.any_tau)) continue;
       const bool eq = rank < 64 ? ((mask >> rank) & 1u) != 0
-                                : sectors_equal(f.bytes, cv.masters + (uint64_t)m * kSectorBytes);
+                                : units_equal<Src::kUnitBytes>(f.bytes, cv.masters + (uint64_t)m * Src::kUnitBytes);
       ++rank;
       if (eq) put_record(out, pos++, f.j, cv.m_file[m], cv.m_k[m], f.image);
     }
@@ -681,6 +693,7 @@ struct carve_index {
   uint64_t n_overflow = 0;
   uint64_t weights = 0;     // djb2's weight table (0 for the CRC)
   uint32_t sig_kind = CARVE_SIG_DJB2_64;
+  uint32_t unit_bytes = kSectorBytes;   // master units: sectors, or 64-byte fragments
   uint32_t log2_bloom_words = 0;
   carve_scan_config cfg{};
   DevBuf keys, tau_mask, cand_off, cand, m_file, m_k, bloom;   // tau_mask: one byte per slot
@@ -705,6 +718,8 @@ struct carve_scan {
   hipStream_t stream = nullptr;
   const carve_index* idx = nullptr;
   bool batch = false;
+  bool fragments = false;        // units are the 64-byte windows of one image
+  uint64_t n_dwords = 0;         // fragments: whole 4-byte words of the image
   std::vector<ImageDesc> desc;   // n_images + 1 (the last: total tiles)
   uint32_t n_images = 0;
   uint64_t n_tiles = 0;
@@ -726,6 +741,7 @@ struct carve_batch : carve_scan {};
 namespace {
 
 OneImage one_image(const carve_scan* sc) { return OneImage{sc->desc[0]}; }
+FragmentWindows fragment_windows(const carve_scan* sc) { return FragmentWindows{sc->desc[0]}; }
 ManyImages many_images(const carve_scan* sc) {
   return ManyImages{sc->d_desc.as<ImageDesc>(), sc->n_images};
 }
@@ -778,10 +794,18 @@ int launch_scan(carve_scan* sc, const Src& src) {
     return CARVE_OK;
   }
   if (sc->timing) HIP_TRY(hipEventRecord(sc->ev0, s));
-  const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
-  CARVE_TRY(launch_k_scan<kFlags>(idx->sig_kind, src, n_words, chunk, idx->cfg.blocks_per_cu, idx->view(),
-                                   idx->weights, sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>(), s,
-                                   idx->layout));
+  if constexpr (std::is_same<Src, FragmentWindows>::value) {
+    const uint64_t n_tasks = cdiv(src.d.n_sectors, kWaveWindows);
+    const int grid = resident_grid(k_frag_scan, kScanThreads, cdiv(n_tasks, kScanWaves), idx->cfg.blocks_per_cu);
+    k_frag_scan<<<grid, kScanThreads, 0, s>>>((const uint32_t*)src.d.base, src.d.n_sectors, sc->n_dwords,
+                                              idx->view(), sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+  } else {
+    const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
+    CARVE_TRY(launch_k_scan<kFlags>(idx->sig_kind, src, n_words, chunk, idx->cfg.blocks_per_cu, idx->view(),
+                                     idx->weights, sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>(), s,
+                                     idx->layout));
+  }
   if (sc->timing) {
     HIP_TRY(hipEventRecord(sc->ev1, s));
     sc->timed = true;
@@ -1020,8 +1044,44 @@ int build_layout(carve_index* ix, const carve_index_params& p, uint64_t n_keys, 
 }
 }  // namespace
 
+namespace {
+// One thread per master fragment: its djb2 over 64 bytes.
+__global__ void k_frag_sigs(const uint32_t* __restrict__ fragments, uint64_t n, uint64_t* __restrict__ sig) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  uint32_t w[16];
+  const u32x4* p = (const u32x4*)(fragments + t * 16);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const u32x4 v = p[k];
+    w[4 * k] = v.x;
+    w[4 * k + 1] = v.y;
+    w[4 * k + 2] = v.z;
+    w[4 * k + 3] = v.w;
+  }
+  sig[t] = fragment_signature(w);
+}
+
+int build_index(const void* master_sectors, const uint64_t* file_sector_offsets, uint32_t n_files,
+                const carve_index_params* params, void* stream, carve_index** out, uint32_t unit);
+}  // namespace
+
 extern "C" int build_master_index(const void* master_sectors, const uint64_t* file_sector_offsets, uint32_t n_files,
                                   const carve_index_params* params, void* stream, carve_index** out) {
+  return build_index(master_sectors, file_sector_offsets, n_files, params, stream, out, kSectorBytes);
+}
+
+extern "C" int build_fragment_index(const void* master_fragments, const uint64_t* file_fragment_offsets,
+                                    uint32_t n_files, const carve_index_params* params, void* stream,
+                                    carve_index** out) {
+  if (params && (params->sig_kind != CARVE_SIG_DJB2_64 || params->layout != CARVE_LAYOUT_BUCKETED))
+    return fail(CARVE_EUNSUPPORTED, "build_fragment_index: fragments use djb2-64 and the bucketed layout");
+  return build_index(master_fragments, file_fragment_offsets, n_files, params, stream, out, kFragBytes);
+}
+
+namespace {
+int build_index(const void* master_sectors, const uint64_t* file_sector_offsets, uint32_t n_files,
+                const carve_index_params* params, void* stream, carve_index** out, uint32_t unit) {
   if (!out) return fail(CARVE_EINVAL, "build_master_index: out is null");
   *out = nullptr;
   if (!file_sector_offsets && n_files) return fail(CARVE_EINVAL, "build_master_index: null offsets");
@@ -1062,6 +1122,7 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   ix->n_masters = n_masters;
   ix->n_files = n_files;
   ix->masters = (const uint8_t*)master_sectors;
+  ix->unit_bytes = unit;
   ix->sig_kind = p.sig_kind;
   if (!sig_table(p.sig_kind, &ix->weights))
     return bail(fail(CARVE_EDEVICE, "build_master_index: weight table unavailable"));
@@ -1118,11 +1179,15 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
     const uint32_t nbk = (uint32_t)cdiv(n_masters, 256);
     k_master_meta<<<nbk, 256, 0, s>>>(d_off.as<uint64_t>(), n_files, n_masters, ix->m_file.as<uint32_t>(),
                                      ix->m_k.as<uint32_t>());
-    const uint64_t n_tiles = cdiv(n_masters, kTileSectors);
-    const OneImage src{ImageDesc{ix->masters, n_masters, 0, 0, 0}};
-    if ((rc = launch_k_scan<kSigs>(ix->sig_kind, src, n_tiles, 1, 0, IndexView{}, ix->weights, sig.as<uint64_t>(),
-                                   nullptr, s)))
-      return bail2(rc);
+    if (unit == kFragBytes) {
+      k_frag_sigs<<<nbk, 256, 0, s>>>((const uint32_t*)ix->masters, n_masters, sig.as<uint64_t>());
+    } else {
+      const uint64_t n_tiles = cdiv(n_masters, kTileSectors);
+      const OneImage src{ImageDesc{ix->masters, n_masters, 0, 0, 0}};
+      if ((rc = launch_k_scan<kSigs>(ix->sig_kind, src, n_tiles, 1, 0, IndexView{}, ix->weights, sig.as<uint64_t>(),
+                                     nullptr, s)))
+        return bail2(rc);
+    }
     k_insert<<<nbk, 256, 0, s>>>(sig.as<uint64_t>(), ix->m_k.as<uint32_t>(), n_masters, ix->keys.as<uint64_t>(), lb,
                                 mask32.as<uint32_t>(), cnt.as<uint32_t>(), m_slot.as<uint32_t>(), d_overflow,
                                 d_failed);
@@ -1194,6 +1259,7 @@ extern "C" int build_master_index(const void* master_sectors, const uint64_t* fi
   *out = ix;
   return CARVE_OK;
 }
+}  // namespace
 
 extern "C" int index_stats(const carve_index* idx, carve_index_stats* out) {
   if (!idx || !out) return fail(CARVE_EINVAL, "index_stats: null argument");
@@ -1243,6 +1309,8 @@ extern "C" void free_batch(carve_batch* b) { free_scan(b); }
 extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_bytes, uint32_t tau0,
                           uint32_t tau_mode, void* stream, carve_scan** io) {
   if (!idx || !io) return fail(CARVE_EINVAL, "scan_image: null idx or io");
+  if (idx->unit_bytes != kSectorBytes)
+    return fail(CARVE_EINVAL, "scan_image: a fragment index (use scan_fragments)");
   CARVE_TRY(validate_image(image, n_bytes, tau0, tau_mode, "scan_image", -1));
   if (*io && (*io)->batch) return fail(CARVE_EINVAL, "scan_image: io is a batch object");
   carve_scan* sc = *io;
@@ -1260,6 +1328,7 @@ extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_
   sc->desc.assign(2, ImageDesc{});
   sc->desc[0] = ImageDesc{(const uint8_t*)image, n_sectors, 0, tau0, tau_mode == CARVE_TAU_ANY ? 1u : 0u};
   sc->desc[1].tile_begin = sc->n_tiles;
+  sc->fragments = false;
   sc->timed = false;
   sc->confirm_enqueued = false;
   int rc = reserve_scan(sc);
@@ -1272,9 +1341,47 @@ extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_
   return CARVE_OK;
 }
 
+extern "C" int scan_fragments(const carve_index* idx, const void* image, uint64_t n_bytes, void* stream,
+                              carve_scan** io) {
+  if (!idx || !io) return fail(CARVE_EINVAL, "scan_fragments: null idx or io");
+  if (idx->unit_bytes != kFragBytes)
+    return fail(CARVE_EINVAL, "scan_fragments: a sector index (build it with build_fragment_index)");
+  if (n_bytes >= kFragBytes && !image) return fail(CARVE_EINVAL, "scan_fragments: null image");
+  if ((uintptr_t)image % 16) return fail(CARVE_EINVAL, "scan_fragments: image not 16-byte aligned");
+  if (*io && (*io)->batch) return fail(CARVE_EINVAL, "scan_fragments: io is a batch object");
+  carve_scan* sc = *io;
+  const bool created = !sc;
+  if (created) {
+    sc = new carve_scan();
+    (void)hipGetDevice(&sc->device);
+  }
+  const uint64_t n_windows = n_bytes < kFragBytes ? 0 : (n_bytes - kFragBytes) / kWindowStride + 1;
+  sc->stream = (hipStream_t)stream;
+  sc->idx = idx;
+  sc->n_images = 1;
+  sc->n_tiles = cdiv(n_windows, kTileSectors);
+  sc->max_sectors = n_windows;
+  sc->n_dwords = n_bytes / 4;
+  sc->desc.assign(2, ImageDesc{});
+  sc->desc[0] = ImageDesc{(const uint8_t*)image, n_windows, 0, 0, 1u};
+  sc->desc[1].tile_begin = sc->n_tiles;
+  sc->fragments = true;
+  sc->timed = false;
+  sc->confirm_enqueued = false;
+  int rc = reserve_scan(sc);
+  if (rc == CARVE_OK) rc = launch_scan(sc, fragment_windows(sc));
+  if (rc != CARVE_OK) {
+    if (created) free_scan(sc);
+    return rc;
+  }
+  *io = sc;
+  return CARVE_OK;
+}
+
 extern "C" int scan_batch(const carve_index* idx, const carve_image_desc* images, uint32_t n_images, void* stream,
                           carve_batch** io) {
   if (!idx || !io || (n_images && !images)) return fail(CARVE_EINVAL, "scan_batch: null argument");
+  if (idx->unit_bytes != kSectorBytes) return fail(CARVE_EINVAL, "scan_batch: a fragment index");
   std::vector<ImageDesc> desc(n_images + 1);
   uint64_t tiles = 0, max_sectors = 0;
   for (uint32_t i = 0; i < n_images; ++i) {
@@ -1373,6 +1480,7 @@ extern "C" int confirm_matches(const carve_index* idx, carve_scan* sc, carve_mat
   if (sc->batch) return fail(CARVE_EINVAL, "confirm_matches: a batch object (use batch_confirm_matches)");
   if (cap && !out) return fail(CARVE_EINVAL, "confirm_matches: null out with cap > 0");
   if (sc->idx != idx) return fail(CARVE_EINVAL, "confirm_matches: scan was made with another index");
+  if (sc->fragments) return confirm_all(idx, sc, fragment_windows(sc), out, cap, n_out);
   return confirm_all(idx, sc, one_image(sc), out, cap, n_out);
 }
 
@@ -1380,6 +1488,7 @@ extern "C" int confirm_enqueue(const carve_index* idx, carve_scan* sc) {
   if (!idx || !sc) return fail(CARVE_EINVAL, "confirm_enqueue: null argument");
   if (sc->batch) return fail(CARVE_EINVAL, "confirm_enqueue: a batch object (use batch_confirm_enqueue)");
   if (sc->idx != idx) return fail(CARVE_EINVAL, "confirm_enqueue: scan was made with another index");
+  if (sc->fragments) return confirm_enqueue_impl<FragmentWindows, carve_match>(idx, sc, fragment_windows(sc));
   return confirm_enqueue_impl<OneImage, carve_match>(idx, sc, one_image(sc));
 }
 
@@ -1498,6 +1607,7 @@ CARVE_HIDDEN int carve_batch_stage_out(carve_batch* b, int with_matches, const c
 extern "C" int autotune_scan(carve_index* idx, const void* sample_image, uint64_t n_bytes, void* stream,
                              carve_scan_config* best) {
   if (!idx) return fail(CARVE_EINVAL, "autotune_scan: null index");
+  if (idx->unit_bytes != kSectorBytes) return fail(CARVE_EINVAL, "autotune_scan: a fragment index");
   if (n_bytes < kSectorBytes) return fail(CARVE_EINVAL, "autotune_scan: the sample needs at least one sector");
   CARVE_TRY(validate_image(sample_image, n_bytes, 0, CARVE_TAU_PER_CLUSTER, "autotune_scan", -1));
   const carve_scan_config saved = idx->cfg;
@@ -1533,3 +1643,5 @@ extern "C" int autotune_scan(carve_index* idx, const void* sample_image, uint64_
   if (rc == CARVE_OK && best) *best = winner;
   return rc;
 }
+
+CARVE_HIDDEN uint32_t carve_index_unit_bytes(const carve_index* idx) { return idx ? idx->unit_bytes : 0; }

@@ -1,0 +1,169 @@
+// Fragment scan (Section 5): every 64-byte window of an image that starts on
+// a 4-byte boundary (window j = bytes [4j, 4j + 64)), hashed with djb2 over
+// its 64 bytes (Eq. (1)), looked up among the signatures of the master files'
+// 64-byte fragments at any position. Device code only; included by carve.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "carve_device.h"
+#include "carve_scan_kernel.h"
+
+namespace carve {
+
+constexpr uint32_t kFragBytes = 64;                          // a master fragment, an image window
+constexpr uint32_t kWindowStride = 4;                        // windows start on 4-byte boundaries
+constexpr uint32_t kLaneWindows = 32;                        // consecutive windows per lane
+constexpr uint32_t kWaveWindows = kWave * kLaneWindows;      // 2048 windows = 8 KiB of image per wave task
+constexpr uint32_t kFragRowDw = kLaneWindows;                // a lane's own 128 bytes, in dwords
+constexpr uint32_t kFragPitchDw = kFragRowDw + 1;            // padded: the 64 lane rows start in distinct banks
+constexpr uint32_t kFragRows = kWave + 1;                    // + the next task's first row (windows overlap it)
+constexpr uint32_t kFragLdsDw = kFragRows * kFragPitchDw;    // 2145 dwords per wave
+
+// Rolling Eq. (1) over a 64-byte window by 4 bytes. With the window's data
+// part H(j) = sum_{i<64} s[4j+i] 33^(63-i) (its signature is 5381*33^64 + H)
+// and D(w) = b0 33^3 + b1 33^2 + b2 33 + b3 for the bytes of word w in address
+// order (D < 2^24):
+//   H(j+1) = H(j) 33^4 - 33^64 D(j) + D(j+16)        (mod 2^64)
+// and the first window is Horner over its 16 words: H = H 33^4 + D(k).
+constexpr uint64_t kPow4 = pow33(4);
+constexpr uint64_t kPow64 = pow33(kFragBytes);
+constexpr uint64_t kFragInit = 5381ull * pow33(kFragBytes);
+
+// The byte weights of D in dot4 form: D = dot(word, low bytes of 33^(3-i))
+// + 256 dot(word, second bytes of 33^(3-i)) (33^3 < 2^16).
+constexpr uint32_t word_weights(uint32_t shift) {
+  uint32_t w = 0;
+  for (uint32_t k = 0; k < 4; ++k) w |= (uint32_t)((pow33(3 - k) >> shift) & 0xFFu) << (8 * k);
+  return w;
+}
+constexpr uint32_t kWordWeightsLo = word_weights(0);
+constexpr uint32_t kWordWeightsHi = word_weights(8);
+
+__device__ __forceinline__ uint32_t word_djb2(uint32_t x) {
+  return __builtin_amdgcn_udot4(x, kWordWeightsLo, 0u, false) +
+         (__builtin_amdgcn_udot4(x, kWordWeightsHi, 0u, false) << 8);
+}
+
+// Signature of a whole 64-byte fragment (16 words, little-endian dwords).
+__device__ __forceinline__ uint64_t fragment_signature(const uint32_t* w) {
+  uint64_t H = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) H = H * kPow4 + word_djb2(w[k]);
+  return kFragInit + H;
+}
+
+// The windows of one image as a tile space for compaction and confirmation:
+// unit j is bytes [4j, 4j + 64); d.n_sectors holds the number of windows.
+struct FragmentWindows {
+  static constexpr uint32_t kUnitBytes = kFragBytes, kUnitStride = kWindowStride;
+  static constexpr bool kAnyPosition = true;
+  ImageDesc d;
+  __device__ __forceinline__ uint64_t n_tiles() const { return (d.n_sectors + kTileSectors - 1) / kTileSectors; }
+  __device__ __forceinline__ const ImageDesc& image(uint32_t) const { return d; }
+  __device__ __forceinline__ uint32_t image_of_tile(uint64_t) const { return 0; }
+};
+
+// Persistent grid; wave q takes tasks q, q + W, ... (W = waves in the grid).
+// Task t: windows [2048t, 2048t + 2048); lane l rolls over windows 32l..32l+31
+// of it and lanes 2m, 2m+1 make hit word 32t + m (bit b = window 64(32t+m)+b).
+// For each hit the matched table slot goes to hit_slot[window].
+__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_frag_scan(
+    const uint32_t* __restrict__ image, uint64_t n_windows, uint64_t n_dwords, IndexView ix,
+    uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
+  __shared__ uint32_t lds[kScanWaves * kFragLdsDw];
+  const uint32_t wv = threadIdx.x / kWave;
+  const uint32_t l = lane_id();
+  uint32_t* my = lds + wv * kFragLdsDw;
+  const uint64_t n_tasks = (n_windows + kWaveWindows - 1) / kWaveWindows;
+  const uint64_t n_words = (n_windows + kTileSectors - 1) / kTileSectors;
+  const uint64_t n_waves = (uint64_t)gridDim.x * kScanWaves;
+  for (uint64_t t = (uint64_t)blockIdx.x * kScanWaves + wv; t < n_tasks; t += n_waves) {
+    // stage dwords [2048t, 2048t + 2080): window j starts at dword j. Staged
+    // dword q goes to row q / 32, column q % 32; lane l's loads are q = l + 64 i,
+    // i.e. row 2i + l / 32. A task inside the image loads from one base with
+    // constant offsets; the last one clamps to the image's last dword (only
+    // windows past the end read the repeated words).
+    const uint64_t dw0 = t * kWaveWindows;
+    constexpr uint32_t kStaged = kFragRows * kFragRowDw;   // 2080
+    uint32_t* dst = my + (l / kFragRowDw) * kFragPitchDw + l % kFragRowDw;
+    if (dw0 + kStaged <= n_dwords) {
+      const uint32_t* src = image + dw0 + l;
+#pragma unroll
+      for (uint32_t i = 0; i < kStaged / kWave; ++i) dst[2 * kFragPitchDw * i] = __builtin_nontemporal_load(src + kWave * i);
+      if (l < kStaged % kWave) dst[2 * kFragPitchDw * (kStaged / kWave)] = __builtin_nontemporal_load(src + kWave * (kStaged / kWave));
+    } else {
+#pragma unroll 4
+      for (uint32_t i = 0; i <= kStaged / kWave; ++i) {
+        const uint32_t q = l + kWave * i;
+        if (q < kStaged) {
+          uint64_t g = dw0 + q;
+          if (g >= n_dwords) g = n_dwords - 1;
+          dst[2 * kFragPitchDw * i] = image[g];
+        }
+      }
+    }
+    wave_sync_lds();
+    // lane l's word k (k < 48) of its stream: row l, then row l + 1 (one pad word between)
+    const uint32_t* row = my + l * kFragPitchDw;
+    auto word = [&](uint32_t k) { return row[k + (k >= kFragRowDw ? kFragPitchDw - kFragRowDw : 0u)]; };
+    const uint64_t j0 = dw0 + (uint64_t)l * kLaneWindows;
+    const uint32_t valid = j0 >= n_windows ? 0u : (n_windows - j0 >= kLaneWindows ? kLaneWindows
+                                                                                   : (uint32_t)(n_windows - j0));
+    uint64_t H = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 16; ++k) H = H * kPow4 + word_djb2(row[k]);
+    uint32_t mask = 0;
+    // batches of 8 windows: 8 signatures, their 8 filter words in flight
+    // together, then the (rare) windows that pass go through the table probe
+#pragma unroll 1
+    for (uint32_t b = 0; b < kLaneWindows; b += 8) {
+      uint64_t h[8];
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i) {
+        const uint32_t w = b + i;
+        h[i] = kFragInit + H;
+        // roll to window w + 1 (after the last window the result is unused)
+        H = H * kPow4 - kPow64 * word_djb2(word(w)) + word_djb2(word(w + 16));
+      }
+      uint32_t pend = valid <= b ? 0u : (valid - b >= 8 ? 0xFFu : (1u << (valid - b)) - 1u);
+      if (ix.bloom) {
+        uint64_t bits[8], fw[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          uint32_t wi;
+          bloom_place(h[i], ix.log2_bloom_words, &wi, &bits[i]);
+          fw[i] = ix.bloom[wi];
+        }
+        uint32_t pass = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) pass |= (uint32_t)(h[i] == kEmptyKey || (fw[i] & bits[i]) == bits[i]) << i;
+        pend &= pass;
+      }
+      while (pend) {
+        const int i = __builtin_ctz(pend);
+        pend &= pend - 1u;
+        uint64_t hv = h[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) hv = i == k ? h[k] : hv;
+        int64_t slot = -1;
+        if (hv == kEmptyKey) {
+          if (ix.zero_sig_mask) slot = ix.zero_slot;
+        } else {
+          slot = find_slot(ix, hv);
+          if (slot >= 0 && ix.tau_mask[slot] == 0) slot = -1;
+        }
+        if (slot >= 0) {
+          mask |= 1u << (b + i);
+          hit_slot[j0 + b + i] = (uint32_t)slot;
+        }
+      }
+    }
+    const uint32_t hi = (uint32_t)__shfl_down((int)mask, 1, kWave);
+    const uint64_t wi = t * (kWaveWindows / kTileSectors) + l / 2;
+    if ((l & 1u) == 0 && wi < n_words) out[wi] = (uint64_t)mask | ((uint64_t)hi << 32);
+    wave_sync_lds();   // this task's rows are read before the next task's stores
+  }
+}
+
+}  // namespace carve

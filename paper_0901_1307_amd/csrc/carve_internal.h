@@ -10,6 +10,9 @@
 // Records a message for carve_last_error() and returns `code`.
 CARVE_HIDDEN int carve_fail_msg(int code, const char* msg);
 
+// Bytes per master unit of an index: 512 (sectors) or 64 (fragments).
+CARVE_HIDDEN uint32_t carve_index_unit_bytes(const carve_index* idx);
+
 // Creates *io when null and grows its device workspace (scan, compaction,
 // confirmation, descriptors) for batches of up to n_sectors sectors in up to
 // n_images images, so later scan_batch / batch_confirm_enqueue calls of that

@@ -40,8 +40,11 @@ __device__ __forceinline__ TileRef tile_of(const ImageDesc& d, uint64_t g, uint3
                  (uint32_t)((first + d.tau0) & (kClusterSectors - 1)), d.any_tau, image};
 }
 
-// A scan of one image: the descriptor travels by value.
+// A scan of one image: the descriptor travels by value. Units are sectors:
+// unit j is bytes [512j, 512j + 512) of its image.
 struct OneImage {
+  static constexpr uint32_t kUnitBytes = kSectorBytes, kUnitStride = kSectorBytes;
+  static constexpr bool kAnyPosition = false;   // the image's own rule applies
   ImageDesc d;
   __device__ __forceinline__ uint64_t n_tiles() const { return (d.n_sectors + kTileSectors - 1) / kTileSectors; }
   // `cursor` is the image of the previous lookup (tiles are visited in increasing order)
@@ -53,6 +56,8 @@ struct OneImage {
 // A batch: descriptors in device memory, n + 1 of them (the last one only
 // carries the total tile count in tile_begin).
 struct ManyImages {
+  static constexpr uint32_t kUnitBytes = kSectorBytes, kUnitStride = kSectorBytes;
+  static constexpr bool kAnyPosition = false;
   const ImageDesc* __restrict__ d;
   uint32_t n;
   __device__ __forceinline__ uint64_t n_tiles() const { return d[n].tile_begin; }

@@ -245,6 +245,7 @@ int launch(carve_server* s, Lane& ln) {
 
 extern "C" int server_create(const carve_index* idx, const carve_server_params* params, carve_server** out) {
   if (!idx || !out) return carve_fail_msg(CARVE_EINVAL, "server_create: null argument");
+  if (carve_index_unit_bytes(idx) != 512) return carve_fail_msg(CARVE_EINVAL, "server_create: a fragment index");
   carve_server_params p{};
   if (params) p = *params;
   for (uint32_t r : p.reserved)

@@ -1,0 +1,149 @@
+"""Fragment scanning (Section 5): every 64-byte window at a 4-byte boundary of
+an image against the 64-byte fragments of master files, on the GPU, against
+the CPU oracle (flags and confirmed matches, element by element)."""
+import random
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pins
+from gpu_util import assert_same_matches, dev_bytes
+from paper_0901_1307_amd import carve
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(idx, image: torch.Tensor, scan=None):
+    sc = carve.scan_fragments(idx, image, scan=scan)
+    return carve.flagged_sectors(sc).numpy().astype(np.uint64), carve.confirm_matches(idx, sc), sc
+
+
+def _oracle(frag_data, offsets, image: bytes):
+    ox = oracle.FragmentIndex(frag_data, offsets, threads=oracle.default_threads())
+    img = np.frombuffer(image, np.uint8)
+    f = ox.flag_windows(img, threads=oracle.default_threads())
+    return f, ox.confirm_windows(img, f)
+
+
+@pytest.mark.parametrize("bloom", [0, carve.CARVE_BLOOM_OFF])
+def test_fragments_small_case(bloom):
+    image, fragments, frag_data, offsets, truth = pins.fragment_small_case()
+    idx = carve.build_fragment_index(dev_bytes(frag_data.tobytes()), offsets, bloom_bits_per_key=bloom)
+    f, m, _ = _gpu(idx, dev_bytes(image))
+    wf, wm = _oracle(frag_data, offsets, image)
+    assert len(wf) > 100
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
+    got = {(int(r["disk_sector"]), int(r["file_id"]), int(r["sector_in_file"])) for r in m}
+    assert truth <= got
+
+
+def _files(rng, n, lo=64, hi=4096):
+    return [bytes(rng.getrandbits(8) for _ in range(rng.randrange(lo, hi))) for _ in range(n)]
+
+
+@pytest.mark.parametrize("n_bytes", [0, 63, 64, 67, 68, 100, 4096, 8191, 8192 + 60, 8192 + 64, 8192 + 67,
+                                     3 * 8192 + 1000, 5 * 8192])
+def test_fragment_sizes(n_bytes):
+    """Every window up to the last one (4j + 64 <= n), across whole and partial
+    wave tasks (8 KiB of windows each), with a fragment planted at the very end."""
+    rng = random.Random(n_bytes)
+    files = _files(rng, 6)
+    frag_data, offsets = oracle.pack_fragment_files(files)
+    img = bytearray(rng.getrandbits(8) for _ in range(n_bytes))
+    if n_bytes >= 64:
+        last = (n_bytes - 64) // 4 * 4
+        if last >= 64:
+            img[0:64] = frag_data[-1].tobytes()               # the first window
+        img[last:last + 64] = frag_data[0].tobytes()          # the last window
+    idx = carve.build_fragment_index(dev_bytes(frag_data.tobytes()), offsets)
+    buf = torch.zeros(max(n_bytes, 16) + 16, dtype=torch.uint8, device="cuda")
+    if n_bytes:
+        buf[:n_bytes] = torch.frombuffer(bytearray(img), dtype=torch.uint8).cuda()
+    f, m, _ = _gpu(idx, buf[:n_bytes])
+    wf, wm = _oracle(frag_data, offsets, bytes(img))
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
+    if n_bytes >= 64:
+        assert int(wf[-1]) == (n_bytes - 64) // 4
+        if n_bytes >= 128:
+            assert int(wf[0]) == 0
+
+
+def test_fragment_many_candidates():
+    """One fragment shared by 70 files (more than the 64 candidates a match
+    mask holds) inside a repeated run: every copy confirmed, in order."""
+    rng = random.Random(3)
+    common = bytes(rng.getrandbits(8) for _ in range(64))
+    files = [bytes(rng.getrandbits(8) for _ in range(64 * (i % 3))) + common for i in range(70)]
+    frag_data, offsets = oracle.pack_fragment_files(files)
+    img = bytearray(rng.getrandbits(8) for _ in range(20000))
+    for o in (400, 1200, 1264, 9000):
+        img[o:o + 64] = common
+    idx = carve.build_fragment_index(dev_bytes(frag_data.tobytes()), offsets)
+    f, m, _ = _gpu(idx, dev_bytes(bytes(img)))
+    wf, wm = _oracle(frag_data, offsets, bytes(img))
+    assert len(wm) == 4 * 70
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
+
+
+def test_fragment_mixed_large():
+    """A 4 MiB image with logos embedded at aligned and unaligned offsets,
+    zero runs and random bytes, 300 master files; also confirmation enqueued
+    and emitted into device memory."""
+    rng = random.Random(9)
+    files = _files(rng, 300, 256, 8192)
+    files[7] = bytes(2048)                                    # a file of zeros
+    frag_data, offsets = oracle.pack_fragment_files(files)
+    n = 4 << 20
+    img = bytearray(np.random.default_rng(9).integers(0, 256, size=n, dtype=np.uint8).tobytes())
+    o = 0
+    while o < n - 10000:
+        data = files[rng.randrange(len(files))]
+        o += rng.randrange(100, 20000)
+        o -= o % 4 if rng.random() < 0.8 else 0
+        img[o:o + len(data)] = data
+        o += len(data)
+    idx = carve.build_fragment_index(dev_bytes(frag_data.tobytes()), offsets)
+    image = dev_bytes(bytes(img))
+    f, m, sc = _gpu(idx, image)
+    wf, wm = _oracle(frag_data, offsets, bytes(img))
+    assert len(wf) > 1000
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
+    carve.scan_fragments(idx, image, scan=sc)
+    carve.confirm_enqueue(idx, sc)
+    assert_same_matches(carve.confirm_matches(idx, sc), wm)
+    carve.scan_fragments(idx, image, scan=sc)
+    out = torch.zeros(16 * (len(wm) + 3), dtype=torch.uint8, device="cuda")
+    assert carve.confirm_matches(idx, sc, out) == len(wm)
+    assert_same_matches(np.frombuffer(out.cpu().numpy().tobytes(), dtype=carve.MATCH_DTYPE)[: len(wm)], wm)
+
+
+def test_fragment_index_guards():
+    rng = random.Random(4)
+    frag_data, offsets = oracle.pack_fragment_files(_files(rng, 3))
+    fidx = carve.build_fragment_index(dev_bytes(frag_data.tobytes()), offsets)
+    sectors = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    sidx = carve.build_master_index(sectors, [0, 8])
+    with pytest.raises(carve.CarveError):
+        carve.scan_image(fidx, sectors)
+    with pytest.raises(carve.CarveError):
+        carve.scan_fragments(sidx, sectors)
+    with pytest.raises(carve.CarveError):
+        carve.scan_batch(fidx, [(sectors, 0, 0)])
+    with pytest.raises(carve.CarveError):
+        carve.Server(fidx)
+    with pytest.raises(carve.CarveError):
+        carve.scan_fragments(fidx, sectors[1:])                # misaligned
+    # fragments use djb2-64: a CRC index of fragments is refused
+    lib = carve.load_library()
+    h = carve.ctypes.c_void_p()
+    p = carve._IndexParams(carve.CARVE_SIG_CRC64_ISO, 0.0, 0, 0)
+    off = np.array([0, 8], np.uint64)
+    rc = lib.build_fragment_index(sectors.data_ptr(), off.ctypes.data, 1, carve.ctypes.byref(p), None,
+                                  carve.ctypes.byref(h))
+    assert rc == carve.CARVE_EUNSUPPORTED and not h.value
