@@ -327,19 +327,25 @@ __device__ __forceinline__ uint32_t bucket_of(uint64_t h, uint32_t log2_buckets)
 // Slot of key h (h != kEmptyKey) or -1. Linear probing over buckets: a key
 // lives in its home bucket or, if that bucket filled up first, a later one
 // (Eq. (3) at bucket granularity); a bucket with a free slot ends the search.
+// The whole 128-byte bucket is loaded before any key is compared: one memory
+// round trip per bucket (keys are distinct, so at most one slot matches).
 __device__ __forceinline__ int64_t find_slot(const IndexView& ix, uint64_t h) {
   const uint32_t nb_mask = (1u << ix.log2_buckets) - 1u;
   uint32_t b = bucket_of(h, ix.log2_buckets);
   for (uint32_t it = 0; it <= nb_mask; ++it) {
     const u64x2* p = (const u64x2*)(ix.keys + (uint64_t)b * kBucketSlots);
+    u64x2 kv[kBucketSlots / 2];
+#pragma unroll
+    for (int c = 0; c < (int)(kBucketSlots / 2); ++c) kv[c] = p[c];
+    int64_t found = -1;
     bool any_empty = false;
 #pragma unroll
     for (int c = 0; c < (int)(kBucketSlots / 2); ++c) {
-      const u64x2 kv = p[c];
-      if (kv.x == h) return (int64_t)b * kBucketSlots + 2 * c;
-      if (kv.y == h) return (int64_t)b * kBucketSlots + 2 * c + 1;
-      any_empty |= (kv.x == kEmptyKey) | (kv.y == kEmptyKey);
+      if (kv[c].x == h) found = (int64_t)b * kBucketSlots + 2 * c;
+      if (kv[c].y == h) found = (int64_t)b * kBucketSlots + 2 * c + 1;
+      any_empty |= (kv[c].x == kEmptyKey) | (kv[c].y == kEmptyKey);
     }
+    if (found >= 0) return found;
     if (any_empty) return -1;
     b = (b + 1) & nb_mask;
   }

@@ -6,12 +6,16 @@ signature, no index and no match (none of the method's arithmetic lives here).
 """
 from .workloads import (  # noqa: F401
     CONFIGS,
+    FRAGMENT_CONFIGS,
     CarveConfig,
+    FragmentConfig,
     DiskImage,
     MasterSet,
     batch_image_specs,
     disk_image,
     disk_sectors,
+    fragment_files,
+    fragment_image,
     master_set,
     master_sectors,
     scaled,

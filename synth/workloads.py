@@ -403,3 +403,67 @@ def served_job_slices(specs, pool_sectors: int, seed: int = 1):
             first -= first % CLUSTER
         out.append(first)
     return out
+
+
+# --------------------------------------------------------------------------
+# fragments (Section 5): small files embedded in a larger image
+# --------------------------------------------------------------------------
+@dataclass
+class FragmentConfig:
+    name: str
+    seed: int
+    n_files: int          # master "logo" files
+    min_bytes: int        # their sizes: log-uniform in [min_bytes, max_bytes]
+    max_bytes: int
+    image_bytes: int
+    n_embedded: int       # whole copies of master files placed in the image
+    p_aligned: float      # share of copies that start on a 4-byte boundary
+
+
+FRAGMENT_CONFIGS = {
+    # 2000 logos of 2-32 KiB (about 25 MB, 380K fragments), 25000 copies in a
+    # 2 GiB image (a scan keeps about 40 B of workspace per 4-byte window)
+    "logos": FragmentConfig("logos", 1, 2000, 2048, 32768, 2 << 30, 25000, 0.8),
+}
+
+
+def fragment_files(cfg: FragmentConfig, device="cpu") -> List[torch.Tensor]:
+    """The master files' bytes (uint8 tensors of log-uniform sizes)."""
+    k = _key(cfg.seed, cfg.name, "frag-files")
+    r = words(k, torch.arange(cfg.n_files, dtype=torch.int64)).double() / float(1 << 32)
+    lo, hi = float(cfg.min_bytes), float(cfg.max_bytes)
+    sizes = torch.exp(torch.log(torch.tensor(lo)) + r * (torch.log(torch.tensor(hi)) - torch.log(torch.tensor(lo))))
+    out = []
+    for f, n in enumerate(sizes.long().tolist()):
+        w = words(_key(cfg.seed, cfg.name, "frag-file", f), torch.arange((n + 3) // 4, dtype=torch.int64, device=device))
+        out.append(_words_to_bytes(w)[:n].clone())
+    return out
+
+
+def fragment_image(cfg: FragmentConfig, files: List[torch.Tensor], device="cpu",
+                   chunk_words: int = 1 << 26) -> torch.Tensor:
+    """Uniform random bytes with n_embedded whole copies of master files, each
+    at an offset that is a multiple of 4 with probability p_aligned (else 1-3
+    past one). Later copies may overwrite earlier ones."""
+    n = cfg.image_bytes
+    img = torch.empty(n, dtype=torch.uint8, device=device)
+    k = _key(cfg.seed, cfg.name, "frag-image")
+    n_words = (n + 3) // 4
+    for w0 in range(0, n_words, chunk_words):
+        w1 = min(n_words, w0 + chunk_words)
+        b = _words_to_bytes(words(k, torch.arange(w0, w1, dtype=torch.int64, device=device)))
+        img[4 * w0: min(n, 4 * w1)] = b[: min(n, 4 * w1) - 4 * w0]
+    kp = _key(cfg.seed, cfg.name, "frag-plant")
+    r = words(kp, torch.arange(3 * cfg.n_embedded, dtype=torch.int64)).view(-1, 3).tolist()
+    thr = _threshold(cfg.p_aligned)
+    for fsel, osel, asel in r:
+        data = files[fsel % len(files)]
+        room = n - data.numel()
+        if room <= 4:
+            continue
+        o = osel % (room - 4)
+        o -= o % 4
+        if asel >= thr:
+            o += 1 + asel % 3
+        img[o: o + data.numel()] = data
+    return img

@@ -147,3 +147,21 @@ def test_fragment_index_guards():
     rc = lib.build_fragment_index(sectors.data_ptr(), off.ctypes.data, 1, carve.ctypes.byref(p), None,
                                   carve.ctypes.byref(h))
     assert rc == carve.CARVE_EUNSUPPORTED and not h.value
+
+
+def test_fragment_workload_scaled():
+    """The benchmark's recipe (logo files embedded in random bytes) at 32 MiB."""
+    import dataclasses
+
+    import synth
+    cfg = dataclasses.replace(synth.FRAGMENT_CONFIGS["logos"], n_files=200, image_bytes=(32 << 20) + 50,
+                              n_embedded=1500)
+    files = synth.fragment_files(cfg, device="cuda")
+    frags, offsets = carve.pack_fragment_files(files)
+    img = synth.fragment_image(cfg, files, device="cuda")
+    idx = carve.build_fragment_index(frags, offsets)
+    f, m, _ = _gpu(idx, img)
+    wf, wm = _oracle(frags.cpu().numpy(), offsets, img.cpu().numpy().tobytes())
+    assert len(wm) > 10000
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
