@@ -232,6 +232,49 @@ int build_fragment_index(const void* master_fragments, const uint64_t* file_frag
  * index, a null or misaligned image, or a batch object. */
 int scan_fragments(const carve_index* idx, const void* image, uint64_t n_bytes, void* stream, carve_scan** io);
 
+/* ---------------------------------------------------------------- host ingest
+ * Section 3.1 (Fig. 7): images in host memory, streamed to the GPU by chunks
+ * through a pair of device buffers while the other chunk is scanned; a
+ * pageable image goes through a pair of pinned host buffers filled by CPU
+ * threads, a pinned one (hipHostMalloc) is transferred directly. Results are
+ * those of scan_image / confirm_matches on the whole image (ids relative to
+ * its first sector). One thread drives an ingest object.
+ */
+typedef struct carve_ingest carve_ingest;
+
+typedef struct {
+  uint64_t chunk_bytes;        /* bytes per transfer, a multiple of 4096 (chunks keep the image's
+                                  cluster positions); 0 = 256 MiB. Device and pinned memory: 2 each */
+  uint32_t confirm;            /* non-zero: confirm the flagged sectors */
+  uint32_t copy_threads;       /* CPU threads staging a pageable image; 0 = 8, at most 64 */
+  uint32_t reserved[4];        /* must be zero */
+} carve_ingest_params;
+
+typedef struct {
+  uint64_t bytes;              /* bytes scanned by the last ingest_scan (whole sectors) */
+  uint64_t chunks;
+  double seconds;              /* its wall time, transfers included */
+  uint32_t pinned_source;      /* 1: the image was pinned and transferred directly */
+  uint32_t reserved;
+} carve_ingest_stats;
+
+/* ingest_create -- idx (a sector index) must outlive the object. EINVAL for a
+ * bad chunk size or a fragment index, ENOMEM when buffers fail. */
+int ingest_create(const carve_index* idx, const carve_ingest_params* params, carve_ingest** out);
+
+/* ingest_scan -- scan host_image (host pointer, n_bytes; the trailing partial
+ * sector is ignored) with tau0 / tau_mode as scan_image; returns when every
+ * chunk is scanned (and confirmed) and its results collected. */
+int ingest_scan(carve_ingest* in, const void* host_image, uint64_t n_bytes, uint32_t tau0, uint32_t tau_mode);
+
+/* ingest_flagged_sectors / ingest_matches -- the last ingest_scan's ascending
+ * flagged sector ids / ordered records (host buffers; ETRUNC + full count when
+ * short; records only with confirm set). */
+int ingest_flagged_sectors(const carve_ingest* in, uint64_t* out, uint64_t cap, uint64_t* n_out);
+int ingest_matches(const carve_ingest* in, carve_match* out, uint64_t cap, uint64_t* n_out);
+int ingest_stats(const carve_ingest* in, carve_ingest_stats* out);
+void ingest_free(carve_ingest* in);   /* NULL is a no-op; waits for transfers and scans in flight */
+
 /* index_stats -- sizes of a built index (host struct). */
 int index_stats(const carve_index* idx, carve_index_stats* out);
 

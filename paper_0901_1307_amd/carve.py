@@ -36,7 +36,8 @@ EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_match
            "scan_set_timing", "scan_kernel_ms", "confirm_enqueue", "batch_confirm_enqueue", "server_create",
            "server_submit", "server_submit_many", "server_poll", "server_job_flags", "server_job_matches",
            "server_release", "server_release_many", "server_stats", "server_free", "free_index", "free_scan",
-           "free_batch", "carve_last_error", "build_fragment_index", "scan_fragments")
+           "free_batch", "carve_last_error", "build_fragment_index", "scan_fragments", "ingest_create",
+           "ingest_scan", "ingest_flagged_sectors", "ingest_matches", "ingest_stats", "ingest_free")
 
 
 class CarveError(RuntimeError):
@@ -81,6 +82,16 @@ class _ServerStats(ctypes.Structure):
                 ("host_retire_s", ctypes.c_double)]
 
 
+class _IngestParams(ctypes.Structure):
+    _fields_ = [("chunk_bytes", ctypes.c_uint64), ("confirm", ctypes.c_uint32), ("copy_threads", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
+
+
+class _IngestStats(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_uint64), ("chunks", ctypes.c_uint64), ("seconds", ctypes.c_double),
+                ("pinned_source", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class _IndexStats(ctypes.Structure):
     _fields_ = [("n_master_sectors", ctypes.c_uint64), ("n_unique_signatures", ctypes.c_uint64),
                 ("n_buckets", ctypes.c_uint64), ("n_overflow_keys", ctypes.c_uint64),
@@ -114,6 +125,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sector_signatures.argtypes = [P, U64, P, P]
     lib.sector_signatures_kind.restype = I32
     lib.sector_signatures_kind.argtypes = [U32, P, U64, P, P]
+    lib.ingest_create.restype = I32
+    lib.ingest_create.argtypes = [P, ctypes.POINTER(_IngestParams), PP]
+    lib.ingest_scan.restype = I32
+    lib.ingest_scan.argtypes = [P, P, U64, U32, U32]
+    lib.ingest_flagged_sectors.restype = I32
+    lib.ingest_flagged_sectors.argtypes = [P, P, U64, PU64]
+    lib.ingest_matches.restype = I32
+    lib.ingest_matches.argtypes = [P, P, U64, PU64]
+    lib.ingest_stats.restype = I32
+    lib.ingest_stats.argtypes = [P, ctypes.POINTER(_IngestStats)]
+    lib.ingest_free.restype = None
+    lib.ingest_free.argtypes = [P]
     lib.build_fragment_index.restype = I32
     lib.build_fragment_index.argtypes = [P, P, U32, ctypes.POINTER(_IndexParams), P, PP]
     lib.scan_fragments.restype = I32
@@ -626,6 +649,60 @@ def image_descs(jobs) -> np.ndarray:
         t = _dev_u8(t, "image")
         out[i] = (t.data_ptr() if t.numel() else 0, t.numel(), int(tau0), int(mode))
     return out
+
+
+class Ingest:
+    """Scans of images in host memory through a pair of device buffers (the
+    paper's double-buffered pipeline); see include/carve.h."""
+
+    def __init__(self, index: Index, chunk_bytes: int = 0, confirm: bool = True, copy_threads: int = 0):
+        lib = load_library()
+        p = _IngestParams(int(chunk_bytes), int(confirm), int(copy_threads))
+        h = ctypes.c_void_p()
+        _check(lib.ingest_create(index.handle, ctypes.byref(p), ctypes.byref(h)))
+        self.handle = h.value
+        self.index = index
+
+    def scan(self, image: torch.Tensor, tau0: int = 0, tau_mode: int = CARVE_TAU_PER_CLUSTER) -> None:
+        """image: a contiguous uint8 CPU tensor (pinned or pageable)."""
+        if image.device.type != "cpu" or image.dtype != torch.uint8 or not image.is_contiguous():
+            raise TypeError("image must be a contiguous uint8 CPU tensor")
+        _check(load_library().ingest_scan(self.handle, image.data_ptr() if image.numel() else None, image.numel(),
+                                          int(tau0), int(tau_mode)))
+
+    def flagged(self) -> np.ndarray:
+        lib = load_library()
+        n = ctypes.c_uint64()
+        _check(lib.ingest_flagged_sectors(self.handle, None, 0, ctypes.byref(n)), allow_trunc=True)
+        out = np.zeros(int(n.value), dtype=np.uint64)
+        if out.size:
+            _check(lib.ingest_flagged_sectors(self.handle, out.ctypes.data, out.size, ctypes.byref(n)))
+        return out
+
+    def matches(self) -> np.ndarray:
+        lib = load_library()
+        n = ctypes.c_uint64()
+        _check(lib.ingest_matches(self.handle, None, 0, ctypes.byref(n)), allow_trunc=True)
+        out = np.zeros(int(n.value), dtype=MATCH_DTYPE)
+        if out.size:
+            _check(lib.ingest_matches(self.handle, out.ctypes.data, out.size, ctypes.byref(n)))
+        return out
+
+    def stats(self) -> dict:
+        st = _IngestStats()
+        _check(load_library().ingest_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _IngestStats._fields_ if k != "reserved"}
+
+    def close(self):
+        h, self.handle = self.handle, None
+        if h:
+            load_library().ingest_free(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def confirm_enqueue(index: Index, scan) -> None:
