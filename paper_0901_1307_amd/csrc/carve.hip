@@ -286,6 +286,16 @@ __global__ void k_bloom_build(const uint64_t* __restrict__ keys, uint64_t n_slot
   atomicOr((unsigned long long*)(bloom + w), (unsigned long long)bits);
 }
 
+// The fragment scan's first-level filter (placed like lds_filter_place).
+__global__ void k_lds_filter_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t log2_words,
+                                   uint32_t* filter) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slots || keys[i] == kEmptyKey) return;
+  uint32_t w, bits;
+  lds_filter_place(keys[i], log2_words, &w, &bits);
+  atomicOr(&filter[w], bits);
+}
+
 // Other probe layouts. The distinct signatures of the table with their slots
 // (any order).
 __global__ void k_occupied(const uint64_t* __restrict__ keys, uint64_t n_slots, uint64_t* __restrict__ out_keys,
@@ -700,11 +710,14 @@ struct carve_index {
   uint32_t layout = CARVE_LAYOUT_BUCKETED;
   DevBuf lin_keys, lin_slot, sorted_keys, sorted_slot;          // probe structures of the other layouts
   uint32_t log2_lin = 0, n_sorted = 0;
+  DevBuf lds_filter;                                            // fragment indexes: first-level filter
+  uint32_t log2_lds_words = 0;
   IndexView view() const {
     return IndexView{keys.as<uint64_t>(), tau_mask.as<uint8_t>(), bloom.bytes ? bloom.as<uint64_t>() : nullptr,
                      log2_buckets, log2_bloom_words, zero_sig_mask, (uint32_t)n_slots,
                      lin_keys.as<uint64_t>(), lin_slot.as<uint32_t>(), log2_lin, n_sorted,
-                     sorted_keys.as<uint64_t>(), sorted_slot.as<uint32_t>()};
+                     sorted_keys.as<uint64_t>(), sorted_slot.as<uint32_t>(), lds_filter.as<uint32_t>(),
+                     log2_lds_words};
   }
   ConfirmView cview() const {
     return ConfirmView{cand_off.as<uint32_t>(), cand.as<uint32_t>(), m_file.as<uint32_t>(), m_k.as<uint32_t>(),
@@ -796,8 +809,8 @@ int launch_scan(carve_scan* sc, const Src& src) {
   if (sc->timing) HIP_TRY(hipEventRecord(sc->ev0, s));
   if constexpr (std::is_same<Src, FragmentWindows>::value) {
     const uint64_t n_tasks = cdiv(src.d.n_sectors, kWaveWindows);
-    const int grid = resident_grid(k_frag_scan, kScanThreads, cdiv(n_tasks, kScanWaves), idx->cfg.blocks_per_cu);
-    k_frag_scan<<<grid, kScanThreads, 0, s>>>((const uint32_t*)src.d.base, src.d.n_sectors, sc->n_dwords,
+    const int grid = resident_grid(k_frag_scan, kFragThreads, cdiv(n_tasks, kFragWaves), idx->cfg.blocks_per_cu);
+    k_frag_scan<<<grid, kFragThreads, 0, s>>>((const uint32_t*)src.d.base, src.d.n_sectors, sc->n_dwords,
                                               idx->view(), sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>());
     HIP_TRY(hipGetLastError());
   } else {
@@ -982,6 +995,7 @@ extern "C" void free_index(carve_index* idx) {
   idx->lin_slot.release();
   idx->sorted_keys.release();
   idx->sorted_slot.release();
+  idx->lds_filter.release();
   delete idx;
 }
 
@@ -1255,6 +1269,18 @@ int build_index(const void* master_sectors, const uint64_t* file_sector_offsets,
     // the distinct signatures counted above include signature 0, which has no slot
     if ((rc = build_layout(ix, p, h_unique - (zmask ? 1 : 0), s))) return bail2(rc);
   }
+  if (unit == kFragBytes) {   // first-level filter: about 16 bits per signature, 1-64 KiB (always present)
+    uint32_t lw = 8;
+    while (lw < 14 && (32ull << lw) < 16 * h_unique) ++lw;
+    if ((rc = ix->lds_filter.reserve(4ull << lw))) return bail2(rc);
+    ix->log2_lds_words = lw;
+    if (hipMemsetAsync(ix->lds_filter.p, 0, 4ull << lw, s) != hipSuccess)
+      return bail2(fail(CARVE_EDEVICE, "build_fragment_index: filter memset failed"));
+    k_lds_filter_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw,
+                                                             ix->lds_filter.as<uint32_t>());
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return bail2(fail(CARVE_EDEVICE, "build_fragment_index: filter build failed"));
+  }
   cleanup();
   *out = ix;
   return CARVE_OK;
@@ -1269,7 +1295,7 @@ extern "C" int index_stats(const carve_index* idx, carve_index_stats* out) {
   out->n_overflow_keys = idx->n_overflow;
   out->device_bytes = idx->keys.bytes + idx->tau_mask.bytes + idx->cand_off.bytes + idx->cand.bytes +
                       idx->m_file.bytes + idx->m_k.bytes + idx->bloom.bytes + idx->lin_keys.bytes +
-                      idx->lin_slot.bytes + idx->sorted_keys.bytes + idx->sorted_slot.bytes;
+                      idx->lin_slot.bytes + idx->sorted_keys.bytes + idx->sorted_slot.bytes + idx->lds_filter.bytes;
   out->bloom_bytes = idx->bloom.bytes;
   return CARVE_OK;
 }

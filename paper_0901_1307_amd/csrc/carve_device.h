@@ -304,6 +304,8 @@ struct IndexView {
   uint32_t n_sorted;         // sorted distinct signatures (binary search)
   const uint64_t* sorted_keys;
   const uint32_t* sorted_slot;
+  const uint32_t* lds_filter;  // fragment indexes: the first-level filter copied into LDS (2^log2_lds_words words)
+  uint32_t log2_lds_words;
 };
 
 // Probe layouts (the values of carve_index_layout).

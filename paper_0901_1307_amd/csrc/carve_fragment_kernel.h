@@ -13,12 +13,26 @@ namespace carve {
 
 constexpr uint32_t kFragBytes = 64;                          // a master fragment, an image window
 constexpr uint32_t kWindowStride = 4;                        // windows start on 4-byte boundaries
-constexpr uint32_t kLaneWindows = 32;                        // consecutive windows per lane
-constexpr uint32_t kWaveWindows = kWave * kLaneWindows;      // 2048 windows = 8 KiB of image per wave task
-constexpr uint32_t kFragRowDw = kLaneWindows;                // a lane's own 128 bytes, in dwords
-constexpr uint32_t kFragPitchDw = kFragRowDw + 1;            // padded: the 64 lane rows start in distinct banks
+constexpr uint32_t kFragThreads = 1024;                      // one block per CU: its LDS holds the filter
+constexpr uint32_t kFragWaves = kFragThreads / kWave;
+constexpr uint32_t kLaneWindows = 16;                        // consecutive windows per lane
+constexpr uint32_t kWaveWindows = kWave * kLaneWindows;      // 1024 windows = 4 KiB of image per wave task
+constexpr uint32_t kFragRowDw = kLaneWindows;                // a lane's own 64 bytes, in dwords
+constexpr uint32_t kFragPitchDw = kFragRowDw + 1;            // odd pitch: the 64 lane rows start in distinct banks
 constexpr uint32_t kFragRows = kWave + 1;                    // + the next task's first row (windows overlap it)
-constexpr uint32_t kFragLdsDw = kFragRows * kFragPitchDw;    // 2145 dwords per wave
+constexpr uint32_t kFragLdsDw = kFragRows * kFragPitchDw;    // 1105 dwords per wave
+constexpr uint32_t kLdsFilterMaxWords = 1u << 14;            // 64 KiB: the first filter, in LDS
+
+// First-level filter: a bitmap of 32-bit words in LDS; a signature sets 2 bits
+// of one word, placed by a multiplicative hash independent of the Bloom
+// filter's. Only windows that pass it read the (L2-resident) Bloom filter.
+constexpr uint64_t kLdsFilterMul = 0x9FB21C651E98DF25ull;
+__device__ __forceinline__ void lds_filter_place(uint64_t h, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
+  const uint64_t p = h * kLdsFilterMul;
+  *word = (uint32_t)(p >> (64 - log2_words));
+  const uint32_t f = (uint32_t)(p >> (54 - log2_words));   // 10 bits below the word index
+  *bits = (1u << (f & 31u)) | (1u << ((f >> 5) & 31u));
+}
 
 // Rolling Eq. (1) over a 64-byte window by 4 bytes. With the window's data
 // part H(j) = sum_{i<64} s[4j+i] 33^(63-i) (its signature is 5381*33^64 + H)
@@ -64,34 +78,42 @@ struct FragmentWindows {
   __device__ __forceinline__ uint32_t image_of_tile(uint64_t) const { return 0; }
 };
 
-// Persistent grid; wave q takes tasks q, q + W, ... (W = waves in the grid).
-// Task t: windows [2048t, 2048t + 2048); lane l rolls over windows 32l..32l+31
-// of it and lanes 2m, 2m+1 make hit word 32t + m (bit b = window 64(32t+m)+b).
-// For each hit the matched table slot goes to hit_slot[window].
-__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_frag_scan(
+// Persistent grid of one block per CU; wave q takes tasks q, q + W, ...
+// (W = waves in the grid). Task t: windows [1024t, 1024t + 1024); lane l
+// rolls over windows 16l..16l+15 of it, and lanes 4m..4m+3 make hit word
+// 16t + m (bit b = window 64(16t+m)+b). For each hit the matched table slot
+// goes to hit_slot[window].
+__global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_frag_scan(
     const uint32_t* __restrict__ image, uint64_t n_windows, uint64_t n_dwords, IndexView ix,
     uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
-  __shared__ uint32_t lds[kScanWaves * kFragLdsDw];
+  __shared__ uint32_t lds[kFragWaves * kFragLdsDw];
+  __shared__ uint32_t lfilter[kLdsFilterMaxWords];
+  const uint32_t lw = ix.log2_lds_words;
+  for (uint32_t i = threadIdx.x; i < (1u << lw); i += kFragThreads) lfilter[i] = ix.lds_filter[i];
+  __syncthreads();   // before any wave of the block can leave
   const uint32_t wv = threadIdx.x / kWave;
   const uint32_t l = lane_id();
   uint32_t* my = lds + wv * kFragLdsDw;
   const uint64_t n_tasks = (n_windows + kWaveWindows - 1) / kWaveWindows;
   const uint64_t n_words = (n_windows + kTileSectors - 1) / kTileSectors;
-  const uint64_t n_waves = (uint64_t)gridDim.x * kScanWaves;
-  for (uint64_t t = (uint64_t)blockIdx.x * kScanWaves + wv; t < n_tasks; t += n_waves) {
-    // stage dwords [2048t, 2048t + 2080): window j starts at dword j. Staged
-    // dword q goes to row q / 32, column q % 32; lane l's loads are q = l + 64 i,
-    // i.e. row 2i + l / 32. A task inside the image loads from one base with
+  const uint64_t n_waves = (uint64_t)gridDim.x * kFragWaves;
+  for (uint64_t t = (uint64_t)blockIdx.x * kFragWaves + wv; t < n_tasks; t += n_waves) {
+    // stage dwords [1024t, 1024t + 1040): window j starts at dword j. Staged
+    // dword q goes to row q / 16, column q % 16; lane l's loads are q = l + 64 i,
+    // i.e. row 4i + l / 16. A task inside the image loads from one base with
     // constant offsets; the last one clamps to the image's last dword (only
     // windows past the end read the repeated words).
     const uint64_t dw0 = t * kWaveWindows;
-    constexpr uint32_t kStaged = kFragRows * kFragRowDw;   // 2080
+    constexpr uint32_t kStaged = kFragRows * kFragRowDw;   // 1040
     uint32_t* dst = my + (l / kFragRowDw) * kFragPitchDw + l % kFragRowDw;
+    constexpr uint32_t kRowsPerLoad = kWave / kFragRowDw;  // 4
     if (dw0 + kStaged <= n_dwords) {
       const uint32_t* src = image + dw0 + l;
 #pragma unroll
-      for (uint32_t i = 0; i < kStaged / kWave; ++i) dst[2 * kFragPitchDw * i] = __builtin_nontemporal_load(src + kWave * i);
-      if (l < kStaged % kWave) dst[2 * kFragPitchDw * (kStaged / kWave)] = __builtin_nontemporal_load(src + kWave * (kStaged / kWave));
+      for (uint32_t i = 0; i < kStaged / kWave; ++i)
+        dst[kRowsPerLoad * kFragPitchDw * i] = __builtin_nontemporal_load(src + kWave * i);
+      if (l < kStaged % kWave)
+        dst[kRowsPerLoad * kFragPitchDw * (kStaged / kWave)] = __builtin_nontemporal_load(src + kWave * (kStaged / kWave));
     } else {
 #pragma unroll 4
       for (uint32_t i = 0; i <= kStaged / kWave; ++i) {
@@ -99,12 +121,12 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
         if (q < kStaged) {
           uint64_t g = dw0 + q;
           if (g >= n_dwords) g = n_dwords - 1;
-          dst[2 * kFragPitchDw * i] = image[g];
+          dst[kRowsPerLoad * kFragPitchDw * i] = image[g];
         }
       }
     }
     wave_sync_lds();
-    // lane l's word k (k < 48) of its stream: row l, then row l + 1 (one pad word between)
+    // lane l's word k (k < 32) of its stream: row l, then row l + 1 (one pad word between)
     const uint32_t* row = my + l * kFragPitchDw;
     auto word = [&](uint32_t k) { return row[k + (k >= kFragRowDw ? kFragPitchDw - kFragRowDw : 0u)]; };
     const uint64_t j0 = dw0 + (uint64_t)l * kLaneWindows;
@@ -114,8 +136,9 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
 #pragma unroll
     for (uint32_t k = 0; k < 16; ++k) H = H * kPow4 + word_djb2(row[k]);
     uint32_t mask = 0;
-    // batches of 8 windows: 8 signatures, their 8 filter words in flight
-    // together, then the (rare) windows that pass go through the table probe
+    // batches of 8 windows: 8 signatures; the LDS filter; Bloom words only for
+    // the windows that pass it, in flight together; then the (rare) windows
+    // that pass both go through the table probe
 #pragma unroll 1
     for (uint32_t b = 0; b < kLaneWindows; b += 8) {
       uint64_t h[8];
@@ -127,13 +150,19 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
         H = H * kPow4 - kPow64 * word_djb2(word(w)) + word_djb2(word(w + 16));
       }
       uint32_t pend = valid <= b ? 0u : (valid - b >= 8 ? 0xFFu : (1u << (valid - b)) - 1u);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        uint32_t wi, bits;
+        lds_filter_place(h[i], lw, &wi, &bits);
+        if (h[i] != kEmptyKey && (lfilter[wi] & bits) != bits) pend &= ~(1u << i);
+      }
       if (ix.bloom) {
         uint64_t bits[8], fw[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           uint32_t wi;
           bloom_place(h[i], ix.log2_bloom_words, &wi, &bits[i]);
-          fw[i] = ix.bloom[wi];
+          fw[i] = ((pend >> i) & 1u) ? ix.bloom[wi] : ~0ull;
         }
         uint32_t pass = 0;
 #pragma unroll
@@ -159,9 +188,13 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
       }
     }
-    const uint32_t hi = (uint32_t)__shfl_down((int)mask, 1, kWave);
-    const uint64_t wi = t * (kWaveWindows / kTileSectors) + l / 2;
-    if ((l & 1u) == 0 && wi < n_words) out[wi] = (uint64_t)mask | ((uint64_t)hi << 32);
+    // four lanes' 16-bit masks make one 64-bit hit word
+    const uint32_t m1 = (uint32_t)__shfl_down((int)mask, 1, kWave);
+    const uint32_t m2 = (uint32_t)__shfl_down((int)mask, 2, kWave);
+    const uint32_t m3 = (uint32_t)__shfl_down((int)mask, 3, kWave);
+    const uint64_t wi = t * (kWaveWindows / kTileSectors) + l / 4;
+    if ((l & 3u) == 0 && wi < n_words)
+      out[wi] = (uint64_t)(mask | (m1 << 16)) | ((uint64_t)(m2 | (m3 << 16)) << 32);
     wave_sync_lds();   // this task's rows are read before the next task's stores
   }
 }
