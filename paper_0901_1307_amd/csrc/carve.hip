@@ -3,22 +3,28 @@
 // A scan covers one image or a batch of images. Their sectors form one tile
 // space: image after image, each padded to whole 64-sector tiles. Every
 // kernel below indexes that space, so a batch of uneven images costs no more
-// launches than one image.
+// launches than one image. A fragment scan (Section 5) uses the same space
+// with 64-byte windows at 4-byte steps as its units.
 //
 // Pipeline of a scan (Sections 3.1-3.2):
-//   k_scan<kFlags>    sector loads -> djb2-64 -> cluster position -> index
-//                     probe -> one 64-bit hit word per tile (ballot); the
+//   k_scan<kFlags>    sector loads -> djb2-64 or CRC-64 -> cluster position ->
+//                     index probe (bucketed, linear or sorted layout, Bloom
+//                     prefilter) -> one 64-bit hit word per tile (ballot); the
 //                     matched slot of each flagged sector is recorded
+//                     (carve_scan_kernel.h; k_frag_scan in
+//                     carve_fragment_kernel.h for fragments)
 //   k_reduce / k_scan_blocks / k_apply<EmitIds>   popcount prefix ->
-//                     ascending flagged sector ids (per image, image order)
+//                     ascending flagged ids (per image, image order)
 //   k_image_offsets   (batches) where each image's ids start
-// Confirmation (Section 3.1), from the slot each flagged sector matched:
-//   k_confirm_count   512-byte comparison with every compatible candidate
-//   prefix sum        output offsets
+// Confirmation (Section 3.1), from the slot each flagged unit matched:
+//   k_confirm_count   byte comparison with every compatible candidate
+//   prefix sum        output offsets (counts read on the device)
 //   k_confirm_emit    ordered match records
+//   k_stage_out       (server) counts, ids and records into pinned host memory
 // Index build (Section 3.1, Eq. (3)):
-//   k_master_meta, k_scan<kSigs>, k_insert, k_narrow_masks, k_scatter,
-//   k_sort_segments, k_bloom_build.
+//   k_master_meta, k_scan<kSigs> / k_frag_sigs, k_insert, k_narrow_masks,
+//   k_scatter, k_sort_segments, k_bloom_build; k_occupied, k_insert_linear and
+//   a radix sort for the other layouts; k_lds_filter_build for fragments.
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdint.h>
@@ -370,7 +376,12 @@ struct ConfirmView {
   const uint8_t* masters;     // packed master sectors
 };
 
-constexpr int kConfirmLanes = 16;   // lanes per flagged sector: 32 B each
+// Lanes per flagged unit in the confirmation count: 16 x 32 B for a sector,
+// 4 x 16 B for a 64-byte window.
+template <class Src>
+constexpr uint32_t confirm_lanes() {
+  return Src::kUnitBytes == kSectorBytes ? 16u : 4u;
+}
 
 __device__ __forceinline__ bool compatible(const ConfirmView& cv, uint32_t m, uint32_t tau, uint32_t any_tau) {
   return any_tau || (cv.m_k[m] & (kClusterSectors - 1)) == tau;
@@ -396,9 +407,10 @@ __device__ __forceinline__ Flagged flagged(const Src& src, const uint64_t* ids, 
                  Src::kAnyPosition ? 1u : d.any_tau, hit_slot[d.tile_begin * kTileSectors + j]};
 }
 
-// 16 lanes per flagged sector: compare its 512 bytes with every candidate
-// master sector of its slot at a compatible cluster position. Records the
-// number of equal ones and, for the first 64 compatible candidates, which.
+// A group of lanes per flagged unit (16 for a sector, 4 for a window):
+// compare its bytes with every candidate master unit of its slot at a
+// compatible cluster position. Records the number of equal ones and, for the
+// first 64 compatible candidates, which.
 template <class Src>
 __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const uint64_t* __restrict__ ids,
                                                                 const uint32_t* __restrict__ img_of,
@@ -406,37 +418,40 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
                                                                 const uint32_t* __restrict__ hit_slot, ConfirmView cv,
                                                                 uint32_t* __restrict__ n_match,
                                                                 uint64_t* __restrict__ match_mask) {
+  constexpr uint32_t kLanes = confirm_lanes<Src>();
+  constexpr uint64_t kGroupMask = (1ull << kLanes) - 1ull;
   const uint64_t n_flagged = count.get();
   const uint32_t l = lane_id();
-  const uint32_t g = l / kConfirmLanes, gl = l % kConfirmLanes;
-  const uint64_t per_block = kBlockThreads / kConfirmLanes;
+  const uint32_t g = l / kLanes, gl = l % kLanes;
+  const uint64_t per_block = kBlockThreads / kLanes;
   const uint64_t n_groups = (uint64_t)gridDim.x * per_block;
-  for (uint64_t i = (uint64_t)blockIdx.x * per_block + threadIdx.x / kConfirmLanes; i < n_flagged; i += n_groups) {
+  for (uint64_t i = (uint64_t)blockIdx.x * per_block + threadIdx.x / kLanes; i < n_flagged; i += n_groups) {
     const Flagged f = flagged(src, ids, img_of, hit_slot, i);
-    // this lane's share of the unit: 2 x 16 B of a sector, or 4 B of a 64-byte window
-    // (windows are only 4-byte aligned)
+    // this lane's share of the unit: 2 x 16 B of a sector, or 16 B of a 64-byte
+    // window read as 4 words (windows are only 4-byte aligned)
     u32x4 d0 = {}, d1 = {};
     if constexpr (Src::kUnitBytes == kSectorBytes) {
       const u32x4* d = (const u32x4*)f.bytes + gl;
       d0 = d[0];
-      d1 = d[kConfirmLanes];
+      d1 = d[kLanes];
     } else {
-      d0.x = ((const uint32_t*)f.bytes)[gl];
+      const uint32_t* d = (const uint32_t*)f.bytes + 4 * gl;
+      d0 = u32x4{d[0], d[1], d[2], d[3]};
     }
     uint32_t cnt = 0, rank = 0;
     uint64_t mask = 0;
     for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e; ++c) {
       const uint32_t m = cv.cand[c];
-      if (!compatible(cv, m, f.tau, f.any_tau)) continue;   // same decision in all 16 lanes
+      if (!compatible(cv, m, f.tau, f.any_tau)) continue;   // same decision in all lanes of the group
       u32x4 x;
       if constexpr (Src::kUnitBytes == kSectorBytes) {
         const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * kSectorBytes) + gl;
-        x = (d0 ^ q[0]) | (d1 ^ q[kConfirmLanes]);
-      } else {
-        x = u32x4{d0.x ^ ((const uint32_t*)(cv.masters + (uint64_t)m * Src::kUnitBytes))[gl], 0u, 0u, 0u};
+        x = (d0 ^ q[0]) | (d1 ^ q[kLanes]);
+      } else {   // master fragments are 64-byte aligned
+        x = d0 ^ ((const u32x4*)(cv.masters + (uint64_t)m * Src::kUnitBytes))[gl];
       }
       const uint64_t diff = ballot((x.x | x.y | x.z | x.w) != 0);
-      if (((diff >> (g * kConfirmLanes)) & 0xFFFFull) == 0) {
+      if (((diff >> (g * kLanes)) & kGroupMask) == 0) {
         ++cnt;
         if (rank < 64) mask |= 1ull << rank;
       }
@@ -896,7 +911,7 @@ int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src,
   sc->rec_cap = dest ? 0 : rec_cap;
   const ConfirmView cv = idx->cview();
   const uint32_t* img_of = sc->batch ? sc->img_of.as<uint32_t>() : nullptr;
-  const uint64_t per_block = kBlockThreads / kConfirmLanes;
+  const uint64_t per_block = kBlockThreads / confirm_lanes<Src>();
   const Count nf{cap_f, d_count};
   k_confirm_count<Src><<<resident_grid(k_confirm_count<Src>, kBlockThreads, cdiv(cap_f, per_block)), kBlockThreads,
                          0, s>>>(src, sc->ids.as<uint64_t>(), img_of, nf, sc->hit_slot.as<uint32_t>(), cv,
