@@ -156,7 +156,7 @@ int build_master_index(const void* master_sectors, const uint64_t* file_sector_o
  *              (its previous results are discarded; it must not be in use on
  *              another stream). out: the scan object (release with free_scan).
  * Errors: EINVAL (null idx/io, null or misaligned image with n_bytes >= 512,
- * tau0 > 7, bad tau_mode), ENOMEM, EDEVICE.
+ * an image in host memory, tau0 > 7, bad tau_mode), ENOMEM, EDEVICE.
  */
 int scan_image(const carve_index* idx, const void* image, uint64_t n_bytes, uint32_t tau0, uint32_t tau_mode,
                void* stream, carve_scan** io);
@@ -229,7 +229,7 @@ int build_fragment_index(const void* master_fragments, const uint64_t* file_frag
 /* scan_fragments -- flag every window of a device-resident image (16-B
  * aligned; any n_bytes; fewer than 64 bytes gives no window). Asynchronous on
  * `stream`; *io as scan_image (reused when non-null). EINVAL for a sector
- * index, a null or misaligned image, or a batch object. */
+ * index, a null, misaligned or host-memory image, or a batch object. */
 int scan_fragments(const carve_index* idx, const void* image, uint64_t n_bytes, void* stream, carve_scan** io);
 
 /* ---------------------------------------------------------------- host ingest
@@ -376,12 +376,18 @@ typedef struct {
  * budget_bytes / n_streams (about 40 bytes per 512-byte sector: ids, match
  * slots, confirmation scratch, records), so serving allocates nothing unless a
  * batch exceeds that share; pinned host memory holds one such batch's ids and
- * records per lane. EINVAL for n_streams > 64 or max_jobs_per_batch > 65536. */
+ * records per lane; the first host-memory job of a lane allocates its arena
+ * (the lane's share of the budget). EINVAL for n_streams > 64 or
+ * max_jobs_per_batch > 65536. */
 int server_create(const carve_index* idx, const carve_server_params* params, carve_server** out);
 
 /* server_submit -- queue a job (host descriptor, image BORROWED until the job is
- * released). EINVAL for a bad descriptor, EUNSUPPORTED when the job alone exceeds
- * the budget. *job_id receives its id. Does not launch anything. */
+ * released). The image may be in device memory, or in host memory (sectors
+ * arriving from disks through host memory, Section 3.1): a host job is copied
+ * into its lane's device arena at launch, asynchronously when the memory is
+ * pinned (hipHostMalloc), blocking the polling thread while it copies when it
+ * is pageable. EINVAL for a bad descriptor, EUNSUPPORTED when the job alone
+ * exceeds the budget. *job_id receives its id. Does not launch anything. */
 int server_submit(carve_server* s, const carve_image_desc* job, uint64_t* job_id);
 
 /* server_submit_many -- server_submit of jobs[0..n) in order, ids into

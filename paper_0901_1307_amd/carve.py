@@ -210,6 +210,14 @@ def _stream_ptr(stream) -> Optional[int]:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def _u8_any(t: torch.Tensor, what: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type not in ("cuda", "cpu"):
+        raise TypeError(f"{what} must be a GPU or host tensor")
+    if t.dtype != torch.uint8 or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous uint8 tensor")
+    return t
+
+
 def _dev_u8(t: torch.Tensor, what: str) -> torch.Tensor:
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError(f"{what} must be a CUDA (HIP) tensor")
@@ -567,7 +575,9 @@ class Server:
         self._done = (_JobDone * 4096)()
 
     def submit(self, image: torch.Tensor, tau0: int = 0, tau_mode: int = CARVE_TAU_PER_CLUSTER) -> int:
-        t = _dev_u8(image, "image")
+        """image: a contiguous uint8 tensor on the GPU, or in host memory
+        (pinned for an asynchronous copy)."""
+        t = _u8_any(image, "image")
         d = _ImageDesc(t.data_ptr() if t.numel() else None, t.numel(), int(tau0), int(tau_mode))
         jid = ctypes.c_uint64()
         _check(load_library().server_submit(self.handle, ctypes.byref(d), ctypes.byref(jid)))
@@ -643,10 +653,10 @@ class Server:
 
 
 def image_descs(jobs) -> np.ndarray:
-    """IMAGE_DESC_DTYPE array from (uint8 device tensor, tau0, tau_mode) tuples."""
+    """IMAGE_DESC_DTYPE array from (uint8 GPU or host tensor, tau0, tau_mode) tuples."""
     out = np.zeros(len(jobs), dtype=IMAGE_DESC_DTYPE)
     for i, (t, tau0, mode) in enumerate(jobs):
-        t = _dev_u8(t, "image")
+        t = _u8_any(t, "image")
         out[i] = (t.data_ptr() if t.numel() else 0, t.numel(), int(tau0), int(mode))
     return out
 

@@ -782,6 +782,16 @@ int read_u64(carve_scan* sc, const uint64_t* d, uint64_t* h) {
   return CARVE_OK;
 }
 
+// Memory a kernel may read: device (or managed) memory, not host memory.
+bool gpu_readable(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();   // unknown to the runtime: plain host memory
+    return false;
+  }
+  return a.type != hipMemoryTypeUnregistered && a.type != hipMemoryTypeHost;
+}
+
 // Device memory the kernels can write directly (else: staging + copy).
 bool is_device_memory(const void* p) {
   hipPointerAttribute_t a;
@@ -1353,6 +1363,8 @@ extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_
   if (idx->unit_bytes != kSectorBytes)
     return fail(CARVE_EINVAL, "scan_image: a fragment index (use scan_fragments)");
   CARVE_TRY(validate_image(image, n_bytes, tau0, tau_mode, "scan_image", -1));
+  if (n_bytes >= kSectorBytes && !gpu_readable(image))
+    return fail(CARVE_EINVAL, "scan_image: image is not in device memory");
   if (*io && (*io)->batch) return fail(CARVE_EINVAL, "scan_image: io is a batch object");
   carve_scan* sc = *io;
   const bool created = !sc;
@@ -1389,6 +1401,8 @@ extern "C" int scan_fragments(const carve_index* idx, const void* image, uint64_
     return fail(CARVE_EINVAL, "scan_fragments: a sector index (build it with build_fragment_index)");
   if (n_bytes >= kFragBytes && !image) return fail(CARVE_EINVAL, "scan_fragments: null image");
   if ((uintptr_t)image % 16) return fail(CARVE_EINVAL, "scan_fragments: image not 16-byte aligned");
+  if (n_bytes >= kFragBytes && !gpu_readable(image))
+    return fail(CARVE_EINVAL, "scan_fragments: image is not in device memory");
   if (*io && (*io)->batch) return fail(CARVE_EINVAL, "scan_fragments: io is a batch object");
   carve_scan* sc = *io;
   const bool created = !sc;

@@ -14,11 +14,18 @@
 // workspace is sized at creation for its share of the budget, so serving
 // allocates and frees nothing (both synchronize the whole device) unless a
 // batch outgrows it.
+//
+// Jobs may also live in host memory (Section 3.1: sectors arrive from disks
+// through host memory). At launch such a job's whole sectors are copied into
+// the lane's device arena on the lane's stream, ahead of the scan; pinned
+// memory makes the copy asynchronous, pageable memory blocks the caller for
+// it. The arena is allocated on the first host job, sized to the lane's share.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <deque>
 #include <memory>
@@ -67,6 +74,7 @@ struct Results {
 struct Job {
   carve_image_desc desc{};
   uint64_t bytes = 0;
+  bool host = false;   // the image is in host memory (copied to the lane's arena at launch)
   int state = 0;   // 0 queued, 1 running, 2 done (reported), 3 done (to report)
   int32_t status = CARVE_OK;
   std::shared_ptr<Results> res;
@@ -81,6 +89,8 @@ struct Lane {
   uint64_t bytes = 0;
   bool busy = false;
   Pinned<uint64_t> stage;         // [0] flagged, [1] matches, then n_images + 1 id offsets
+  void* arena = nullptr;          // device copies of the batch's host-memory jobs
+  uint64_t arena_cap = 0;
   std::shared_ptr<Results> res;   // ids and records of the batch in flight
   uint64_t match_room = 0;        // records the device held for the stage-out
 };
@@ -191,6 +201,40 @@ int retire(carve_server* s, Lane& ln) {
   return rc;
 }
 
+// Host-memory jobs of the batch being launched: their whole sectors go to the
+// lane's arena (4 KiB-aligned slots) on the lane's stream, and their
+// descriptors point there.
+int stage_host_jobs(carve_server* s, Lane& ln) {
+  constexpr uint64_t kAlign = 4096;
+  uint64_t need = 0;
+  for (uint64_t id : ln.jobs) {
+    const Job& j = s->jobs[id];
+    if (j.host) need += (j.bytes + kAlign - 1) / kAlign * kAlign;
+  }
+  if (!need) return CARVE_OK;
+  if (need > ln.arena_cap) {
+    const uint64_t share = s->p.budget_bytes / s->lanes.size();
+    const uint64_t cap = std::max(need, (share + kAlign - 1) / kAlign * kAlign);
+    if (ln.arena) (void)hipFree(ln.arena);
+    ln.arena = nullptr;
+    ln.arena_cap = 0;
+    if (hipMalloc(&ln.arena, cap) != hipSuccess) return carve_fail_msg(CARVE_ENOMEM, "server: arena allocation failed");
+    ln.arena_cap = cap;
+  }
+  uint64_t at = 0;
+  for (size_t i = 0; i < ln.jobs.size(); ++i) {
+    const Job& j = s->jobs[ln.jobs[i]];
+    if (!j.host) continue;
+    uint8_t* dst = (uint8_t*)ln.arena + at;
+    if (j.bytes && hipMemcpyAsync(dst, j.desc.image, j.bytes, hipMemcpyHostToDevice, ln.stream) != hipSuccess)
+      return carve_fail_msg(CARVE_EDEVICE, "server: host job copy failed");
+    s->descs[i].image = dst;
+    s->descs[i].n_bytes = j.bytes;
+    at += (j.bytes + kAlign - 1) / kAlign * kAlign;
+  }
+  return CARVE_OK;
+}
+
 // Fill a free lane with queued jobs, oldest first, within the budget. A lane
 // takes at most its share of the budget (a job larger than that goes alone),
 // so at saturation the lanes' batches overlap instead of one lane holding it all.
@@ -210,7 +254,8 @@ int launch(carve_server* s, Lane& ln) {
     s->queue.pop_front();
   }
   if (ln.jobs.empty()) return CARVE_OK;
-  int rc = scan_batch(s->idx, s->descs.data(), (uint32_t)s->descs.size(), ln.stream, &ln.batch);
+  int rc = stage_host_jobs(s, ln);
+  if (rc == CARVE_OK) rc = scan_batch(s->idx, s->descs.data(), (uint32_t)s->descs.size(), ln.stream, &ln.batch);
   if (rc == CARVE_OK && s->p.confirm) rc = batch_confirm_enqueue(s->idx, ln.batch);
   if (rc == CARVE_OK) ln.res = s->new_results(results_room(ln.bytes / 512), &rc);
   if (rc == CARVE_OK && !ln.stage.reserve(ln.jobs.size() + 3))
@@ -302,11 +347,23 @@ int check_job(const carve_server* s, const carve_image_desc* job, long which) {
   return carve_fail_msg(code, msg);
 }
 
+// Host memory: pinned (hipHostMalloc) or plain pageable memory, which the
+// runtime reports as unregistered (or does not know at all).
+bool in_host_memory(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();   // clear the sticky error
+    return true;
+  }
+  return a.type == hipMemoryTypeUnregistered || a.type == hipMemoryTypeHost;
+}
+
 uint64_t enqueue_job(carve_server* s, const carve_image_desc* job) {
   const uint64_t id = s->next_id++;
   Job& j = s->jobs[id];
   j.desc = *job;
   j.bytes = job->n_bytes - job->n_bytes % 512;
+  j.host = j.bytes && in_host_memory(job->image);
   s->queue.push_back(id);
   return id;
 }
@@ -428,6 +485,7 @@ extern "C" void server_free(carve_server* s) {
     if (ln.stream) (void)hipStreamSynchronize(ln.stream);
     free_batch(ln.batch);
     ln.stage.release();
+    if (ln.arena) (void)hipFree(ln.arena);
     if (ln.done) (void)hipEventDestroy(ln.done);
     if (ln.stream) (void)hipStreamDestroy(ln.stream);
   }

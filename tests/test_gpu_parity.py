@@ -368,3 +368,17 @@ def test_confirm_into_device_memory(tiny_gpu):
     assert e.value.code == carve.CARVE_ETRUNC and str(len(m)) in str(e.value)
     first = np.frombuffer(short.cpu().numpy().tobytes(), dtype=carve.MATCH_DTYPE)
     assert_same_matches(first, m[:7])
+
+
+def test_host_memory_image_rejected(tiny_gpu):
+    """scan_image takes device memory: a pinned or pageable host image is refused
+    on the host (EINVAL), before any kernel runs."""
+    cfg, ms, img, idx = tiny_gpu
+    lib = carve.load_library()
+    pinned = torch.zeros(4096, dtype=torch.uint8, pin_memory=True)
+    pageable = torch.zeros(4096, dtype=torch.uint8)
+    for t in (pinned, pageable):
+        h = carve.ctypes.c_void_p()
+        rc = lib.scan_image(idx.handle, t.data_ptr(), t.numel(), 0, 0, None, carve.ctypes.byref(h))
+        assert rc == carve.CARVE_EINVAL and not h.value
+        assert b"device memory" in lib.carve_last_error()

@@ -169,3 +169,33 @@ def test_bulk_submit_poll_release(pool):
         srv.flags(int(ids[0]))                                   # released by the first call
     assert srv.stats()["done_jobs"] == 0
     srv.close()
+
+
+def test_host_memory_jobs(pool):
+    """Jobs in host memory (pinned and pageable) beside device jobs: each is
+    copied to its lane's device arena at launch, and every result equals the
+    same bytes scanned alone on the GPU."""
+    ms, idx, img = pool
+    part = img[: 64 << 20]
+    pinned = torch.empty(part.numel(), dtype=torch.uint8, pin_memory=True)
+    pinned.copy_(part.cpu())
+    pageable = pinned.clone()
+    jobs = _jobs(part, 60, seed=31, max_bytes=4 << 20)
+    srv = carve.Server(idx, n_streams=3, budget_bytes=48 << 20)
+    ids, where = [], []
+    for k, (t, tau0, mode) in enumerate(jobs):
+        off = t.data_ptr() - part.data_ptr()
+        src = (t, pinned, pageable)[k % 3]
+        if k % 3:
+            src = src[off: off + t.numel()]
+        ids.append(srv.submit(src, tau0, mode))
+        where.append(k % 3)
+    done = _drain(srv, ids)
+    assert srv.stats()["batches_launched"] > 1
+    for jid, (t, tau0, mode) in zip(ids, jobs):
+        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
+        assert done[jid] == (len(f), len(m))
+        assert np.array_equal(srv.flags(jid), f)
+        assert_same_matches(srv.matches(jid), m)
+    assert sum(done[j][0] for j, w in zip(ids, where) if w) > 0     # host jobs found something
+    srv.close()
