@@ -443,11 +443,23 @@ def run_served(args):
     idx = carve.build_master_index(ms.sectors, ms.file_offsets)
     pool = synth.disk_image(cfg, ms, device="cuda").data
     pool_sectors = pool.numel() // 512
-    specs = synth.served_job_specs(cfg.seed, rate=args.rate, duration=args.duration)
+    rate = args.rate if args.rate is not None else (1500.0 if args.host_jobs else 2000.0)
+    src = pool
+    h2d = None
+    if args.host_jobs:   # jobs arrive in (pinned) host memory and cross PCIe
+        src = torch.empty(pool.numel(), dtype=torch.uint8, pin_memory=True)
+        src.copy_(pool.cpu())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(3):
+            pool.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        h2d = 3 * pool.numel() / (time.perf_counter() - t1) / 1e9
+    specs = synth.served_job_specs(cfg.seed, rate=rate, duration=args.duration)
     firsts = synth.served_job_slices(specs, pool_sectors, cfg.seed)
     jobs = []
     for (t, size, flow), first in zip(specs, firsts):
-        view = pool[first * 512: first * 512 + size]
+        view = src[first * 512: first * 512 + size]
         jobs.append((t, view, first % 8 if not flow else 0,
                      carve.CARVE_TAU_ANY if flow else carve.CARVE_TAU_PER_CLUSTER))
     log(f"[bench] served: {len(jobs)} jobs over {args.duration:.0f} s, "
@@ -511,6 +523,27 @@ def run_served(args):
     log(f"[bench] closed loop: {len(sub)} jobs, {sub_bytes / 1e9:.1f} GB in {t_closed:.2f} s = {capacity:.0f} GB/s")
     st = srv.stats()
     srv.close()
+    workload = (f"served: Poisson arrivals at {rate:.0f}/s for {args.duration:.0f} s, sizes "
+                f"log-uniform 64 KiB-256 MiB (flow buffers < 1 MiB matched at any position), "
+                f"{'pinned host-memory' if args.host_jobs else 'device-resident'} pool, resident index of "
+                f"{cfg.n_master_sectors} master sectors, 32 GiB admission budget, {args.lanes} stream lanes, "
+                f"confirmation on")
+    common = {
+        "metric": METRIC, "value": round(sustained, 2), "unit": "GB/s", "n_gpus": 1, "steps": n,
+        "warmup": 64, "ms_per_step": round(elapsed * 1e3 / n, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": workload, "jobs": n, "bytes": bytes_done, "host_jobs": bool(args.host_jobs)},
+        "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "max": round(pmax, 4),
+                       "excluded_warmup_s": 5.0 if args.duration > 10 else 0.0},
+        "offered_GBps": round(bytes_done / args.duration / 1e9, 2),
+        "saturation_GBps": round(capacity, 1),
+        "flagged": flags, "confirmed": confirmed,
+    }
+    if args.host_jobs:   # PCIe-bound: compare with a plain host-to-device copy
+        log(f"[bench] plain pinned host-to-device copy: {h2d:.1f} GB/s")
+        common.update({"h2d_copy_GBps": round(h2d, 2), "saturation_vs_copy": round(capacity / h2d, 3)})
+        print(json.dumps(common), flush=True)
+        return
     # reference: the same closed-loop jobs as one batch through the plain
     # batch path (scan, every image's ids and confirmed matches to the host)
     ref_jobs = [(v, tau0, mode) for _, v, tau0, mode in sub]
@@ -552,25 +585,10 @@ def run_served(args):
     plain = pool.numel() * 10 / (time.perf_counter() - t3) / 1e9
     log(f"[bench] same jobs as one batch: {ref_gbps:.0f} GB/s; plain path over the pool: {plain:.0f} GB/s; "
         f"server host time: launch {st['host_launch_s']:.2f} s, retire {st['host_retire_s']:.2f} s")
-    out = {
-        "metric": METRIC, "value": round(sustained, 2), "unit": "GB/s", "n_gpus": 1, "steps": n,
-        "warmup": 64, "ms_per_step": round(elapsed * 1e3 / n, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": (f"served: Poisson arrivals at {args.rate:.0f}/s for {args.duration:.0f} s, sizes "
-                                f"log-uniform 64 KiB-256 MiB (flow buffers < 1 MiB matched at any position), "
-                                f"device-resident pool, resident index of {cfg.n_master_sectors} master sectors, "
-                                f"32 GiB admission budget, {args.lanes} stream lanes, confirmation on"),
-                   "jobs": n, "bytes": bytes_done},
-        "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "max": round(pmax, 4),
-                       "excluded_warmup_s": 5.0 if args.duration > 10 else 0.0},
-        "offered_GBps": round(bytes_done / args.duration / 1e9, 2),
-        "saturation_GBps": round(capacity, 1),
-        "same_jobs_one_batch_GBps": round(ref_gbps, 1),
-        "saturation_vs_one_batch": round(capacity / ref_gbps, 3),
-        "plain_path_whole_pool_GBps": round(plain, 1),
-        "flagged": flags, "confirmed": confirmed,
-    }
-    print(json.dumps(out), flush=True)
+    common.update({"same_jobs_one_batch_GBps": round(ref_gbps, 1),
+                   "saturation_vs_one_batch": round(capacity / ref_gbps, 3),
+                   "plain_path_whole_pool_GBps": round(plain, 1)})
+    print(json.dumps(common), flush=True)
 
 
 def main():
@@ -589,7 +607,10 @@ def main():
     ap.add_argument("--sig", default="djb2", choices=["djb2", "crc64"],
                     help="plain: sector signature (djb2-64 of Eq. (1), or the CRC-64 of Section 2.1)")
     ap.add_argument("--images", type=int, default=256, help="batched: number of images")
-    ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="served: arrivals per second (2000; 1500 with --host-jobs, under the PCIe rate)")
+    ap.add_argument("--host-jobs", action="store_true",
+                    help="served: jobs arrive in pinned host memory and cross PCIe")
     ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
     ap.add_argument("--lanes", type=int, default=4, help="served: stream lanes")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
