@@ -1294,9 +1294,9 @@ int build_index(const void* master_sectors, const uint64_t* file_sector_offsets,
     // the distinct signatures counted above include signature 0, which has no slot
     if ((rc = build_layout(ix, p, h_unique - (zmask ? 1 : 0), s))) return bail2(rc);
   }
-  if (unit == kFragBytes) {   // first-level filter: about 16 bits per signature, 1-64 KiB (always present)
+  if (unit == kFragBytes) {   // first-level filter: about 16 bits per signature, 1-128 KiB (always present)
     uint32_t lw = 8;
-    while (lw < 14 && (32ull << lw) < 16 * h_unique) ++lw;
+    while ((1u << (lw + 1)) <= kLdsFilterMaxWords && (32ull << lw) < 16 * h_unique) ++lw;
     if ((rc = ix->lds_filter.reserve(4ull << lw))) return bail2(rc);
     ix->log2_lds_words = lw;
     if (hipMemsetAsync(ix->lds_filter.p, 0, 4ull << lw, s) != hipSuccess)

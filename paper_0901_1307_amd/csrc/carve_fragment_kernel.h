@@ -18,10 +18,7 @@ constexpr uint32_t kFragWaves = kFragThreads / kWave;
 constexpr uint32_t kLaneWindows = 16;                        // consecutive windows per lane
 constexpr uint32_t kWaveWindows = kWave * kLaneWindows;      // 1024 windows = 4 KiB of image per wave task
 constexpr uint32_t kFragRowDw = kLaneWindows;                // a lane's own 64 bytes, in dwords
-constexpr uint32_t kFragPitchDw = kFragRowDw + 1;            // odd pitch: the 64 lane rows start in distinct banks
-constexpr uint32_t kFragRows = kWave + 1;                    // + the next task's first row (windows overlap it)
-constexpr uint32_t kFragLdsDw = kFragRows * kFragPitchDw;    // 1105 dwords per wave
-constexpr uint32_t kLdsFilterMaxWords = 1u << 14;            // 64 KiB: the first filter, in LDS
+constexpr uint32_t kLdsFilterMaxWords = 1u << 15;            // 128 KiB: the first filter, in LDS
 
 // First-level filter: a bitmap of 32-bit words in LDS; a signature sets 2 bits
 // of one word, placed by a multiplicative hash independent of the Bloom
@@ -82,64 +79,64 @@ struct FragmentWindows {
 // (W = waves in the grid). Task t: windows [1024t, 1024t + 1024); lane l
 // rolls over windows 16l..16l+15 of it, and lanes 4m..4m+3 make hit word
 // 16t + m (bit b = window 64(16t+m)+b). For each hit the matched table slot
-// goes to hit_slot[window].
+// goes to hit_slot[window]. The block's LDS holds only the first filter; the
+// image goes straight to registers.
 __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_frag_scan(
     const uint32_t* __restrict__ image, uint64_t n_windows, uint64_t n_dwords, IndexView ix,
     uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
-  __shared__ uint32_t lds[kFragWaves * kFragLdsDw];
   __shared__ uint32_t lfilter[kLdsFilterMaxWords];
   const uint32_t lw = ix.log2_lds_words;
   for (uint32_t i = threadIdx.x; i < (1u << lw); i += kFragThreads) lfilter[i] = ix.lds_filter[i];
   __syncthreads();   // before any wave of the block can leave
   const uint32_t wv = threadIdx.x / kWave;
   const uint32_t l = lane_id();
-  uint32_t* my = lds + wv * kFragLdsDw;
   const uint64_t n_tasks = (n_windows + kWaveWindows - 1) / kWaveWindows;
   const uint64_t n_words = (n_windows + kTileSectors - 1) / kTileSectors;
   const uint64_t n_waves = (uint64_t)gridDim.x * kFragWaves;
   for (uint64_t t = (uint64_t)blockIdx.x * kFragWaves + wv; t < n_tasks; t += n_waves) {
-    // stage dwords [1024t, 1024t + 1040): window j starts at dword j. Staged
-    // dword q goes to row q / 16, column q % 16; lane l's loads are q = l + 64 i,
-    // i.e. row 4i + l / 16. A task inside the image loads from one base with
-    // constant offsets; the last one clamps to the image's last dword (only
-    // windows past the end read the repeated words).
+    // Lane l's windows read dwords [16l, 16l + 32) of the task (dword dw0 =
+    // window 1024t): its own 16 (own[k] = dword 16l + k) and the next lane's.
+    // Lane 63's second 16 are the next task's first words, which lanes 0-15
+    // load (ext). Inside the image these are 16-byte loads; the last task
+    // clamps every dword to the image's last one (only windows past the end
+    // read the repeated words).
     const uint64_t dw0 = t * kWaveWindows;
-    constexpr uint32_t kStaged = kFragRows * kFragRowDw;   // 1040
-    uint32_t* dst = my + (l / kFragRowDw) * kFragPitchDw + l % kFragRowDw;
-    constexpr uint32_t kRowsPerLoad = kWave / kFragRowDw;  // 4
-    if (dw0 + kStaged <= n_dwords) {
-      const uint32_t* src = image + dw0 + l;
+    uint32_t own[kFragRowDw], ext;
+    if (dw0 + kWaveWindows + kFragRowDw <= n_dwords) {
+      const uint32_t* src = image + dw0 + (uint64_t)l * kFragRowDw;
 #pragma unroll
-      for (uint32_t i = 0; i < kStaged / kWave; ++i)
-        dst[kRowsPerLoad * kFragPitchDw * i] = __builtin_nontemporal_load(src + kWave * i);
-      if (l < kStaged % kWave)
-        dst[kRowsPerLoad * kFragPitchDw * (kStaged / kWave)] = __builtin_nontemporal_load(src + kWave * (kStaged / kWave));
-    } else {
-#pragma unroll 4
-      for (uint32_t i = 0; i <= kStaged / kWave; ++i) {
-        const uint32_t q = l + kWave * i;
-        if (q < kStaged) {
-          uint64_t g = dw0 + q;
-          if (g >= n_dwords) g = n_dwords - 1;
-          dst[kRowsPerLoad * kFragPitchDw * i] = image[g];
-        }
+      for (uint32_t q = 0; q < kFragRowDw / 4; ++q) {
+        const u32x4 v = __builtin_nontemporal_load((const u32x4*)(src + 4 * q));
+        own[4 * q] = v.x, own[4 * q + 1] = v.y, own[4 * q + 2] = v.z, own[4 * q + 3] = v.w;
       }
+      ext = __builtin_nontemporal_load(image + dw0 + kWaveWindows + (l % kFragRowDw));
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < kFragRowDw; ++k) {
+        const uint64_t g = dw0 + (uint64_t)l * kFragRowDw + k;
+        own[k] = image[g < n_dwords ? g : n_dwords - 1];
+      }
+      const uint64_t g = dw0 + kWaveWindows + (l % kFragRowDw);
+      ext = image[g < n_dwords ? g : n_dwords - 1];
     }
-    wave_sync_lds();
-    // lane l's word k (k < 32) of its stream: row l, then row l + 1 (one pad word between)
-    const uint32_t* row = my + l * kFragPitchDw;
-    auto word = [&](uint32_t k) { return row[k + (k >= kFragRowDw ? kFragPitchDw - kFragRowDw : 0u)]; };
+    // word 16 + k of lane l's stream: the next lane's own[k]; for lane 63,
+    // lane k's ext (the whole wave runs this code, so every source lane is active)
+    auto second = [&](uint32_t k) {
+      const uint32_t next_lane = (uint32_t)__shfl_down((int)own[k], 1, kWave);
+      const uint32_t from_ext = (uint32_t)__builtin_amdgcn_readlane((int)ext, (int)k);
+      return l == kWave - 1 ? from_ext : next_lane;
+    };
     const uint64_t j0 = dw0 + (uint64_t)l * kLaneWindows;
     const uint32_t valid = j0 >= n_windows ? 0u : (n_windows - j0 >= kLaneWindows ? kLaneWindows
                                                                                    : (uint32_t)(n_windows - j0));
     uint64_t H = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < 16; ++k) H = H * kPow4 + word_djb2(row[k]);
+    for (uint32_t k = 0; k < kFragRowDw; ++k) H = H * kPow4 + word_djb2(own[k]);
     uint32_t mask = 0;
     // batches of 8 windows: 8 signatures; the LDS filter; Bloom words only for
     // the windows that pass it, in flight together; then the (rare) windows
     // that pass both go through the table probe
-#pragma unroll 1
+#pragma unroll
     for (uint32_t b = 0; b < kLaneWindows; b += 8) {
       uint64_t h[8];
 #pragma unroll
@@ -147,7 +144,7 @@ __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4)
         const uint32_t w = b + i;
         h[i] = kFragInit + H;
         // roll to window w + 1 (after the last window the result is unused)
-        H = H * kPow4 - kPow64 * word_djb2(word(w)) + word_djb2(word(w + 16));
+        H = H * kPow4 - kPow64 * word_djb2(own[w]) + word_djb2(second(w));
       }
       uint32_t pend = valid <= b ? 0u : (valid - b >= 8 ? 0xFFu : (1u << (valid - b)) - 1u);
 #pragma unroll
@@ -195,7 +192,6 @@ __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4)
     const uint64_t wi = t * (kWaveWindows / kTileSectors) + l / 4;
     if ((l & 3u) == 0 && wi < n_words)
       out[wi] = (uint64_t)(mask | (m1 << 16)) | ((uint64_t)(m2 | (m3 << 16)) << 32);
-    wave_sync_lds();   // this task's rows are read before the next task's stores
   }
 }
 
