@@ -76,7 +76,8 @@ typedef struct {
                                   (bucketed: keys per slot; linear: distinct signatures per slot;
                                   sorted: unused) */
   uint32_t bloom_bits_per_key; /* prefilter in front of the table: 0 = automatic (at least 4 bits per
-                                  distinct signature, then as many as a 4 MiB filter and 16 bits allow),
+                                  distinct signature, then as many as a 4 MiB filter and 16 bits allow;
+                                  32 bits for a fragment index),
                                   CARVE_BLOOM_OFF = none, else 4..64 bits per signature */
   uint32_t layout;             /* carve_index_layout; 0 = bucketed */
   uint32_t reserved[4];        /* must be zero */

@@ -70,19 +70,24 @@ struct PopcountItems {
   __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return (uint64_t)__popcll(words[i]); }
 };
 
+// Items are taken in chunks of kItemsPerBlock, chunk c = items [c kItemsPerBlock,
+// (c + 1) kItemsPerBlock); a block handles chunks blockIdx.x, + gridDim.x, ...
+// so a grid sized for a count read on the device need not cover its upper
+// bound. Chunks past the count are not touched (their sums are not scanned).
 template <class Items>
 __global__ __launch_bounds__(kBlockThreads) void k_reduce(Items items, Count count, uint64_t* __restrict__ blk_sums) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
   const uint64_t n = count.get();
-  if ((uint64_t)blockIdx.x * kItemsPerBlock >= n) return;   // the whole block: no items (sum not scanned)
-  const uint64_t base = (uint64_t)blockIdx.x * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
-  uint64_t s = 0;
+  for (uint64_t c = blockIdx.x; c * kItemsPerBlock < n; c += gridDim.x) {
+    const uint64_t base = c * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
+    uint64_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kItemsPerThread; ++k)
-    if (base + k < n) s += items(base + k);
-  uint64_t total;
-  block_exclusive_scan<kBlockThreads>(s, lds_w, &total);
-  if (threadIdx.x == 0) blk_sums[blockIdx.x] = total;
+    for (int k = 0; k < kItemsPerThread; ++k)
+      if (base + k < n) s += items(base + k);
+    uint64_t total;
+    block_exclusive_scan<kBlockThreads>(s, lds_w, &total);
+    if (threadIdx.x == 0) blk_sums[c] = total;
+  }
 }
 
 // One block: exclusive offsets of the block sums; total into *total. Only
@@ -137,25 +142,27 @@ struct EmitOffsets {
   __device__ __forceinline__ void emit(uint64_t i, uint64_t pos) const { out[i] = (T)pos; }
 };
 
+// Chunks as in k_reduce.
 template <class Emit>
 __global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, Count count, const uint64_t* __restrict__ blk_off) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
   const uint64_t n = count.get();
-  if ((uint64_t)blockIdx.x * kItemsPerBlock >= n) return;   // the whole block: no items (offset not scanned)
-  const uint64_t base = (uint64_t)blockIdx.x * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
-  uint64_t c[kItemsPerThread];
-  uint64_t s = 0;
+  for (uint64_t ch = blockIdx.x; ch * kItemsPerBlock < n; ch += gridDim.x) {
+    const uint64_t base = ch * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
+    uint64_t c[kItemsPerThread];
+    uint64_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kItemsPerThread; ++k) {
-    c[k] = (base + k < n) ? e.count(base + k) : 0;
-    s += c[k];
-  }
-  uint64_t total;
-  uint64_t pos = blk_off[blockIdx.x] + block_exclusive_scan<kBlockThreads>(s, lds_w, &total);
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      c[k] = (base + k < n) ? e.count(base + k) : 0;
+      s += c[k];
+    }
+    uint64_t total;
+    uint64_t pos = blk_off[ch] + block_exclusive_scan<kBlockThreads>(s, lds_w, &total);
 #pragma unroll
-  for (int k = 0; k < kItemsPerThread; ++k) {
-    if (base + k < n) e.emit(base + k, pos);
-    pos += c[k];
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      if (base + k < n) e.emit(base + k, pos);
+      pos += c[k];
+    }
   }
 }
 
@@ -292,14 +299,23 @@ __global__ void k_bloom_build(const uint64_t* __restrict__ keys, uint64_t n_slot
   atomicOr((unsigned long long*)(bloom + w), (unsigned long long)bits);
 }
 
-// The fragment scan's first-level filter (placed like lds_filter_place).
+// The fragment scan's two filters (placed by frag_lds_place and
+// frag_bloom_place; 32-bit words).
 __global__ void k_lds_filter_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t log2_words,
                                    uint32_t* filter) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_slots || keys[i] == kEmptyKey) return;
   uint32_t w, bits;
-  lds_filter_place(keys[i], log2_words, &w, &bits);
+  frag_lds_place(keys[i], log2_words, &w, &bits);
   atomicOr(&filter[w], bits);
+}
+__global__ void k_frag_bloom_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t log2_words,
+                                   uint32_t* bloom) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slots || keys[i] == kEmptyKey) return;
+  uint32_t w, bits;
+  frag_bloom_place(keys[i], log2_words, &w, &bits);
+  atomicOr(&bloom[w], bits);
 }
 
 // Other probe layouts. The distinct signatures of the table with their slots
@@ -376,11 +392,13 @@ struct ConfirmView {
   const uint8_t* masters;     // packed master sectors
 };
 
-// Lanes per flagged unit in the confirmation count: 16 x 32 B for a sector,
-// 4 x 16 B for a 64-byte window.
+// Lanes per flagged unit in the confirmation count: 16 x 32 B for a sector;
+// one lane for a 64-byte window (its chain of dependent loads, id -> slot ->
+// candidate list -> master, is what takes the time, so more windows in
+// flight beat sharing the compare).
 template <class Src>
 constexpr uint32_t confirm_lanes() {
-  return Src::kUnitBytes == kSectorBytes ? 16u : 4u;
+  return Src::kUnitBytes == kSectorBytes ? 16u : 1u;
 }
 
 __device__ __forceinline__ bool compatible(const ConfirmView& cv, uint32_t m, uint32_t tau, uint32_t any_tau) {
@@ -407,7 +425,7 @@ __device__ __forceinline__ Flagged flagged(const Src& src, const uint64_t* ids, 
                  Src::kAnyPosition ? 1u : d.any_tau, hit_slot[d.tile_begin * kTileSectors + j]};
 }
 
-// A group of lanes per flagged unit (16 for a sector, 4 for a window):
+// A group of lanes per flagged sector (16), or one lane per flagged window:
 // compare its bytes with every candidate master unit of its slot at a
 // compatible cluster position. Records the number of equal ones and, for the
 // first 64 compatible candidates, which.
@@ -421,45 +439,63 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
   constexpr uint32_t kLanes = confirm_lanes<Src>();
   constexpr uint64_t kGroupMask = (1ull << kLanes) - 1ull;
   const uint64_t n_flagged = count.get();
-  const uint32_t l = lane_id();
-  const uint32_t g = l / kLanes, gl = l % kLanes;
-  const uint64_t per_block = kBlockThreads / kLanes;
-  const uint64_t n_groups = (uint64_t)gridDim.x * per_block;
-  for (uint64_t i = (uint64_t)blockIdx.x * per_block + threadIdx.x / kLanes; i < n_flagged; i += n_groups) {
-    const Flagged f = flagged(src, ids, img_of, hit_slot, i);
-    // this lane's share of the unit: 2 x 16 B of a sector, or 16 B of a 64-byte
-    // window read as 4 words (windows are only 4-byte aligned)
-    u32x4 d0 = {}, d1 = {};
-    if constexpr (Src::kUnitBytes == kSectorBytes) {
-      const u32x4* d = (const u32x4*)f.bytes + gl;
-      d0 = d[0];
-      d1 = d[kLanes];
-    } else {
-      const uint32_t* d = (const uint32_t*)f.bytes + 4 * gl;
-      d0 = u32x4{d[0], d[1], d[2], d[3]};
-    }
-    uint32_t cnt = 0, rank = 0;
-    uint64_t mask = 0;
-    for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e; ++c) {
-      const uint32_t m = cv.cand[c];
-      if (!compatible(cv, m, f.tau, f.any_tau)) continue;   // same decision in all lanes of the group
-      u32x4 x;
-      if constexpr (Src::kUnitBytes == kSectorBytes) {
-        const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * kSectorBytes) + gl;
-        x = (d0 ^ q[0]) | (d1 ^ q[kLanes]);
-      } else {   // master fragments are 64-byte aligned
-        x = d0 ^ ((const u32x4*)(cv.masters + (uint64_t)m * Src::kUnitBytes))[gl];
+  if constexpr (kLanes == 1) {   // 64-byte windows (4-byte aligned) against 64-byte aligned master fragments
+    static_assert(Src::kUnitBytes == 64, "one lane per unit only for 64-byte units");
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x; i < n_flagged;
+         i += (uint64_t)gridDim.x * kBlockThreads) {
+      const Flagged f = flagged(src, ids, img_of, hit_slot, i);
+      uint32_t w[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) w[k] = ((const uint32_t*)f.bytes)[k];
+      uint32_t cnt = 0, rank = 0;
+      uint64_t mask = 0;
+      for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e; ++c) {
+        const uint32_t m = cv.cand[c];
+        if (!compatible(cv, m, f.tau, f.any_tau)) continue;
+        const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * Src::kUnitBytes);
+        uint32_t x = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const u32x4 v = q[k];
+          x |= (v.x ^ w[4 * k]) | (v.y ^ w[4 * k + 1]) | (v.z ^ w[4 * k + 2]) | (v.w ^ w[4 * k + 3]);
+        }
+        if (x == 0) {
+          ++cnt;
+          if (rank < 64) mask |= 1ull << rank;
+        }
+        ++rank;
       }
-      const uint64_t diff = ballot((x.x | x.y | x.z | x.w) != 0);
-      if (((diff >> (g * kLanes)) & kGroupMask) == 0) {
-        ++cnt;
-        if (rank < 64) mask |= 1ull << rank;
-      }
-      ++rank;
-    }
-    if (gl == 0) {
       n_match[i] = cnt;
       match_mask[i] = mask;
+    }
+  } else {   // sectors: each lane compares 2 x 16 B
+    static_assert(Src::kUnitBytes == kSectorBytes, "lane groups only for sectors");
+    const uint32_t l = lane_id();
+    const uint32_t g = l / kLanes, gl = l % kLanes;
+    const uint64_t per_block = kBlockThreads / kLanes;
+    const uint64_t n_groups = (uint64_t)gridDim.x * per_block;
+    for (uint64_t i = (uint64_t)blockIdx.x * per_block + threadIdx.x / kLanes; i < n_flagged; i += n_groups) {
+      const Flagged f = flagged(src, ids, img_of, hit_slot, i);
+      const u32x4* d = (const u32x4*)f.bytes + gl;
+      const u32x4 d0 = d[0], d1 = d[kLanes];
+      uint32_t cnt = 0, rank = 0;
+      uint64_t mask = 0;
+      for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e; ++c) {
+        const uint32_t m = cv.cand[c];
+        if (!compatible(cv, m, f.tau, f.any_tau)) continue;   // same decision in all lanes of the group
+        const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * kSectorBytes) + gl;
+        const u32x4 x = (d0 ^ q[0]) | (d1 ^ q[kLanes]);
+        const uint64_t diff = ballot((x.x | x.y | x.z | x.w) != 0);
+        if (((diff >> (g * kLanes)) & kGroupMask) == 0) {
+          ++cnt;
+          if (rank < 64) mask |= 1ull << rank;
+        }
+        ++rank;
+      }
+      if (gl == 0) {
+        n_match[i] = cnt;
+        match_mask[i] = mask;
+      }
     }
   }
 }
@@ -640,24 +676,6 @@ int device_cus() {
   return cus;
 }
 
-// Exclusive scan of n u32 counts into out[0..n] (out[n] = total); total also
-// left in *d_total. ws holds the block sums and offsets. With n_dev, the count
-// is read on the device and n is only its upper bound.
-template <class T>
-int scan_counts(const uint32_t* in, T* out, uint64_t n, uint64_t* d_total, DevBuf& ws, hipStream_t s,
-                const uint64_t* n_dev = nullptr) {
-  const uint64_t nb = cdiv(n ? n : 1, kItemsPerBlock);
-  CARVE_TRY(ws.reserve(2 * nb * sizeof(uint64_t)));
-  uint64_t* sums = ws.as<uint64_t>();
-  uint64_t* offs = sums + nb;
-  k_reduce<<<nb, kBlockThreads, 0, s>>>(U32Items{in}, Count{n, n_dev}, sums);
-  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n, n_dev}, offs, d_total);
-  k_apply<<<nb, kBlockThreads, 0, s>>>(EmitOffsets<T>{in, out}, Count{n, n_dev}, offs);
-  k_write_total<T><<<1, 1, 0, s>>>(out, Count{n, n_dev}, d_total);
-  HIP_TRY(hipGetLastError());
-  return CARVE_OK;
-}
-
 // Blocks of a persistent grid: as many as stay resident at once (capped by
 // `per_cu_cap` when non-zero) so no block waits for a second round, and no
 // more than the work needs.
@@ -669,6 +687,28 @@ int resident_grid(Kernel kernel, int threads, uint64_t want, uint32_t per_cu_cap
   if (per_cu_cap && (uint32_t)per_cu > per_cu_cap) per_cu = (int)per_cu_cap;
   const uint64_t cap = (uint64_t)device_cus() * (uint64_t)per_cu;
   return (int)(want < cap ? (want ? want : 1) : cap);
+}
+
+// Exclusive scan of n u32 counts into out[0..n] (out[n] = total); total also
+// left in *d_total. ws holds the block sums and offsets. With n_dev, the count
+// is read on the device and n is only its upper bound.
+template <class T>
+int scan_counts(const uint32_t* in, T* out, uint64_t n, uint64_t* d_total, DevBuf& ws, hipStream_t s,
+                const uint64_t* n_dev = nullptr) {
+  const uint64_t nb = cdiv(n ? n : 1, kItemsPerBlock);
+  CARVE_TRY(ws.reserve(2 * nb * sizeof(uint64_t)));
+  uint64_t* sums = ws.as<uint64_t>();
+  uint64_t* offs = sums + nb;
+  // a count read on the device is often far below n: a resident grid strides
+  // over the chunks it has instead of launching a block per possible chunk
+  const uint64_t g_red = n_dev ? (uint64_t)resident_grid(k_reduce<U32Items>, kBlockThreads, nb) : nb;
+  const uint64_t g_app = n_dev ? (uint64_t)resident_grid(k_apply<EmitOffsets<T>>, kBlockThreads, nb) : nb;
+  k_reduce<<<g_red, kBlockThreads, 0, s>>>(U32Items{in}, Count{n, n_dev}, sums);
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n, n_dev}, offs, d_total);
+  k_apply<<<g_app, kBlockThreads, 0, s>>>(EmitOffsets<T>{in, out}, Count{n, n_dev}, offs);
+  k_write_total<T><<<1, 1, 0, s>>>(out, Count{n, n_dev}, d_total);
+  HIP_TRY(hipGetLastError());
+  return CARVE_OK;
 }
 
 template <int kMode, int kSig, int kLayout, class Src>
@@ -1270,22 +1310,30 @@ int build_index(const void* master_sectors, const uint64_t* file_sector_offsets,
     // per signature, then as large as 4 MiB and 16 bits per signature allow.
     // A filter word per sector costs less traffic than a bucket line even
     // where the filter no longer fits in L2.
+    // Fragment indexes (32-bit words of 4 bits, which fill less evenly) aim
+    // at twice the bits.
     constexpr uint64_t kAutoBytes = 4ull << 20;
     const uint64_t keys_n = h_unique ? h_unique : 1;
+    const uint64_t aim = unit == kFragBytes ? 32 : 16;
     uint32_t lw = 0;
     if (p.bloom_bits_per_key == 0) {
       while ((64ull << lw) < 4 * keys_n) ++lw;
-      while ((8ull << (lw + 1)) <= kAutoBytes && (64ull << lw) < 16 * keys_n) ++lw;
+      while ((8ull << (lw + 1)) <= kAutoBytes && (64ull << lw) < aim * keys_n) ++lw;
     } else if (p.bloom_bits_per_key != CARVE_BLOOM_OFF) {
       while ((64ull << lw) < (uint64_t)p.bloom_bits_per_key * keys_n) ++lw;
     }
+    if (unit == kFragBytes && lw > 31) lw = 31;   // fragment filters count 32-bit words: at most 2^32
     if (lw > 0 && lw <= 32) {
       if ((rc = ix->bloom.reserve(8ull << lw))) return bail2(rc);
       ix->log2_bloom_words = lw;
       if (hipMemsetAsync(ix->bloom.p, 0, 8ull << lw, s) != hipSuccess)
         return bail2(fail(CARVE_EDEVICE, "build_master_index: bloom memset failed"));
-      k_bloom_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw,
-                                                          ix->bloom.as<uint64_t>());
+      if (unit == kFragBytes)   // the same bytes as 2^(lw+1) words of 32 bits, 4 bits per signature
+        k_frag_bloom_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw + 1,
+                                                                   ix->bloom.as<uint32_t>());
+      else
+        k_bloom_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw,
+                                                            ix->bloom.as<uint64_t>());
       if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return bail2(fail(CARVE_EDEVICE, "build_master_index: bloom build failed"));
     }

@@ -20,15 +20,28 @@ constexpr uint32_t kWaveWindows = kWave * kLaneWindows;      // 1024 windows = 4
 constexpr uint32_t kFragRowDw = kLaneWindows;                // a lane's own 64 bytes, in dwords
 constexpr uint32_t kLdsFilterMaxWords = 1u << 15;            // 128 KiB: the first filter, in LDS
 
-// First-level filter: a bitmap of 32-bit words in LDS; a signature sets 2 bits
-// of one word, placed by a multiplicative hash independent of the Bloom
-// filter's. Only windows that pass it read the (L2-resident) Bloom filter.
-constexpr uint64_t kLdsFilterMul = 0x9FB21C651E98DF25ull;
-__device__ __forceinline__ void lds_filter_place(uint64_t h, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
-  const uint64_t p = h * kLdsFilterMul;
-  *word = (uint32_t)(p >> (64 - log2_words));
-  const uint32_t f = (uint32_t)(p >> (54 - log2_words));   // 10 bits below the word index
-  *bits = (1u << (f & 31u)) | (1u << ((f >> 5) & 31u));
+// The two filters of a fragment index, both of 32-bit words. Their positions
+// come from two 32 x 32 -> 64-bit products of the signature's halves,
+// a = hi * kFragMulA and b = lo * kFragMulB (one multiply-add instruction
+// each); a word index is the top bits of a product's low half (multiplicative
+// hashing), bit positions are 5-bit fields of its high half:
+// * first level, in LDS: word from a, 2 bits from a's high half;
+// * second level, the Bloom filter in L2: word from b, 4 bits from b's high half.
+// Only windows that pass the first level read the second.
+constexpr uint32_t kFragMulA = 0x9E3779B1u;
+constexpr uint32_t kFragMulB = 0x85EBCA77u;
+__device__ __forceinline__ void frag_lds_place(uint64_t h, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
+  const uint64_t a = (uint64_t)(uint32_t)(h >> 32) * kFragMulA;
+  const uint32_t a_hi = (uint32_t)(a >> 32);
+  *word = (uint32_t)a >> (32 - log2_words);   // log2_words in 8..15
+  *bits = (1u << (a_hi & 31u)) | (1u << ((a_hi >> 5) & 31u));
+}
+__device__ __forceinline__ void frag_bloom_place(uint64_t h, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
+  const uint64_t b = (uint64_t)(uint32_t)h * kFragMulB;
+  const uint32_t b_hi = (uint32_t)(b >> 32);
+  *word = log2_words ? (uint32_t)b >> (32 - log2_words) : 0u;   // log2_words in 0..32
+  *bits = (1u << (b_hi & 31u)) | (1u << ((b_hi >> 5) & 31u)) | (1u << ((b_hi >> 10) & 31u)) |
+          (1u << ((b_hi >> 15) & 31u));
 }
 
 // Rolling Eq. (1) over a 64-byte window by 4 bytes. With the window's data
@@ -36,10 +49,15 @@ __device__ __forceinline__ void lds_filter_place(uint64_t h, uint32_t log2_words
 // and D(w) = b0 33^3 + b1 33^2 + b2 33 + b3 for the bytes of word w in address
 // order (D < 2^24):
 //   H(j+1) = H(j) 33^4 - 33^64 D(j) + D(j+16)        (mod 2^64)
-// and the first window is Horner over its 16 words: H = H 33^4 + D(k).
+// and the first window is Horner over its 16 words: H = H 33^4 + D(k). On the
+// signatures themselves, sig(j) = 5381*33^64 + H(j):
+//   sig(j+1) = sig(j) 33^4 + D(j+16) + [5381*33^64 (1 - 33^4) - 33^64 D(j)]
+// where the bracket is one multiply-add of D(j) with constants.
 constexpr uint64_t kPow4 = pow33(4);
 constexpr uint64_t kPow64 = pow33(kFragBytes);
 constexpr uint64_t kFragInit = 5381ull * pow33(kFragBytes);
+constexpr uint64_t kRollAdd = kFragInit - kFragInit * kPow4;   // mod 2^64
+constexpr uint64_t kNegPow64 = 0ull - kPow64;                  // mod 2^64
 
 // The byte weights of D in dot4 form: D = dot(word, low bytes of 33^(3-i))
 // + 256 dot(word, second bytes of 33^(3-i)) (33^3 < 2^16).
@@ -95,35 +113,37 @@ __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4)
   const uint64_t n_waves = (uint64_t)gridDim.x * kFragWaves;
   for (uint64_t t = (uint64_t)blockIdx.x * kFragWaves + wv; t < n_tasks; t += n_waves) {
     // Lane l's windows read dwords [16l, 16l + 32) of the task (dword dw0 =
-    // window 1024t): its own 16 (own[k] = dword 16l + k) and the next lane's.
-    // Lane 63's second 16 are the next task's first words, which lanes 0-15
-    // load (ext). Inside the image these are 16-byte loads; the last task
-    // clamps every dword to the image's last one (only windows past the end
-    // read the repeated words).
+    // window 1024t): its own 16 and the next lane's. Lane 63's second 16 are
+    // the next task's first words, which lanes 0-15 load. Only the words' D
+    // values are kept. Inside the image these are 16-byte loads; the last
+    // task clamps every dword to the image's last one (only windows past the
+    // end read the repeated words).
     const uint64_t dw0 = t * kWaveWindows;
-    uint32_t own[kFragRowDw], ext;
+    // d[k] = D(dword 16l + k), dx = D of dword 1024 + (l % 16) of the task
+    uint32_t d[kFragRowDw], dx;
     if (dw0 + kWaveWindows + kFragRowDw <= n_dwords) {
       const uint32_t* src = image + dw0 + (uint64_t)l * kFragRowDw;
 #pragma unroll
       for (uint32_t q = 0; q < kFragRowDw / 4; ++q) {
         const u32x4 v = __builtin_nontemporal_load((const u32x4*)(src + 4 * q));
-        own[4 * q] = v.x, own[4 * q + 1] = v.y, own[4 * q + 2] = v.z, own[4 * q + 3] = v.w;
+        d[4 * q] = word_djb2(v.x), d[4 * q + 1] = word_djb2(v.y);
+        d[4 * q + 2] = word_djb2(v.z), d[4 * q + 3] = word_djb2(v.w);
       }
-      ext = __builtin_nontemporal_load(image + dw0 + kWaveWindows + (l % kFragRowDw));
+      dx = word_djb2(__builtin_nontemporal_load(image + dw0 + kWaveWindows + (l % kFragRowDw)));
     } else {
 #pragma unroll
       for (uint32_t k = 0; k < kFragRowDw; ++k) {
         const uint64_t g = dw0 + (uint64_t)l * kFragRowDw + k;
-        own[k] = image[g < n_dwords ? g : n_dwords - 1];
+        d[k] = word_djb2(image[g < n_dwords ? g : n_dwords - 1]);
       }
       const uint64_t g = dw0 + kWaveWindows + (l % kFragRowDw);
-      ext = image[g < n_dwords ? g : n_dwords - 1];
+      dx = word_djb2(image[g < n_dwords ? g : n_dwords - 1]);
     }
-    // word 16 + k of lane l's stream: the next lane's own[k]; for lane 63,
-    // lane k's ext (the whole wave runs this code, so every source lane is active)
-    auto second = [&](uint32_t k) {
-      const uint32_t next_lane = (uint32_t)__shfl_down((int)own[k], 1, kWave);
-      const uint32_t from_ext = (uint32_t)__builtin_amdgcn_readlane((int)ext, (int)k);
+    // D of word 16 + k of lane l's stream: the next lane's d[k]; for lane 63,
+    // lane k's dx (the whole wave runs this code, so every source lane is active)
+    auto d_second = [&](uint32_t k) {
+      const uint32_t next_lane = (uint32_t)__shfl_down((int)d[k], 1, kWave);
+      const uint32_t from_ext = (uint32_t)__builtin_amdgcn_readlane((int)dx, (int)k);
       return l == kWave - 1 ? from_ext : next_lane;
     };
     const uint64_t j0 = dw0 + (uint64_t)l * kLaneWindows;
@@ -131,7 +151,10 @@ __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4)
                                                                                    : (uint32_t)(n_windows - j0));
     uint64_t H = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < kFragRowDw; ++k) H = H * kPow4 + word_djb2(own[k]);
+    for (uint32_t k = 0; k < kFragRowDw; ++k) H = H * kPow4 + d[k];
+    uint64_t sig = kFragInit + H;   // window 16l of the task
+    const uint32_t* bloom = (const uint32_t*)ix.bloom;   // fragment indexes: 32-bit words
+    const uint32_t lwb = ix.log2_bloom_words + 1;
     uint32_t mask = 0;
     // batches of 8 windows: 8 signatures; the LDS filter; Bloom words only for
     // the windows that pass it, in flight together; then the (rare) windows
@@ -142,24 +165,25 @@ __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4)
 #pragma unroll
       for (uint32_t i = 0; i < 8; ++i) {
         const uint32_t w = b + i;
-        h[i] = kFragInit + H;
+        h[i] = sig;
         // roll to window w + 1 (after the last window the result is unused)
-        H = H * kPow4 - kPow64 * word_djb2(own[w]) + word_djb2(second(w));
+        sig = sig * kPow4 + (kRollAdd + kNegPow64 * d[w]) + d_second(w);
       }
       uint32_t pend = valid <= b ? 0u : (valid - b >= 8 ? 0xFFu : (1u << (valid - b)) - 1u);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < 8; ++i) {   // no branches: every window reads its LDS word
         uint32_t wi, bits;
-        lds_filter_place(h[i], lw, &wi, &bits);
-        if (h[i] != kEmptyKey && (lfilter[wi] & bits) != bits) pend &= ~(1u << i);
+        frag_lds_place(h[i], lw, &wi, &bits);
+        const bool out = (lfilter[wi] & bits) != bits && h[i] != kEmptyKey;
+        pend &= ~((uint32_t)out << i);
       }
-      if (ix.bloom) {
-        uint64_t bits[8], fw[8];
+      if (bloom) {
+        uint32_t bits[8], fw[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           uint32_t wi;
-          bloom_place(h[i], ix.log2_bloom_words, &wi, &bits[i]);
-          fw[i] = ((pend >> i) & 1u) ? ix.bloom[wi] : ~0ull;
+          frag_bloom_place(h[i], lwb, &wi, &bits[i]);
+          fw[i] = ((pend >> i) & 1u) ? bloom[wi] : ~0u;
         }
         uint32_t pass = 0;
 #pragma unroll
