@@ -27,31 +27,34 @@ sys.path.insert(0, ROOT)
 METRIC = "disk GB/s scanned (bit-exact flags) and % HBM roofline; p99 latency served"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SECTOR_ALG = 512 + 1.0 / 8.0   # read the sector once, write one flag bit
-# the scan kernel's code and its compiler flags: the traffic counters stay valid while these are unchanged
+# a kernel's code and its compiler flags: its traffic counters stay valid while these are unchanged
 KERNEL_SOURCES = ("paper_0901_1307_amd/csrc/carve_scan_kernel.h", "paper_0901_1307_amd/csrc/carve_device.h",
                   "paper_0901_1307_amd/build.py")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_scan_mid.json")
+FRAG_KERNEL_SOURCES = ("paper_0901_1307_amd/csrc/carve_fragment_kernel.h", "paper_0901_1307_amd/csrc/carve_device.h",
+                       "paper_0901_1307_amd/build.py")
+FRAG_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_frag_scan_logos.json")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(config: str, kernel_ms: float):
-    """HBM bytes per launch of the scan kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a
-    copy of known size), as a rate over this run's kernel duration; None if
-    there is no summary for this workload or the kernel changed since."""
+def measured_traffic(config: str, kernel_ms: float, path: str = TRAFFIC_FILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a copy of
+    known size), as a rate over this run's kernel duration; None if there is
+    no summary for this workload or the kernel changed since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None, None
-    if t.get("config") != config or t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("config") != config or t.get("kernel_source_sha256_16") != kernel_source_hash(sources):
         return None, None
     b = float(t["fetch_bytes_per_launch"]) + float(t["write_bytes_per_launch"])
     return round(b / (kernel_ms * 1e-3) / 1e9, 1), t
@@ -323,6 +326,7 @@ def run_fragments(args):
     alg = n_bytes + n_windows / 8            # the image read once, one flag bit per window
     achieved = alg / (k_avg * 1e-3) / 1e9
     value = n_bytes / (ms_per_step * 1e-3) / 1e9
+    traffic, traffic_src = measured_traffic("logos", k_avg, FRAG_TRAFFIC_FILE, FRAG_KERNEL_SOURCES)
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, kernel {k_avg:.3f} ms")
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -337,7 +341,10 @@ def run_fragments(args):
         "flagged": n_flag, "confirmed": n_match,
         "roofline": {"bound": "hbm", "kernel": "k_frag_scan (rolling signatures + filter/table probe)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel_ms": round(k_avg, 4)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel_ms": round(k_avg, 4),
+                     "traffic_bytes_per_launch": (None if traffic_src is None else
+                                                  round(traffic_src["fetch_bytes_per_launch"] +
+                                                        traffic_src["write_bytes_per_launch"]))},
     }
     if not args.no_cpu_baseline:
         import oracle
