@@ -401,6 +401,19 @@ constexpr uint32_t confirm_lanes() {
   return Src::kUnitBytes == kSectorBytes ? 16u : 1u;
 }
 
+// The match mask of a flagged unit: bit r = the r-th compatible candidate is
+// equal, for the first kMaskRanks of them (later ones are compared again when
+// emitted). Windows (any position: every candidate is compatible) with at
+// most 32 candidates use a short form instead: bit 63 set, the list's first
+// index in bits 32-62, the equality mask of the whole list in bits 0-31; so
+// emitting needs neither the slot nor the list offsets.
+template <class Src>
+constexpr uint32_t mask_ranks() {
+  return Src::kUnitBytes == kSectorBytes ? 64u : 63u;
+}
+constexpr uint64_t kShortMask = 1ull << 63;
+constexpr uint32_t kShortMaxList = 32;
+
 __device__ __forceinline__ bool compatible(const ConfirmView& cv, uint32_t m, uint32_t tau, uint32_t any_tau) {
   return any_tau || (cv.m_k[m] & (kClusterSectors - 1)) == tau;
 }
@@ -427,8 +440,8 @@ __device__ __forceinline__ Flagged flagged(const Src& src, const uint64_t* ids, 
 
 // A group of lanes per flagged sector (16), or one lane per flagged window:
 // compare its bytes with every candidate master unit of its slot at a
-// compatible cluster position. Records the number of equal ones and, for the
-// first 64 compatible candidates, which.
+// compatible cluster position. Records the number of equal ones and the match
+// mask (mask_ranks).
 template <class Src>
 __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const uint64_t* __restrict__ ids,
                                                                 const uint32_t* __restrict__ img_of,
@@ -447,11 +460,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
       uint32_t w[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) w[k] = ((const uint32_t*)f.bytes)[k];
+      static_assert(Src::kAnyPosition, "windows match at any position");
       uint32_t cnt = 0, rank = 0;
       uint64_t mask = 0;
-      for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e; ++c) {
+      const uint32_t c0 = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1];
+      for (uint32_t c = c0; c < e; ++c) {   // every candidate is compatible: rank = c - c0
         const uint32_t m = cv.cand[c];
-        if (!compatible(cv, m, f.tau, f.any_tau)) continue;
         const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * Src::kUnitBytes);
         uint32_t x = 0;
 #pragma unroll
@@ -461,10 +475,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
         }
         if (x == 0) {
           ++cnt;
-          if (rank < 64) mask |= 1ull << rank;
+          if (rank < mask_ranks<Src>()) mask |= 1ull << rank;
         }
         ++rank;
       }
+      if (e - c0 <= kShortMaxList && c0 < (1u << 31)) mask |= kShortMask | ((uint64_t)c0 << 32);
       n_match[i] = cnt;
       match_mask[i] = mask;
     }
@@ -488,7 +503,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
         const uint64_t diff = ballot((x.x | x.y | x.z | x.w) != 0);
         if (((diff >> (g * kLanes)) & kGroupMask) == 0) {
           ++cnt;
-          if (rank < 64) mask |= 1ull << rank;
+          if (rank < mask_ranks<Src>()) mask |= 1ull << rank;
         }
         ++rank;
       }
@@ -541,14 +556,27 @@ __global__ void k_confirm_emit(Src src, const uint64_t* __restrict__ ids, const 
        i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t pos = out_off[i];
     if (pos >= cap) continue;
-    const Flagged f = flagged(src, ids, img_of, hit_slot, i);
     const uint64_t mask = match_mask[i];
+    if constexpr (Src::kUnitBytes != kSectorBytes) {
+      if (mask & kShortMask) {   // the list start and its equality mask
+        const uint32_t c0 = (uint32_t)(mask >> 32) & 0x7FFFFFFFu;
+        const uint64_t j = ids[i];
+        const uint32_t im = img_of ? img_of[i] : 0u;
+        for (uint32_t bits = (uint32_t)mask; bits && pos < cap; bits &= bits - 1u) {
+          const uint32_t m = cv.cand[c0 + (uint32_t)__builtin_ctz(bits)];
+          put_record(out, pos++, j, cv.m_file[m], cv.m_k[m], im);
+        }
+        continue;
+      }
+    }
+    const Flagged f = flagged(src, ids, img_of, hit_slot, i);
     uint32_t rank = 0;
     for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e && pos < cap; ++c) {
       const uint32_t m = cv.cand[c];
       if (!compatible(cv, m, f.tau, f.any_tau)) continue;
-      const bool eq = rank < 64 ? ((mask >> rank) & 1u) != 0
-                                : units_equal<Src::kUnitBytes>(f.bytes, cv.masters + (uint64_t)m * Src::kUnitBytes);
+      const bool eq = rank < mask_ranks<Src>()
+                          ? ((mask >> rank) & 1u) != 0
+                          : units_equal<Src::kUnitBytes>(f.bytes, cv.masters + (uint64_t)m * Src::kUnitBytes);
       ++rank;
       if (eq) put_record(out, pos++, f.j, cv.m_file[m], cv.m_k[m], f.image);
     }

@@ -200,8 +200,7 @@ __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4)
         if (hv == kEmptyKey) {
           if (ix.zero_sig_mask) slot = ix.zero_slot;
         } else {
-          slot = find_slot(ix, hv);
-          if (slot >= 0 && ix.tau_mask[slot] == 0) slot = -1;
+          slot = find_slot(ix, hv);   // any position: every occupied slot has masters
         }
         if (slot >= 0) {
           mask |= 1u << (b + i);

@@ -90,6 +90,33 @@ def test_fragment_many_candidates():
     assert_same_matches(m, wm)
 
 
+@pytest.mark.parametrize("n_list", [31, 32, 33, 63, 64])
+def test_fragment_candidate_lists(n_list):
+    """A candidate list of n_list fragments with one signature, every third a
+    crafted collision (same signature, other bytes): windows equal to the
+    common fragment match only the equal ones, a window equal to a collision
+    only its copies (lists up to 32 and longer ones are recorded differently)."""
+    from oracle import spec
+    rng = random.Random(n_list)
+    common = bytes(rng.getrandbits(8) for _ in range(64))
+    spots = [i for i in range(63) if common[i] <= 254 and common[i + 1] >= 33]
+    variants = [spec.collide(common, i) for i in spots[:3]]
+    assert all(spec.djb2_closed(v) == spec.djb2_closed(common) and v != common for v in variants)
+    files = [variants[(k // 3) % len(variants)] if k % 3 == 2 else common for k in range(n_list)]
+    frag_data, offsets = oracle.pack_fragment_files(files)
+    img = bytearray(rng.getrandbits(8) for _ in range(16384))
+    for o in (0, 1000, 5000, 16384 - 64):
+        img[o:o + 64] = common
+    img[9000:9064] = variants[0]
+    idx = carve.build_fragment_index(dev_bytes(frag_data.tobytes()), offsets)
+    f, m, _ = _gpu(idx, dev_bytes(bytes(img)))
+    wf, wm = _oracle(frag_data, offsets, bytes(img))
+    n_common = sum(1 for x in files if x == common)
+    assert len(wm) == 4 * n_common + sum(1 for x in files if x == variants[0])
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
+
+
 def test_fragment_mixed_large():
     """A 4 MiB image with logos embedded at aligned and unaligned offsets,
     zero runs and random bytes, 300 master files; also confirmation enqueued
