@@ -1,0 +1,60 @@
+"""Scans where every unit is flagged, large enough that the compaction and
+the confirmation offsets run over more chunks than their grids have blocks
+(a count read on the device above about 4M); results in closed form.
+
+* 4 GiB of zero sectors against a file of eight zero sectors (one at every
+  cluster position, Section 3.1): every sector flagged, each confirmed by the
+  master at its position.
+* An image repeating one 4-byte word against a file whose one fragment is
+  that word 16 times (Section 5): every 64-byte window flagged and confirmed."""
+import numpy as np
+import pytest
+import torch
+
+from paper_0901_1307_amd import carve
+
+pytestmark = pytest.mark.gpu
+
+
+def test_every_sector_flagged():
+    n_sectors = 8 << 20                                     # 4 GiB
+    image = torch.zeros(n_sectors * 512, dtype=torch.uint8, device="cuda")
+    masters, offsets = carve.pack_master_files([torch.zeros(8 * 512, dtype=torch.uint8, device="cuda")])
+    idx = carve.build_master_index(masters, offsets)
+    for tau0 in (0, 3):
+        sc = carve.scan_image(idx, image, tau0=tau0)
+        ids = torch.empty(n_sectors, dtype=torch.int64, device="cuda")
+        assert carve.flagged_sectors(sc, ids).numel() == n_sectors
+        assert torch.equal(ids, torch.arange(n_sectors, dtype=torch.int64, device="cuda"))
+        out = torch.empty(16 * n_sectors, dtype=torch.uint8, device="cuda")
+        assert carve.confirm_matches(idx, sc, out) == n_sectors
+        rec = out.view(torch.int64).view(n_sectors, 2)
+        j = torch.arange(n_sectors, dtype=torch.int64, device="cuda")
+        assert torch.equal(rec[:, 0], j)                        # disk sector
+        assert torch.equal(rec[:, 1] & 0xFFFFFFFF, torch.zeros_like(j))   # file 0
+        assert torch.equal(rec[:, 1] >> 32, (j + tau0) % 8)     # the master at the same position
+        # records produced again at copy-out (more than the room kept by the scan)
+        carve.scan_image(idx, image, tau0=tau0, scan=sc)
+        carve.confirm_enqueue(idx, sc)
+        host = carve.confirm_matches(idx, sc)
+        assert len(host) == n_sectors
+        assert np.array_equal(host["disk_sector"], np.arange(n_sectors, dtype=np.uint64))
+        assert np.array_equal(host["sector_in_file"], ((np.arange(n_sectors) + tau0) % 8).astype(np.uint32))
+
+
+def test_every_window_flagged():
+    word = torch.tensor([0x4B, 0x1F, 0xA7, 0x03], dtype=torch.uint8, device="cuda")
+    n_bytes = 80 << 20                                      # about 21M windows
+    image = word.repeat(n_bytes // 4)
+    frag, offsets = carve.pack_fragment_files([word.repeat(16)])
+    idx = carve.build_fragment_index(frag, offsets)
+    sc = carve.scan_fragments(idx, image)
+    n_windows = (n_bytes - 64) // 4 + 1
+    ids = torch.empty(n_windows, dtype=torch.int64, device="cuda")
+    assert carve.flagged_sectors(sc, ids).numel() == n_windows
+    assert torch.equal(ids, torch.arange(n_windows, dtype=torch.int64, device="cuda"))
+    out = torch.empty(16 * n_windows, dtype=torch.uint8, device="cuda")
+    assert carve.confirm_matches(idx, sc, out) == n_windows
+    rec = out.view(torch.int64).view(n_windows, 2)
+    assert torch.equal(rec[:, 0], torch.arange(n_windows, dtype=torch.int64, device="cuda"))
+    assert torch.equal(rec[:, 1], torch.zeros(n_windows, dtype=torch.int64, device="cuda"))   # file 0, fragment 0
