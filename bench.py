@@ -113,11 +113,22 @@ def cpu_baseline(ms, img, n_sectors: int, target_s: float, sig_kind: int = 0):
         flags = ix.flag_image(host, threads=threads)
         dt += time.perf_counter() - t0
         passes += 1
+    # one thread, on about a quarter of that CPU time
+    n1 = 1 << 14
+    t0 = time.perf_counter()
+    ix.flag_image(host[:n1 * 512], threads=1)
+    n1 = int(min(n, max(n1, n1 / max(time.perf_counter() - t0, 1e-6) * target_s / 4)))
+    n1 -= n1 % 8
+    t0 = time.perf_counter()
+    ix.flag_image(host[:n1 * 512], threads=1)
+    dt1 = time.perf_counter() - t0
     return {
         "value": round(passes * n * 512 / dt / 1e9, 4),
         "unit": "GB/s",
         "cores": threads,
         "kind": "oracle",
+        "single_thread_value": round(n1 * 512 / dt1 / 1e9, 4),
+        "single_thread_sample": f"first {n1} sectors ({n1 * 512 / 2**30:.2f} GiB) once, {dt1:.2f} s",
         "sample": (f"first {n} sectors ({n * 512 / 2**30:.2f} GiB) of the benchmark image, {len(flags)} flagged, "
                    f"scanned {passes} times; signatures + sorted-array membership + flag list in {dt:.2f} s on "
                    f"{threads} threads ({cpu_model()}); master sort {t_sort:.2f} s excluded"),
