@@ -754,6 +754,8 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "kernel_ms": round(k_avg, 4),
+            "kernel_ms_median": round(sorted(kernel_ms)[len(kernel_ms) // 2], 4),
+            "kernel_ms_min": round(min(kernel_ms), 4),
             "algorithmic_bytes_per_launch": round(n_sectors * BYTES_PER_SECTOR_ALG),
             "traffic_bytes_per_launch": (None if traffic_src is None else
                                          round(traffic_src["fetch_bytes_per_launch"] +
