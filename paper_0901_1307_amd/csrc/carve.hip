@@ -52,6 +52,13 @@ constexpr int kItemsPerBlock = kBlockThreads * kItemsPerThread;   // 2048
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be placed
 
+// A scan object's device counters: [0] flagged units, [1] confirmed records,
+// [kConfirmedWord] 1 once a confirmation ran after the latest scan. Every
+// scan's compaction clears the marker on the device, so a scan replayed from a
+// captured graph (which runs no host code) still invalidates an earlier
+// confirmation; the host checks it before reusing one.
+constexpr uint32_t kConfirmedWord = 2;
+
 // -------------------------------------------------------- prefix sums
 // An item count known on the host (dev == null) or read on the device, so work
 // sized by a count the host has not seen can be enqueued without waiting.
@@ -92,10 +99,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce(Items items, Count cou
 
 // One block: exclusive offsets of the block sums; total into *total. Only
 // the blocks that hold items are scanned (a count read on the device can be
-// far below the capacity the launches were sized for).
+// far below the capacity the launches were sized for). A scan's compaction
+// also clears its confirmation marker (*clear, see kConfirmedWord).
 __global__ __launch_bounds__(kBlockThreads) void k_scan_blocks(const uint64_t* __restrict__ blk_sums, Count items,
                                                               uint64_t* __restrict__ blk_off,
-                                                              uint64_t* __restrict__ total) {
+                                                              uint64_t* __restrict__ total,
+                                                              uint64_t* __restrict__ clear = nullptr) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
   const uint64_t n_blk = (items.get() + kItemsPerBlock - 1) / kItemsPerBlock;
   uint64_t carry = 0;
@@ -107,7 +116,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_scan_blocks(const uint64_t* _
     if (b < n_blk) blk_off[b] = carry + ex;
     carry += t;
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (threadIdx.x == 0) {
+    *total = carry;
+    if (clear) *clear = 0;
+  }
 }
 
 // Hit words -> ascending ids of the flagged sectors, relative to their image
@@ -448,7 +460,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
                                                                 Count count,
                                                                 const uint32_t* __restrict__ hit_slot, ConfirmView cv,
                                                                 uint32_t* __restrict__ n_match,
-                                                                uint64_t* __restrict__ match_mask) {
+                                                                uint64_t* __restrict__ match_mask,
+                                                                uint64_t* __restrict__ confirmed) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *confirmed = 1;   // stream order: after the scan that cleared it
   constexpr uint32_t kLanes = confirm_lanes<Src>();
   constexpr uint64_t kGroupMask = (1ull << kLanes) - 1ull;
   const uint64_t n_flagged = count.get();
@@ -893,8 +907,8 @@ int launch_scan(carve_scan* sc, const Src& src) {
   hipStream_t s = sc->stream;
   const uint64_t n_words = sc->n_tiles;
   uint64_t* d_count = sc->count.as<uint64_t>();
-  if (n_words == 0) {   // nothing to scan: the count is zero
-    k_fill_u64<<<1, 64, 0, s>>>(d_count, 1, 0);
+  if (n_words == 0) {   // nothing to scan: the count is zero (and the confirmation marker cleared)
+    k_fill_u64<<<1, 64, 0, s>>>(d_count, kConfirmedWord + 1, 0);
     if (sc->batch) k_fill_u64<<<1, 256, 0, s>>>(sc->img_off.as<uint64_t>(), sc->n_images + 1, 0);
     HIP_TRY(hipGetLastError());
     return CARVE_OK;
@@ -920,7 +934,7 @@ int launch_scan(carve_scan* sc, const Src& src) {
   uint64_t* sums = sc->ws.as<uint64_t>();
   uint64_t* offs = sums + nb;
   k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{sc->bitmap.as<uint64_t>()}, Count{n_words, nullptr}, sums);
-  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n_words, nullptr}, offs, d_count);
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n_words, nullptr}, offs, d_count, d_count + kConfirmedWord);
   k_apply<<<nb, kBlockThreads, 0, s>>>(
       EmitIds<Src>{src, sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr},
       Count{n_words, nullptr}, offs);
@@ -993,7 +1007,8 @@ int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src,
   const Count nf{cap_f, d_count};
   k_confirm_count<Src><<<resident_grid(k_confirm_count<Src>, kBlockThreads, cdiv(cap_f, per_block)), kBlockThreads,
                          0, s>>>(src, sc->ids.as<uint64_t>(), img_of, nf, sc->hit_slot.as<uint32_t>(), cv,
-                                 sc->n_match.as<uint32_t>(), sc->match_mask.as<uint64_t>());
+                                 sc->n_match.as<uint32_t>(), sc->match_mask.as<uint64_t>(),
+                                 sc->count.as<uint64_t>() + kConfirmedWord);
   uint64_t* d_total = sc->count.as<uint64_t>() + 1;
   CARVE_TRY(scan_counts<uint64_t>(sc->n_match.as<uint32_t>(), sc->out_off.as<uint64_t>(), cap_f, d_total, sc->cws, s,
                                   d_count));
@@ -1011,6 +1026,13 @@ template <class Src, class Rec>
 int confirm_all(const carve_index* idx, carve_scan* sc, const Src& src, Rec* out, uint64_t cap, uint64_t* n_out) {
   hipStream_t s = sc->stream;
   *n_out = 0;
+  if (sc->confirm_enqueued && sc->n_tiles) {
+    // enqueued after the latest scan call, but a scan replayed from a graph
+    // since then would have cleared the marker on the device
+    uint64_t confirmed = 0;
+    CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>() + kConfirmedWord, &confirmed));
+    if (!confirmed) sc->confirm_enqueued = false;
+  }
   // not yet enqueued, device destination: records are written there directly
   const bool direct = !sc->confirm_enqueued && cap && is_device_memory(out);
   if (!sc->confirm_enqueued) CARVE_TRY((confirm_enqueue_impl<Src, Rec>(idx, sc, src, direct ? out : nullptr, cap)));

@@ -117,6 +117,64 @@ def test_batch_reuse_and_graph_replay(setup):
         _check_batch(idx, b, alone)
 
 
+def _plant(ms, image, rep, tau0):
+    """New bytes in place: the first 16 sectors of master file 0 at a sector
+    of the image whose cluster position is 0 (a different one each time)."""
+    p = 64 * (rep + 1) + (-tau0) % 8
+    image[p * 512:(p + 16) * 512] = ms.sectors.reshape(-1)[:16 * 512]
+
+
+def test_graph_of_scan_only_confirms_each_replay(setup):
+    """A graph that captures only the scan: the confirmation asked for after a
+    replay is that of the bytes the replay scanned, also when the batch object
+    was confirmed before (a replay runs no host code)."""
+    ms, idx, images = setup
+    imgs = [(t.clone(), tau0, mode) for t, tau0, mode in images]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = carve.scan_batch(idx, imgs)
+        carve.batch_confirm_matches(idx, b)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            carve.scan_batch(idx, imgs, batch=b)
+    big, tau0, _ = imgs[6]
+    for rep in range(4):
+        _plant(ms, big, rep, tau0)
+        if rep == 3:
+            with torch.cuda.stream(stream):
+                carve.confirm_enqueue(idx, b)      # confirmed before the replay
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _check_batch(idx, b, _alone(idx, imgs))
+
+
+def test_graph_of_scan_image_confirms_each_replay(setup):
+    """The same for one image: scan_image captured alone, confirm_matches after
+    each replay over new bytes equals a fresh scan of them."""
+    ms, idx, images = setup
+    t, tau0, mode = images[6]
+    img = t.clone()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sc = carve.scan_image(idx, img, tau0=tau0, tau_mode=mode)
+        carve.confirm_matches(idx, sc)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            carve.scan_image(idx, img, tau0=tau0, tau_mode=mode, scan=sc)
+    for rep in range(3):
+        _plant(ms, img, rep, tau0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        f, m, _ = gpu_flags_and_matches(idx, img, tau0, mode == carve.CARVE_TAU_ANY)
+        assert np.array_equal(carve.flagged_sectors(sc).numpy().astype(np.uint64), f)
+        assert_same_matches(carve.confirm_matches(idx, sc), m)
+        assert len(m) >= 16
+
+
 def test_batch_rejects_bad_descriptor(setup):
     ms, idx, images = setup
     bad = list(images)
