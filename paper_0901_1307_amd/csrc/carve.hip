@@ -404,13 +404,13 @@ struct ConfirmView {
   const uint8_t* masters;     // packed master sectors
 };
 
-// Lanes per flagged unit in the confirmation count: 16 x 32 B for a sector;
-// one lane for a 64-byte window (its chain of dependent loads, id -> slot ->
-// candidate list -> master, is what takes the time, so more windows in
-// flight beat sharing the compare).
+// Lanes per flagged unit in the confirmation count: 8 x 64 B for a sector;
+// one lane for a 64-byte window. The time goes to a chain of dependent loads
+// (id -> slot -> candidate list -> master), so more units in flight per wave
+// beat spreading one compare over more lanes.
 template <class Src>
 constexpr uint32_t confirm_lanes() {
-  return Src::kUnitBytes == kSectorBytes ? 16u : 1u;
+  return Src::kUnitBytes == kSectorBytes ? 8u : 1u;
 }
 
 // The match mask of a flagged unit: bit r = the r-th compatible candidate is
@@ -450,7 +450,7 @@ __device__ __forceinline__ Flagged flagged(const Src& src, const uint64_t* ids, 
                  Src::kAnyPosition ? 1u : d.any_tau, hit_slot[d.tile_begin * kTileSectors + j]};
 }
 
-// A group of lanes per flagged sector (16), or one lane per flagged window:
+// A group of lanes per flagged sector (8), or one lane per flagged window:
 // compare its bytes with every candidate master unit of its slot at a
 // compatible cluster position. Records the number of equal ones and the match
 // mask (mask_ranks).
@@ -497,8 +497,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
       n_match[i] = cnt;
       match_mask[i] = mask;
     }
-  } else {   // sectors: each lane compares 2 x 16 B
+  } else {   // sectors: lane gl of a group compares the 16-byte chunks gl, gl + kLanes, ...
     static_assert(Src::kUnitBytes == kSectorBytes, "lane groups only for sectors");
+    constexpr uint32_t kChunks = kSectorBytes / 16 / kLanes;
     const uint32_t l = lane_id();
     const uint32_t g = l / kLanes, gl = l % kLanes;
     const uint64_t per_block = kBlockThreads / kLanes;
@@ -506,14 +507,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_confirm_count(Src src, const 
     for (uint64_t i = (uint64_t)blockIdx.x * per_block + threadIdx.x / kLanes; i < n_flagged; i += n_groups) {
       const Flagged f = flagged(src, ids, img_of, hit_slot, i);
       const u32x4* d = (const u32x4*)f.bytes + gl;
-      const u32x4 d0 = d[0], d1 = d[kLanes];
+      u32x4 dv[kChunks];
+#pragma unroll
+      for (uint32_t k = 0; k < kChunks; ++k) dv[k] = d[k * kLanes];
       uint32_t cnt = 0, rank = 0;
       uint64_t mask = 0;
       for (uint32_t c = cv.cand_off[f.slot], e = cv.cand_off[f.slot + 1]; c < e; ++c) {
         const uint32_t m = cv.cand[c];
         if (!compatible(cv, m, f.tau, f.any_tau)) continue;   // same decision in all lanes of the group
         const u32x4* q = (const u32x4*)(cv.masters + (uint64_t)m * kSectorBytes) + gl;
-        const u32x4 x = (d0 ^ q[0]) | (d1 ^ q[kLanes]);
+        u32x4 x = dv[0] ^ q[0];
+#pragma unroll
+        for (uint32_t k = 1; k < kChunks; ++k) x |= dv[k] ^ q[k * kLanes];
         const uint64_t diff = ballot((x.x | x.y | x.z | x.w) != 0);
         if (((diff >> (g * kLanes)) & kGroupMask) == 0) {
           ++cnt;
