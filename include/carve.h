@@ -189,6 +189,12 @@ int confirm_matches(const carve_index* idx, carve_scan* sc, carve_match* out, ui
  * confirm_matches then only copies the records out. Lets the whole hot path be
  * enqueued, or captured in a HIP graph, ahead of any readback. Calling
  * confirm_matches without it enqueues the work itself.
+ * Graphs: a scan replayed from a captured graph runs no host code, so the
+ * scan marks on the device that its confirmation is still to be done, and
+ * confirm_matches checks that mark (one 8-byte readback) before reusing a
+ * confirmation enqueued earlier: after replaying a graph that holds only the
+ * scan, confirm_matches confirms the replayed scan; a graph that holds scan
+ * and confirm_enqueue leaves only the copy to it.
  */
 int confirm_enqueue(const carve_index* idx, carve_scan* sc);
 
@@ -324,7 +330,8 @@ int batch_flagged_sectors(carve_batch* b, uint32_t image, uint64_t* out, uint64_
 int batch_confirm_matches(const carve_index* idx, carve_batch* b, carve_batch_match* out, uint64_t cap,
                           uint64_t* n_out);
 
-/* batch_confirm_enqueue -- confirm_enqueue for a batch. */
+/* batch_confirm_enqueue -- confirm_enqueue for a batch (the same rule for
+ * graphs holding only scan_batch). */
 int batch_confirm_enqueue(const carve_index* idx, carve_batch* b);
 
 /* scan_set_timing -- when enable != 0, later scan_image calls bracket the
