@@ -63,9 +63,13 @@ constexpr uint32_t kConfirmedWord = 2;
 // An item count known on the host (dev == null) or read on the device, so work
 // sized by a count the host has not seen can be enqueued without waiting.
 struct Count {
-  uint64_t v;
+  uint64_t v;            // the count, or with dev: the most the buffers have room for
   const uint64_t* dev;
-  __device__ __forceinline__ uint64_t get() const { return dev ? *dev : v; }
+  __device__ __forceinline__ uint64_t get() const {
+    if (!dev) return v;
+    const uint64_t n = *dev;
+    return n < v ? n : v;
+  }
 };
 
 struct U32Items {
@@ -834,6 +838,8 @@ struct carve_scan {
   const carve_index* idx = nullptr;
   bool batch = false;
   bool fragments = false;        // units are the 64-byte windows of one image
+  uint64_t conf_room = 0;        // flagged units the last enqueued confirmation had room for
+  uint64_t conf_need = 0;        // the most flagged units a confirmation of this object has met
   uint64_t n_dwords = 0;         // fragments: whole 4-byte words of the image
   std::vector<ImageDesc> desc;   // n_images + 1 (the last: total tiles)
   uint32_t n_images = 0;
@@ -861,13 +867,15 @@ ManyImages many_images(const carve_scan* sc) {
   return ManyImages{sc->d_desc.as<ImageDesc>(), sc->n_images};
 }
 
-int read_u64(carve_scan* sc, const uint64_t* d, uint64_t* h) {
+// n (at most 8) consecutive device words, in one copy.
+int read_words(carve_scan* sc, const uint64_t* d, uint32_t n, uint64_t* h) {
   CARVE_TRY(sc->h_small.reserve(64));
-  HIP_TRY(hipMemcpyAsync(sc->h_small.p, d, 8, hipMemcpyDeviceToHost, sc->stream));
+  HIP_TRY(hipMemcpyAsync(sc->h_small.p, d, 8 * n, hipMemcpyDeviceToHost, sc->stream));
   HIP_TRY(hipStreamSynchronize(sc->stream));
-  *h = sc->h_small.as<uint64_t>()[0];
+  for (uint32_t i = 0; i < n; ++i) h[i] = sc->h_small.as<uint64_t>()[i];
   return CARVE_OK;
 }
+int read_u64(carve_scan* sc, const uint64_t* d, uint64_t* h) { return read_words(sc, d, 1, h); }
 
 // Memory a kernel may read: device (or managed) memory, not host memory.
 bool gpu_readable(const void* p) {
@@ -1001,7 +1009,19 @@ int confirm_enqueue_impl(const carve_index* idx, carve_scan* sc, const Src& src,
   sc->confirm_enqueued = true;
   sc->rec_cap = 0;
   if (sc->n_tiles == 0) return CARVE_OK;
-  const uint64_t cap_f = sc->n_tiles * kTileSectors;   // flagged sectors are at most this many
+  // Flagged units are at most `most`. A sector scan's per-flagged arrays have
+  // room for all of them; a fragment scan's for an eighth of its windows (at
+  // least 2^20), or for what an earlier confirmation of this object met: the
+  // kernels stop at the room, and confirm_all redoes a confirmation that ran
+  // short (a window scan would otherwise keep about 20 bytes per window here).
+  const uint64_t most = sc->n_tiles * kTileSectors;
+  uint64_t cap_f = most;
+  if (sc->fragments) {
+    uint64_t room = most / 8 > (1ull << 20) ? most / 8 : (1ull << 20);
+    if (room < sc->conf_need) room = sc->conf_need;
+    if (room < cap_f) cap_f = room;
+  }
+  sc->conf_room = cap_f;
   const uint64_t* d_count = sc->count.as<uint64_t>();
   uint64_t rec_cap = 0;
   CARVE_TRY(reserve_confirm<Rec>(sc, cap_f, &rec_cap));
@@ -1042,14 +1062,18 @@ int confirm_all(const carve_index* idx, carve_scan* sc, const Src& src, Rec* out
   const bool direct = !sc->confirm_enqueued && cap && is_device_memory(out);
   if (!sc->confirm_enqueued) CARVE_TRY((confirm_enqueue_impl<Src, Rec>(idx, sc, src, direct ? out : nullptr, cap)));
   if (sc->n_tiles == 0) return CARVE_OK;
-  uint64_t nm = 0;
-  CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>() + 1, &nm));
+  uint64_t c[2];   // flagged units, confirmed records
+  CARVE_TRY(read_words(sc, sc->count.as<uint64_t>(), 2, c));
+  if (c[0] > sc->conf_room) {   // the confirmation had room for fewer flagged units: again, with room for all
+    sc->conf_need = c[0];
+    sc->confirm_enqueued = false;
+    return confirm_all(idx, sc, src, out, cap, n_out);
+  }
+  const uint64_t nf = c[0], nm = c[1];
   *n_out = nm;
   const uint64_t k = nm < cap ? nm : cap;
   if (k && !direct) {
     if (k > sc->rec_cap) {   // more records than the room enqueued: produce them again, all of them
-      uint64_t nf = 0;
-      CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>(), &nf));
       CARVE_TRY(sc->matches.reserve(k * sizeof(Rec)));
       sc->rec_cap = k;
       k_confirm_emit<Src, Rec><<<resident_grid(k_confirm_emit<Src, Rec>, 256, cdiv(nf, 256)), 256, 0, s>>>(

@@ -6,7 +6,8 @@ the confirmation offsets run over more chunks than their grids have blocks
   cluster position, Section 3.1): every sector flagged, each confirmed by the
   master at its position.
 * An image repeating one 4-byte word against a file whose one fragment is
-  that word 16 times (Section 5): every 64-byte window flagged and confirmed."""
+  that word 16 times (Section 5): every 64-byte window flagged and confirmed,
+  more than a fragment scan's confirmation reserves room for at first."""
 import numpy as np
 import pytest
 import torch
@@ -58,3 +59,11 @@ def test_every_window_flagged():
     rec = out.view(torch.int64).view(n_windows, 2)
     assert torch.equal(rec[:, 0], torch.arange(n_windows, dtype=torch.int64, device="cuda"))
     assert torch.equal(rec[:, 1], torch.zeros(n_windows, dtype=torch.int64, device="cuda"))   # file 0, fragment 0
+    # a fresh scan object: the confirmation enqueued ahead has room for an
+    # eighth of the windows, so copying its records out redoes it with room for all
+    sc2 = carve.scan_fragments(idx, image)
+    carve.confirm_enqueue(idx, sc2)
+    host = carve.confirm_matches(idx, sc2)
+    assert len(host) == n_windows
+    assert np.array_equal(host["disk_sector"], np.arange(n_windows, dtype=np.uint64))
+    assert not host["file_id"].any() and not host["sector_in_file"].any()
