@@ -355,7 +355,11 @@ def run_fragments(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel_ms": round(k_avg, 4),
                      "traffic_bytes_per_launch": (None if traffic_src is None else
                                                   round(traffic_src["fetch_bytes_per_launch"] +
-                                                        traffic_src["write_bytes_per_launch"]))},
+                                                        traffic_src["write_bytes_per_launch"])),
+                     # from the same committed counters (SQ_INSTS_VALU): VALU issue, the other limit
+                     "valu_instructions_per_window": (None if traffic_src is None else
+                                                      traffic_src.get("valu_instructions_per_window")),
+                     "valu_busy": None if traffic_src is None else traffic_src.get("valu_busy")},
     }
     if not args.no_cpu_baseline:
         import oracle
