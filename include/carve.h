@@ -236,7 +236,10 @@ int build_fragment_index(const void* master_fragments, const uint64_t* file_frag
 /* scan_fragments -- flag every window of a device-resident image (16-B
  * aligned; any n_bytes; fewer than 64 bytes gives no window). Asynchronous on
  * `stream`; *io as scan_image (reused when non-null). EINVAL for a sector
- * index, a null, misaligned or host-memory image, or a batch object. */
+ * index, a null, misaligned or host-memory image, or a batch object. The scan
+ * object keeps about 15 bytes of device workspace per window; its
+ * confirmation first reserves room for an eighth of the windows and
+ * confirm_matches redoes it, with room for all, when more were flagged. */
 int scan_fragments(const carve_index* idx, const void* image, uint64_t n_bytes, void* stream, carve_scan** io);
 
 /* ---------------------------------------------------------------- host ingest
