@@ -636,6 +636,7 @@ def main():
     ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
     ap.add_argument("--lanes", type=int, default=4, help="served: stream lanes")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--seed", type=int, default=None, help="plain: workload seed (default: the configuration's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 4 GiB device copy (counter scaling)")
     args = ap.parse_args()
@@ -671,6 +672,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     cfg = synth.CONFIGS[args.config]
+    if args.seed is not None:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, seed=args.seed)
     t0 = time.perf_counter()
     log(f"[bench] generating {cfg.name}: {cfg.n_master_sectors} master sectors, {cfg.n_disk_sectors} disk sectors")
     ms = synth.master_set(cfg, device="cuda")
@@ -717,6 +721,23 @@ def main():
     sc.set_timing(False)
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (event), wall {wall * 1e3 / args.steps:.3f} ms/step")
+    # apart from the timed steps: the same step with ids and records copied to
+    # pinned host memory (end to end including device-to-host)
+    flag_h = torch.empty(n_flag + 1024, dtype=torch.int64, pin_memory=True)
+    match_h = torch.empty(16 * (n_match + 1024), dtype=torch.uint8, pin_memory=True)
+
+    def step_host():
+        carve.scan_image(idx, img.data, scan=sc)
+        nf = carve.flagged_sectors(sc, flag_h).numel()
+        nm = carve.confirm_matches(idx, sc, match_h)
+        return nf, nm
+
+    step_host()
+    torch.cuda.synchronize()
+    t_h = time.perf_counter()
+    for _ in range(5):
+        assert step_host() == (n_flag, n_match)
+    ms_host = (time.perf_counter() - t_h) * 1e3 / 5
 
     value = image_bytes / (ms_per_step * 1e-3) / 1e9
     k_avg = sum(kernel_ms) / len(kernel_ms)
@@ -746,6 +767,7 @@ def main():
             "seed": cfg.seed,
         },
         "sectors_per_s": round(n_sectors / (ms_per_step * 1e-3)),
+        "ms_per_step_host_outputs": round(ms_host, 4),
         "hbm_frac_of_value": round(value / HBM_PEAK_GBS, 4),
         "flagged": n_flag,
         "confirmed": n_match,
