@@ -421,8 +421,8 @@ class FragmentConfig:
 
 
 FRAGMENT_CONFIGS = {
-    # 2000 logos of 2-32 KiB (about 25 MB, 380K fragments), 25000 copies in a
-    # 2 GiB image (a scan keeps about 40 B of workspace per 4-byte window)
+    # 2000 logos of 2-32 KiB (about 22 MB, 346,577 fragments), 25000 copies in a
+    # 2 GiB image (a scan keeps about 15 B of workspace per 4-byte window)
     "logos": FragmentConfig("logos", 1, 2000, 2048, 32768, 2 << 30, 25000, 0.8),
 }
 

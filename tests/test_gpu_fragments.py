@@ -192,3 +192,25 @@ def test_fragment_workload_scaled():
     assert len(wm) > 10000
     assert np.array_equal(f, wf)
     assert_same_matches(m, wm)
+
+
+def test_fragment_workload_full():
+    """The benchmark's workload at its full size (2 GiB image, 346,577
+    fragments of 2,000 files, the 128 KiB LDS filter and the 2 MiB Bloom
+    filter), scanned as bench.py times it: every window's flag and every
+    confirmed record equal the oracle's over the whole image."""
+    import synth
+    cfg = synth.FRAGMENT_CONFIGS["logos"]
+    files = synth.fragment_files(cfg, device="cuda")
+    frags, offsets = carve.pack_fragment_files(files)
+    img = synth.fragment_image(cfg, files, device="cuda")
+    idx = carve.build_fragment_index(frags, offsets)
+    f, m, _ = _gpu(idx, img)
+    host = img.cpu().numpy()
+    del img
+    ox = oracle.FragmentIndex(frags.cpu().numpy(), offsets, threads=oracle.default_threads())
+    wf = ox.flag_windows(host, threads=oracle.default_threads())
+    wm = ox.confirm_windows(host, wf)
+    assert len(wf) > 3_000_000
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
