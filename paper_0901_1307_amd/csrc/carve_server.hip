@@ -316,13 +316,26 @@ extern "C" int server_create(const carve_index* idx, const carve_server_params* 
     int rc = carve_batch_reserve(idx, &ln.batch, share_sectors, p.max_jobs_per_batch, ln.stream);
     if (rc == CARVE_OK && !ln.stage.reserve((uint64_t)p.max_jobs_per_batch + 3))
       rc = carve_fail_msg(CARVE_ENOMEM, "server_create: pinned allocation failed");
-    if (rc == CARVE_OK) ln.res = s->new_results(results_room(share_sectors), &rc);
     if (rc != CARVE_OK) {
       server_free(s);
       return rc;
     }
   }
-  for (Lane& ln : s->lanes) ln.res.reset();   // warm buffers wait in the spare pool
+  // Warm result buffers, two per lane: a retired batch's buffer stays with its
+  // jobs until they are released, and by then the lane already runs its next
+  // batch. Pinned allocation (and freeing) stalls the device, so serving at
+  // saturation must find them ready.
+  {
+    std::vector<std::shared_ptr<Results>> warm;
+    int rc = CARVE_OK;
+    for (size_t i = 0; i < 2 * s->lanes.size() && rc == CARVE_OK; ++i)
+      warm.push_back(s->new_results(results_room(share_sectors), &rc));
+    warm.clear();   // into the spare pool
+    if (rc != CARVE_OK) {
+      server_free(s);
+      return rc;
+    }
+  }
   *out = s;
   return CARVE_OK;
 }
