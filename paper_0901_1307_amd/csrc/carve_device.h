@@ -133,6 +133,15 @@ struct ContiguousRows {
     return base + (uint64_t)(s < n_valid ? s : n_valid - 1) * kSectorBytes;
   }
 };
+// A tile of one cluster position: sector s is base + s*4096 (the same
+// position in 64 consecutive clusters); past n_valid, the last valid one.
+struct ClusterStrideRows {
+  const uint8_t* base;
+  uint32_t n_valid;   // 1..64
+  __device__ __forceinline__ const uint8_t* row(uint32_t s) const {
+    return base + (uint64_t)(s < n_valid ? s : n_valid - 1) * (kClusterSectors * kSectorBytes);
+  }
+};
 
 template <bool kNonTemporal>
 __device__ __forceinline__ u32x4 load16(const uint8_t* p) {
@@ -306,6 +315,10 @@ struct IndexView {
   const uint32_t* sorted_slot;
   const uint32_t* lds_filter;  // fragment indexes: the first-level filter copied into LDS (2^log2_lds_words words)
   uint32_t log2_lds_words;
+  // sector indexes: the Bloom filter split by cluster position, slice t (2^log2_bloom_tau
+  // words at bloom_tau + t 2^log2_bloom_tau) holding the keys present at position t; or null
+  const uint64_t* bloom_tau;
+  uint32_t log2_bloom_tau;
 };
 
 // Probe layouts (the values of carve_index_layout).
@@ -402,29 +415,33 @@ __device__ __forceinline__ bool tau_ok(uint32_t mask, uint32_t tau, bool any_tau
 // (2 B each); all 16 loads are issued before any is used, so the tile pays
 // one memory latency. Returns the tile's hit mask (bit l = sector l); tau is
 // this lane's cluster position. For each hit, the slot that matched is
-// stored in slot_out[sector] (the candidate list that confirmation walks).
+// stored in slot_out[sector * kSlotStride] (the candidate list that
+// confirmation walks; the stride is 8 for a tile of one cluster position).
 // The linear and sorted layouts probe lane by lane, after the filter if there
 // is one.
-template <int kLayout = kLayoutBucketed>
+// bloom / log2_bloom: the filter to consult (the index's, or one position's
+// slice of it), or null.
+template <int kLayout = kLayoutBucketed, uint32_t kSlotStride = 1>
 __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, uint32_t tau, bool any_tau,
-                                               uint32_t* __restrict__ slot_out) {
+                                               uint32_t* __restrict__ slot_out, const uint64_t* bloom,
+                                               uint32_t log2_bloom) {
   const uint32_t l = lane_id();
   // signature 0 cannot be stored in the table (it marks free slots)
   const bool ok_zero = (h == kEmptyKey) && tau_ok(ix.zero_sig_mask, tau, any_tau);
-  if (ok_zero) slot_out[l] = ix.zero_slot;
-  if (kLayout != kLayoutBucketed || ix.bloom) {
+  if (ok_zero) slot_out[l * kSlotStride] = ix.zero_slot;
+  if (kLayout != kLayoutBucketed || bloom) {
     bool maybe = h != kEmptyKey;
-    if (ix.bloom) {
+    if (bloom) {
       uint32_t w;
       uint64_t bits;
-      bloom_place(h, ix.log2_bloom_words, &w, &bits);
-      maybe = maybe && (ix.bloom[w] & bits) == bits;
+      bloom_place(h, log2_bloom, &w, &bits);
+      maybe = maybe && (bloom[w] & bits) == bits;
     }
     bool ok = false;
     if (maybe) {
       const int64_t slot = find_slot_in<kLayout>(ix, h);
       ok = slot >= 0 && tau_ok(ix.tau_mask[slot], tau, any_tau);
-      if (ok) slot_out[l] = (uint32_t)slot;
+      if (ok) slot_out[l * kSlotStride] = (uint32_t)slot;
     }
     return ballot(ok) | ballot(ok_zero);
   }
@@ -454,7 +471,7 @@ __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, 
     const bool ok = (m0 | m1) && tau_ok(mask, ts, any_tau);
     // cross-lane reads only with every lane active: lane s may be idle inside `if (ok)`
     const uint32_t slot0 = (uint32_t)__shfl((int)bkt, (int)s, kWave) * kBucketSlots + 2u * (l & 7u);
-    if (ok) slot_out[s] = slot0 + (m1 ? 1u : 0u);
+    if (ok) slot_out[s * kSlotStride] = slot0 + (m1 ? 1u : 0u);
     hits |= (uint64_t)bytes_nonzero(ballot(ok)) << (8 * r);
     unresolved |= (uint64_t)(~bytes_nonzero(ballot(m0 | m1 | empty)) & 0xFFu) << (8 * r);
   }
@@ -463,7 +480,7 @@ __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, 
   if ((unresolved >> l) & 1u) {
     const int64_t slot = find_slot(ix, h);
     ok_more = slot >= 0 && tau_ok(ix.tau_mask[slot], tau, any_tau);
-    if (ok_more) slot_out[l] = (uint32_t)slot;
+    if (ok_more) slot_out[l * kSlotStride] = (uint32_t)slot;
   }
   return hits | ballot(ok_more) | ballot(ok_zero);
 }

@@ -116,7 +116,8 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
       h = tile_signature_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, wt, A, B, prefetch);
     if constexpr (kMode == kFlags) {
       const uint32_t tau = (tr.tau_first + l) & (kClusterSectors - 1);
-      uint64_t hits = tile_probe<kLayout>(ix, h, tau, tr.any_tau != 0, hit_slot + g * kTileSectors);
+      uint64_t hits = tile_probe<kLayout>(ix, h, tau, tr.any_tau != 0, hit_slot + g * kTileSectors, ix.bloom,
+                                          ix.log2_bloom_words);
       if (tr.n_valid < kTileSectors) hits &= (1ull << tr.n_valid) - 1ull;
       if (l == 0) out[g] = hits;
     } else {
@@ -125,6 +126,72 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
     if (!more) break;
     g = gn;
     cur = cur_n;
+    tr = tn;
+  }
+}
+
+// ------------------------------------------------- position-split scan
+// One image, per-cluster rule, split by cluster position. Workgroups are
+// dispatched to the chip's 8 XCDs in turn (block b runs on XCD b mod 8), so
+// block b scans only the sectors at position p = b mod 8 and probes only
+// position p's slice of the Bloom filter: each XCD's L2 holds one eighth of
+// the filter instead of all of it. Tile k of position p is the sectors
+// j = 8(64k + i) + r (i = 0..63, r = (p - tau0) mod 8), 512 B each, one
+// cluster apart; its 64 hit bits go to tau_words[p * words_per_pos + k]
+// (lane i = bit i), to be merged into the ordinary bitmap afterwards.
+constexpr uint32_t kPositions = kClusterSectors;
+
+__device__ __forceinline__ uint64_t position_count(uint64_t n_sectors, uint32_t r) {
+  return n_sectors > r ? (n_sectors - r + kPositions - 1) / kPositions : 0;
+}
+
+template <int kSig, int kLayout = kLayoutBucketed>
+__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan_tau(
+    const uint8_t* __restrict__ image, uint64_t n_sectors, uint32_t tau0, uint64_t words_per_pos, uint32_t chunk,
+    IndexView ix, uint64_t wt, uint64_t* __restrict__ tau_words, uint32_t* __restrict__ hit_slot) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
+  // the wave's index, uniform (so tile addresses stay in scalar registers)
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const uint32_t l = lane_id();
+  uint8_t* my = lds + w * kTileLds;
+  const uint32_t p = blockIdx.x % kPositions;
+  const uint32_t r = (p - tau0) & (kPositions - 1);
+  const uint64_t count = position_count(n_sectors, r);
+  const uint64_t n_tiles = (count + kTileSectors - 1) / kTileSectors;
+  // this position's slice of the filter
+  const uint64_t* bloom = ix.bloom_tau ? ix.bloom_tau + ((uint64_t)p << ix.log2_bloom_tau) : ix.bloom;
+  const uint32_t log2_bloom = ix.bloom_tau ? ix.log2_bloom_tau : ix.log2_bloom_words;
+  const uint64_t n_waves = (uint64_t)(gridDim.x / kPositions) * kScanWaves;
+  uint64_t g = ((uint64_t)(blockIdx.x / kPositions) * kScanWaves + w) * chunk;
+  if (g >= n_tiles) return;
+  auto next_of = [&](uint64_t t) {
+    return ((t + 1) % chunk != 0) ? t + 1 : t + 1 + (n_waves - 1) * chunk;
+  };
+  auto rows_of = [&](uint64_t k) {
+    const uint64_t first = k * kTileSectors;   // its first cluster among this position's
+    const uint64_t rem = count - first;
+    return ClusterStrideRows{image + (first * kPositions + r) * kSectorBytes,
+                             rem >= kTileSectors ? kTileSectors : (uint32_t)rem};
+  };
+  ClusterStrideRows tr = rows_of(g);
+  PhaseRegs A, B;
+  load_phase<true>(tr, 0, A);
+  while (true) {
+    const uint64_t gn = next_of(g);
+    const bool more = gn < n_tiles;
+    const ClusterStrideRows tn = more ? rows_of(gn) : tr;
+    auto prefetch = [&](PhaseRegs& R) { load_phase<true>(tn, 0, R); };   // unconditionally, as in k_scan
+    uint64_t h;
+    if constexpr (kSig == kSigCrc64)
+      h = tile_crc_pipelined<true>(tr, my, A, B, prefetch);
+    else
+      h = tile_signature_pipelined<true>(tr, my, wt, A, B, prefetch);
+    uint64_t hits = tile_probe<kLayout, kPositions>(ix, h, p, false,
+                                                    hit_slot + (g * kTileSectors * kPositions + r), bloom, log2_bloom);
+    if (tr.n_valid < kTileSectors) hits &= (1ull << tr.n_valid) - 1ull;
+    if (l == 0) tau_words[p * words_per_pos + g] = hits;
+    if (!more) break;
+    g = gn;
     tr = tn;
   }
 }
