@@ -783,7 +783,8 @@ def main():
         "confirmed": n_match,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_scan<kFlags> (signature + probe)",
+            "kernel": ("k_scan_tau (signature + probe, split by cluster position over the 8 XCDs)"
+                       if idx.stats()["bloom_bytes"] >= (4 << 20) else "k_scan<kFlags> (signature + probe)"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
