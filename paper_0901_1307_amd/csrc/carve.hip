@@ -1168,19 +1168,21 @@ template <class Src, class Rec>
 int confirm_all(const carve_index* idx, carve_scan* sc, const Src& src, Rec* out, uint64_t cap, uint64_t* n_out) {
   hipStream_t s = sc->stream;
   *n_out = 0;
+  static_assert(kConfirmedWord == 2, "the counts and the marker are read in one copy");
+  uint64_t c[3] = {0, 0, 0};   // flagged units, confirmed records, confirmation marker
+  bool have_counts = false;
   if (sc->confirm_enqueued && sc->n_tiles) {
     // enqueued after the latest scan call, but a scan replayed from a graph
     // since then would have cleared the marker on the device
-    uint64_t confirmed = 0;
-    CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>() + kConfirmedWord, &confirmed));
-    if (!confirmed) sc->confirm_enqueued = false;
+    CARVE_TRY(read_words(sc, sc->count.as<uint64_t>(), 3, c));
+    if (c[kConfirmedWord]) have_counts = true;
+    else sc->confirm_enqueued = false;
   }
   // not yet enqueued, device destination: records are written there directly
   const bool direct = !sc->confirm_enqueued && cap && is_device_memory(out);
   if (!sc->confirm_enqueued) CARVE_TRY((confirm_enqueue_impl<Src, Rec>(idx, sc, src, direct ? out : nullptr, cap)));
   if (sc->n_tiles == 0) return CARVE_OK;
-  uint64_t c[2];   // flagged units, confirmed records
-  CARVE_TRY(read_words(sc, sc->count.as<uint64_t>(), 2, c));
+  if (!have_counts) CARVE_TRY(read_words(sc, sc->count.as<uint64_t>(), 2, c));
   if (c[0] > sc->conf_room) {   // the confirmation had room for fewer flagged units: again, with room for all
     sc->conf_need = c[0];
     sc->confirm_enqueued = false;
