@@ -372,12 +372,12 @@ __global__ void k_bloom_tau_build(const uint64_t* __restrict__ keys, const uint8
 
 // The fragment scan's two filters (placed by frag_lds_place and
 // frag_bloom_place; 32-bit words).
-__global__ void k_lds_filter_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t log2_words,
+__global__ void k_lds_filter_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t n_words,
                                    uint32_t* filter) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_slots || keys[i] == kEmptyKey) return;
   uint32_t w, bits;
-  frag_lds_place(keys[i], log2_words, &w, &bits);
+  frag_lds_place(keys[i], n_words, &w, &bits);
   atomicOr(&filter[w], bits);
 }
 __global__ void k_frag_bloom_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t log2_words,
@@ -908,7 +908,7 @@ struct carve_index {
   DevBuf lin_keys, lin_slot, sorted_keys, sorted_slot;          // probe structures of the other layouts
   uint32_t log2_lin = 0, n_sorted = 0;
   DevBuf lds_filter;                                            // fragment indexes: first-level filter
-  uint32_t log2_lds_words = 0;
+  uint32_t lds_words = 0;
   DevBuf bloom_tau;                                             // sector indexes: the filter split by position
   uint32_t log2_bloom_tau = 0;
   IndexView view() const {
@@ -916,7 +916,7 @@ struct carve_index {
                      log2_buckets, log2_bloom_words, zero_sig_mask, (uint32_t)n_slots,
                      lin_keys.as<uint64_t>(), lin_slot.as<uint32_t>(), log2_lin, n_sorted,
                      sorted_keys.as<uint64_t>(), sorted_slot.as<uint32_t>(), lds_filter.as<uint32_t>(),
-                     log2_lds_words, bloom_tau.bytes ? bloom_tau.as<uint64_t>() : nullptr, log2_bloom_tau};
+                     lds_words, bloom_tau.bytes ? bloom_tau.as<uint64_t>() : nullptr, log2_bloom_tau};
   }
   ConfirmView cview() const {
     return ConfirmView{cand_off.as<uint32_t>(), cand.as<uint32_t>(), m_file.as<uint32_t>(), m_k.as<uint32_t>(),
@@ -1550,12 +1550,12 @@ int build_index(const void* master_sectors, const uint64_t* file_sector_offsets,
     // the distinct signatures counted above include signature 0, which has no slot
     if ((rc = build_layout(ix, p, h_unique - (zmask ? 1 : 0), s))) return bail2(rc);
   }
-  if (unit == kFragBytes) {   // first-level filter: about 16 bits per signature, 1-128 KiB (always present)
-    uint32_t lw = 8;
-    while ((1u << (lw + 1)) <= kLdsFilterMaxWords && (32ull << lw) < 16 * h_unique) ++lw;
-    if ((rc = ix->lds_filter.reserve(4ull << lw))) return bail2(rc);
-    ix->log2_lds_words = lw;
-    if (hipMemsetAsync(ix->lds_filter.p, 0, 4ull << lw, s) != hipSuccess)
+  if (unit == kFragBytes) {   // first-level filter: about 16 bits per signature, 1-160 KiB (always present)
+    const uint64_t want = cdiv(16 * h_unique, 32 * 256) * 256;   // words, a multiple of 256
+    const uint32_t lw = (uint32_t)(want < 256 ? 256 : (want > kLdsFilterMaxWords ? kLdsFilterMaxWords : want));
+    if ((rc = ix->lds_filter.reserve(4ull * lw))) return bail2(rc);
+    ix->lds_words = lw;
+    if (hipMemsetAsync(ix->lds_filter.p, 0, 4ull * lw, s) != hipSuccess)
       return bail2(fail(CARVE_EDEVICE, "build_fragment_index: filter memset failed"));
     k_lds_filter_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw,
                                                              ix->lds_filter.as<uint32_t>());

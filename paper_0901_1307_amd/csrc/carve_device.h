@@ -313,8 +313,8 @@ struct IndexView {
   uint32_t n_sorted;         // sorted distinct signatures (binary search)
   const uint64_t* sorted_keys;
   const uint32_t* sorted_slot;
-  const uint32_t* lds_filter;  // fragment indexes: the first-level filter copied into LDS (2^log2_lds_words words)
-  uint32_t log2_lds_words;
+  const uint32_t* lds_filter;  // fragment indexes: the first-level filter copied into LDS (lds_words words)
+  uint32_t lds_words;
   // sector indexes: the Bloom filter split by cluster position, slice t (2^log2_bloom_tau
   // words at bloom_tau + t 2^log2_bloom_tau) holding the keys present at position t; or null
   const uint64_t* bloom_tau;

@@ -18,22 +18,23 @@ constexpr uint32_t kFragWaves = kFragThreads / kWave;
 constexpr uint32_t kLaneWindows = 16;                        // consecutive windows per lane
 constexpr uint32_t kWaveWindows = kWave * kLaneWindows;      // 1024 windows = 4 KiB of image per wave task
 constexpr uint32_t kFragRowDw = kLaneWindows;                // a lane's own 64 bytes, in dwords
-constexpr uint32_t kLdsFilterMaxWords = 1u << 15;            // 128 KiB: the first filter, in LDS
+constexpr uint32_t kLdsFilterMaxWords = 40960;               // 160 KiB, all of a CU's LDS: the first filter
 
 // The two filters of a fragment index, both of 32-bit words. Their positions
 // come from two 32 x 32 -> 64-bit products of the signature's halves,
 // a = hi * kFragMulA and b = lo * kFragMulB (one multiply-add instruction
-// each); a word index is the top bits of a product's low half (multiplicative
-// hashing), bit positions are 5-bit fields of its high half:
-// * first level, in LDS: word from a, 2 bits from a's high half;
+// each); a word index comes from the top bits of a product's low half
+// (multiplicative hashing), bit positions are 5-bit fields of its high half:
+// * first level, in LDS: word from a (the low half scaled to the word count,
+//   which need not be a power of two), 2 bits from a's high half;
 // * second level, the Bloom filter in L2: word from b, 4 bits from b's high half.
 // Only windows that pass the first level read the second.
 constexpr uint32_t kFragMulA = 0x9E3779B1u;
 constexpr uint32_t kFragMulB = 0x85EBCA77u;
-__device__ __forceinline__ void frag_lds_place(uint64_t h, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
+__device__ __forceinline__ void frag_lds_place(uint64_t h, uint32_t n_words, uint32_t* word, uint32_t* bits) {
   const uint64_t a = (uint64_t)(uint32_t)(h >> 32) * kFragMulA;
   const uint32_t a_hi = (uint32_t)(a >> 32);
-  *word = (uint32_t)a >> (32 - log2_words);   // log2_words in 8..15
+  *word = (uint32_t)(((uint64_t)(uint32_t)a * n_words) >> 32);   // < n_words
   *bits = (1u << (a_hi & 31u)) | (1u << ((a_hi >> 5) & 31u));
 }
 __device__ __forceinline__ void frag_bloom_place(uint64_t h, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
@@ -103,8 +104,8 @@ __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4)
     const uint32_t* __restrict__ image, uint64_t n_windows, uint64_t n_dwords, IndexView ix,
     uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
   __shared__ uint32_t lfilter[kLdsFilterMaxWords];
-  const uint32_t lw = ix.log2_lds_words;
-  for (uint32_t i = threadIdx.x; i < (1u << lw); i += kFragThreads) lfilter[i] = ix.lds_filter[i];
+  const uint32_t lw = ix.lds_words;   // at most kLdsFilterMaxWords
+  for (uint32_t i = threadIdx.x; i < lw; i += kFragThreads) lfilter[i] = ix.lds_filter[i];
   __syncthreads();   // before any wave of the block can leave
   const uint32_t wv = threadIdx.x / kWave;
   const uint32_t l = lane_id();
