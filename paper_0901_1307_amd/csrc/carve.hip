@@ -117,16 +117,20 @@ struct TauMergeItems {
 // (c + 1) kItemsPerBlock); a block handles chunks blockIdx.x, + gridDim.x, ...
 // so a grid sized for a count read on the device need not cover its upper
 // bound. Chunks past the count are not touched (their sums are not scanned).
+// Within a chunk, consecutive threads take consecutive items (the sum does not
+// depend on the order), so every load instruction is coalesced.
 template <class Items>
 __global__ __launch_bounds__(kBlockThreads) void k_reduce(Items items, Count count, uint64_t* __restrict__ blk_sums) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
   const uint64_t n = count.get();
   for (uint64_t c = blockIdx.x; c * kItemsPerBlock < n; c += gridDim.x) {
-    const uint64_t base = c * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
+    const uint64_t base = c * kItemsPerBlock + threadIdx.x;
     uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kItemsPerThread; ++k)
-      if (base + k < n) s += items(base + k);
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      const uint64_t i = base + (uint64_t)k * kBlockThreads;
+      if (i < n) s += items(i);
+    }
     uint64_t total;
     block_exclusive_scan<kBlockThreads>(s, lds_w, &total);
     if (threadIdx.x == 0) blk_sums[c] = total;
@@ -159,16 +163,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_scan_blocks(const uint64_t* _
 }
 
 // Hit words -> ascending ids of the flagged sectors, relative to their image
-// (and, for batches, the image of each).
+// (and, for batches, the image of each). An Emit type gives k_apply an item's
+// raw value (load), its count (count_of; 0 for the value 0) and what to write
+// for it at its exclusive position (emit); finish(n, end) runs once per scan
+// of n items, with end = the total.
 template <class Src>
 struct EmitIds {
   Src src;
   const uint64_t* words;
   uint64_t* ids;
   uint32_t* img_of;   // null for one image
-  __device__ __forceinline__ uint64_t count(uint64_t i) const { return (uint64_t)__popcll(words[i]); }
-  __device__ __forceinline__ void emit(uint64_t i, uint64_t pos) const {
-    uint64_t x = words[i];
+  __device__ __forceinline__ uint64_t load(uint64_t i) const { return words[i]; }
+  __device__ __forceinline__ uint64_t count_of(uint64_t x) const { return (uint64_t)__popcll(x); }
+  __device__ __forceinline__ void emit(uint64_t i, uint64_t x, uint64_t pos) const {
     if (!x) return;
     const uint32_t im = src.image_of_tile(i);
     const uint64_t first = (i - src.image(im).tile_begin) * kTileSectors;
@@ -180,43 +187,66 @@ struct EmitIds {
       x &= x - 1;
     }
   }
+  __device__ __forceinline__ void finish(uint64_t, uint64_t) const {}
 };
 // u32 counts -> exclusive offsets (out[n] = total).
 template <class T>
 struct EmitOffsets {
   const uint32_t* v;
   T* out;
-  __device__ __forceinline__ uint64_t count(uint64_t i) const { return v[i]; }
-  __device__ __forceinline__ void emit(uint64_t i, uint64_t pos) const { out[i] = (T)pos; }
+  __device__ __forceinline__ uint64_t load(uint64_t i) const { return v[i]; }
+  __device__ __forceinline__ uint64_t count_of(uint64_t x) const { return x; }
+  __device__ __forceinline__ void emit(uint64_t i, uint64_t, uint64_t pos) const { out[i] = (T)pos; }
+  __device__ __forceinline__ void finish(uint64_t n, uint64_t end) const { out[n] = (T)end; }
 };
+
+// A chunk's items go through LDS: loaded coalesced (consecutive threads,
+// consecutive items), then each thread takes its kItemsPerThread consecutive
+// items for the ordered scan. One pad word per 32 spreads a thread's reads
+// over the LDS banks.
+__device__ __forceinline__ uint32_t stage_index(uint32_t j) { return j + (j >> 5); }
+constexpr uint32_t kStageWords = kItemsPerBlock + kItemsPerBlock / 32;
 
 // Chunks as in k_reduce.
 template <class Emit>
 __global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, Count count, const uint64_t* __restrict__ blk_off) {
   __shared__ uint64_t lds_w[kBlockThreads / kWave];
+  __shared__ uint64_t stage[kStageWords];
   const uint64_t n = count.get();
+  if (n == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) e.finish(0, 0);
+    return;
+  }
   for (uint64_t ch = blockIdx.x; ch * kItemsPerBlock < n; ch += gridDim.x) {
-    const uint64_t base = ch * kItemsPerBlock + (uint64_t)threadIdx.x * kItemsPerThread;
-    uint64_t c[kItemsPerThread];
+    const uint64_t c0 = ch * kItemsPerBlock;
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      const uint32_t j = (uint32_t)k * kBlockThreads + threadIdx.x;
+      stage[stage_index(j)] = c0 + j < n ? e.load(c0 + j) : 0;
+    }
+    __syncthreads();
+    const uint32_t j0 = threadIdx.x * kItemsPerThread;
+    uint64_t x[kItemsPerThread], c[kItemsPerThread];
     uint64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
-      c[k] = (base + k < n) ? e.count(base + k) : 0;
+      x[k] = stage[stage_index(j0 + k)];
+      c[k] = e.count_of(x[k]);
       s += c[k];
     }
+    // (the scan's barriers also keep the next chunk's stores behind these reads)
     uint64_t total;
     uint64_t pos = blk_off[ch] + block_exclusive_scan<kBlockThreads>(s, lds_w, &total);
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
-      if (base + k < n) e.emit(base + k, pos);
-      pos += c[k];
+      const uint64_t i = c0 + j0 + k;
+      if (i < n) {
+        e.emit(i, x[k], pos);
+        pos += c[k];
+        if (i == n - 1) e.finish(n, pos);
+      }
     }
   }
-}
-
-template <class T>
-__global__ void k_write_total(T* out, Count n, const uint64_t* total) {
-  out[n.get()] = (T)*total;
 }
 
 // Batches: first flagged-id position of each image (img_off[n] = total), from
@@ -811,8 +841,7 @@ int scan_counts(const uint32_t* in, T* out, uint64_t n, uint64_t* d_total, DevBu
   const uint64_t g_app = n_dev ? (uint64_t)resident_grid(k_apply<EmitOffsets<T>>, kBlockThreads, nb) : nb;
   k_reduce<<<g_red, kBlockThreads, 0, s>>>(U32Items{in}, Count{n, n_dev}, sums);
   k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n, n_dev}, offs, d_total);
-  k_apply<<<g_app, kBlockThreads, 0, s>>>(EmitOffsets<T>{in, out}, Count{n, n_dev}, offs);
-  k_write_total<T><<<1, 1, 0, s>>>(out, Count{n, n_dev}, d_total);
+  k_apply<<<g_app, kBlockThreads, 0, s>>>(EmitOffsets<T>{in, out}, Count{n, n_dev}, offs);   // also out[count]
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
