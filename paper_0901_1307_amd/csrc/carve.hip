@@ -169,6 +169,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_scan_blocks(const uint64_t* _
 // of n items, with end = the total.
 template <class Src>
 struct EmitIds {
+  static constexpr bool kDenseOut = false;   // a variable number of records per item
   Src src;
   const uint64_t* words;
   uint64_t* ids;
@@ -192,6 +193,7 @@ struct EmitIds {
 // u32 counts -> exclusive offsets (out[n] = total).
 template <class T>
 struct EmitOffsets {
+  static constexpr bool kDenseOut = true;   // out[i] for every item i: k_apply stores it coalesced
   const uint32_t* v;
   T* out;
   __device__ __forceinline__ uint64_t load(uint64_t i) const { return v[i]; }
@@ -237,13 +239,31 @@ __global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, Count count, co
     // (the scan's barriers also keep the next chunk's stores behind these reads)
     uint64_t total;
     uint64_t pos = blk_off[ch] + block_exclusive_scan<kBlockThreads>(s, lds_w, &total);
+    if constexpr (Emit::kDenseOut) {
+      // one output per item: the positions go back through LDS (every thread
+      // has read its items: the scan's barriers) and out in item order
 #pragma unroll
-    for (int k = 0; k < kItemsPerThread; ++k) {
-      const uint64_t i = c0 + j0 + k;
-      if (i < n) {
-        e.emit(i, x[k], pos);
+      for (int k = 0; k < kItemsPerThread; ++k) {
+        stage[stage_index(j0 + k)] = pos;
+        if (c0 + j0 + k == n - 1) e.finish(n, pos + c[k]);
         pos += c[k];
-        if (i == n - 1) e.finish(n, pos);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kItemsPerThread; ++k) {
+        const uint32_t j = (uint32_t)k * kBlockThreads + threadIdx.x;
+        if (c0 + j < n) e.emit(c0 + j, 0, stage[stage_index(j)]);
+      }
+      __syncthreads();   // before the next chunk's loads overwrite the stage
+    } else {
+#pragma unroll
+      for (int k = 0; k < kItemsPerThread; ++k) {
+        const uint64_t i = c0 + j0 + k;
+        if (i < n) {
+          e.emit(i, x[k], pos);
+          pos += c[k];
+          if (i == n - 1) e.finish(n, pos);
+        }
       }
     }
   }
