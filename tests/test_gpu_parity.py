@@ -290,6 +290,31 @@ def test_many_duplicates_of_one_sector():
     assert len(m) == 4 * 300
 
 
+@pytest.mark.parametrize("n_planted", [2047, 2048, 2049, 4097])
+def test_compaction_chunk_edges(n_planted):
+    """The compaction works in chunks of 2048 items: hit words (64 sectors
+    each) for the flagged ids, then one count per flagged sector for the
+    record offsets. Flags on both sides of a word chunk's edge and flagged
+    counts around multiples of 2048 give the oracle's lists exactly."""
+    gen = torch.Generator().manual_seed(n_planted)
+    masters = torch.randint(0, 256, (4096 * SECTOR,), dtype=torch.uint8, generator=gen)
+    n_sec = 2048 * 64 * 2 + 37                         # 4096 hit words and a ragged one
+    image = torch.randint(0, 256, (n_sec * SECTOR,), dtype=torch.uint8, generator=gen)
+    edges = [0, 2048 * 64 - 1, 2048 * 64, 2048 * 64 + 1, 4096 * 64 - 1, 4096 * 64, n_sec - 1]
+    rng = random.Random(n_planted)
+    rest = rng.sample(sorted(set(range(n_sec)) - set(edges)), n_planted - len(edges))
+    img2 = image.view(n_sec, SECTOR)
+    m2 = masters.view(4096, SECTOR)
+    for p in edges + rest:
+        img2[p] = m2[8 * rng.randrange(512) + p % 8]      # a master at the sector's own cluster position
+    idx = carve.build_master_index(masters.cuda(), [0, 4096])
+    f, m, _ = gpu_flags_and_matches(idx, image.cuda())
+    wf, wm = oracle_flags_and_matches(masters.numpy(), [0, 4096], image.numpy())
+    assert len(wf) == n_planted
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
+
+
 def test_invalid_arguments():
     img = torch.zeros(4 * SECTOR + 16, dtype=torch.uint8, device="cuda")
     idx = carve.build_master_index(torch.zeros(SECTOR, dtype=torch.uint8, device="cuda"), [0, 1])
