@@ -104,11 +104,17 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
     const uint64_t gn = next_of(g);
     const bool more = gn < n_tiles;
     uint32_t cur_n = cur;
-    const TileRef tn = more ? src.tile(gn, cur_n) : tr;
+    TileRef tn = tr;
     // The next tile's first phase is loaded while this tile's last one is
     // hashed. Unconditionally (the last tile reloads itself): a load under a
-    // branch would make the compiler wait for every load at the join.
-    auto prefetch = [&](PhaseRegs& R) { load_phase<true>(ContiguousRows{tn.base, tn.n_valid}, 0, R); };
+    // branch would make the compiler wait for every load at the join. The
+    // next tile is looked up only here, with this tile's last phase in
+    // flight: in a batch the lookup walks the image descriptors (dependent
+    // loads), which must not hold back this tile's own loads.
+    auto prefetch = [&](PhaseRegs& R) {
+      if (more) tn = src.tile(gn, cur_n);
+      load_phase<true>(ContiguousRows{tn.base, tn.n_valid}, 0, R);
+    };
     uint64_t h;
     if constexpr (kSig == kSigCrc64)
       h = tile_crc_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, A, B, prefetch);
