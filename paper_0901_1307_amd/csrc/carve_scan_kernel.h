@@ -62,7 +62,20 @@ struct ManyImages {
   uint32_t n;
   __device__ __forceinline__ uint64_t n_tiles() const { return d[n].tile_begin; }
   __device__ __forceinline__ TileRef tile(uint64_t g, uint32_t& cursor) const {
-    while (g >= d[cursor + 1].tile_begin) ++cursor;   // skips empty images too
+    // The image holding tile g is the last i with d[i].tile_begin <= g
+    // (empty images are skipped). A wave's tiles are a stride of the grid
+    // apart, which can pass several small images: the next 8 starts are
+    // read at once (independent loads, one wait), not one after another.
+    while (true) {
+      uint32_t step = 0;
+#pragma unroll
+      for (uint32_t k = 1; k <= 8; ++k) {
+        const uint32_t i = cursor + k < n ? cursor + k : n;   // d[n] (the total) ends every walk
+        step += g >= d[i].tile_begin ? 1u : 0u;
+      }
+      cursor += step;
+      if (step < 8) break;
+    }
     return tile_of(d[cursor], g, cursor);
   }
   __device__ __forceinline__ const ImageDesc& image(uint32_t i) const { return d[i]; }
