@@ -487,6 +487,7 @@ def run_served(args):
     log(f"[bench] served: {len(jobs)} jobs over {args.duration:.0f} s, "
         f"{sum(j[1].numel() for j in jobs) / 1e9:.1f} GB, pool {pool.numel() / 2**30:.1f} GiB, "
         f"index {idx.stats()['n_master_sectors']} master sectors")
+    idx.set_scan_config(blocks_per_cu=args.blocks_per_cu, tiles_per_chunk=0)
     srv = carve.Server(idx, n_streams=args.lanes, budget_bytes=32 << 30, confirm=True)
 
     def drain(n_jobs):
@@ -554,11 +555,12 @@ def run_served(args):
         + ("" if cold is None else f" (first, untimed pass: {cold:.0f} GB/s)"))
     st = srv.stats()
     srv.close()
+    idx.set_scan_config(blocks_per_cu=0, tiles_per_chunk=0)   # the references below use the default launch shape
     workload = (f"served: Poisson arrivals at {rate:.0f}/s for {args.duration:.0f} s, sizes "
                 f"log-uniform 64 KiB-256 MiB (flow buffers < 1 MiB matched at any position), "
                 f"{'pinned host-memory' if args.host_jobs else 'device-resident'} pool, resident index of "
-                f"{cfg.n_master_sectors} master sectors, 32 GiB admission budget, {args.lanes} stream lanes, "
-                f"confirmation on")
+                f"{cfg.n_master_sectors} master sectors, 32 GiB admission budget, {args.lanes} stream lanes"
+                f"{f' of {args.blocks_per_cu} scan blocks per CU' if args.blocks_per_cu else ''}, confirmation on")
     common = {
         "metric": METRIC, "value": round(sustained, 2), "unit": "GB/s", "n_gpus": 1, "steps": n,
         "warmup": 64, "ms_per_step": round(elapsed * 1e3 / n, 4), "higher_is_better": True, "scaling": "weak",
@@ -645,6 +647,8 @@ def main():
                     help="served: jobs arrive in pinned host memory and cross PCIe")
     ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
     ap.add_argument("--lanes", type=int, default=4, help="served: stream lanes")
+    ap.add_argument("--blocks-per-cu", type=int, default=0,
+                    help="served: scan blocks per CU of each lane's launches (0: as many as fit)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--seed", type=int, default=None, help="plain: workload seed (default: the configuration's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
