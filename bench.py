@@ -646,7 +646,7 @@ def main():
     ap.add_argument("--host-jobs", action="store_true",
                     help="served: jobs arrive in pinned host memory and cross PCIe")
     ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
-    ap.add_argument("--lanes", type=int, default=4, help="served: stream lanes")
+    ap.add_argument("--lanes", type=int, default=2, help="served: stream lanes (the server's default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0,
                     help="served: scan blocks per CU of each lane's launches (0: as many as fit)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")

@@ -359,7 +359,8 @@ int scan_kernel_ms(carve_scan* sc, float* ms);
 typedef struct carve_server carve_server;
 
 typedef struct {
-  uint32_t n_streams;          /* stream lanes (concurrent batches); 0 = 4 */
+  uint32_t n_streams;          /* stream lanes (concurrent batches); 0 = 2. A lane whose batch
+                                  starts while another lane's runs scans on half of the CUs' slots */
   uint32_t max_jobs_per_batch; /* 0 = 4096; at most 65536 */
   uint64_t budget_bytes;       /* image bytes admitted and not completed; 0 = 32 GiB */
   uint32_t confirm;            /* non-zero: confirm each job's flagged sectors */

@@ -563,7 +563,7 @@ class Server:
     the jobs completed since the last call as (job_id, n_flagged, n_confirmed,
     status) tuples; flags()/matches() fetch a completed job's results."""
 
-    def __init__(self, index: Index, n_streams: int = 4, max_jobs_per_batch: int = 0, budget_bytes: int = 0,
+    def __init__(self, index: Index, n_streams: int = 0, max_jobs_per_batch: int = 0, budget_bytes: int = 0,
                  confirm: bool = True):
         lib = load_library()
         p = _ServerParams(n_streams, max_jobs_per_batch, budget_bytes, int(confirm))

@@ -987,6 +987,7 @@ struct carve_scan {
   uint32_t n_images = 0;
   uint64_t n_tiles = 0;
   uint64_t max_sectors = 0;      // largest id space of one image, for flagged_sectors' copy kernel
+  uint32_t grid_per_cu = 0;      // scan blocks per CU for this object's launches; 0: the index's setting
   DevBuf d_desc;                 // batches: the descriptors on the device
   HostBuf h_desc;                // pinned staging for their upload
   std::vector<ImageDesc> uploaded;
@@ -1061,6 +1062,7 @@ template <class Src>
 int launch_scan(carve_scan* sc, const Src& src) {
   const carve_index* idx = sc->idx;
   hipStream_t s = sc->stream;
+  const uint32_t per_cu = sc->grid_per_cu ? sc->grid_per_cu : per_cu;
   const uint64_t n_words = sc->n_tiles;
   uint64_t* d_count = sc->count.as<uint64_t>();
   if (n_words == 0) {   // nothing to scan: the count is zero (and the confirmation marker cleared)
@@ -1079,18 +1081,18 @@ int launch_scan(carve_scan* sc, const Src& src) {
   if (sc->timing) HIP_TRY(hipEventRecord(sc->ev0, s));
   if constexpr (std::is_same<Src, FragmentWindows>::value) {
     const uint64_t n_tasks = cdiv(src.d.n_sectors, kWaveWindows);
-    const int grid = resident_grid(k_frag_scan, kFragThreads, cdiv(n_tasks, kFragWaves), idx->cfg.blocks_per_cu);
+    const int grid = resident_grid(k_frag_scan, kFragThreads, cdiv(n_tasks, kFragWaves), per_cu);
     k_frag_scan<<<grid, kFragThreads, 0, s>>>((const uint32_t*)src.d.base, src.d.n_sectors, sc->n_dwords,
                                               idx->view(), sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>());
     HIP_TRY(hipGetLastError());
   } else if (split) {
     const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
     CARVE_TRY(launch_k_scan_tau(idx->sig_kind, idx->layout, one, cdiv(n_words, kPositions), chunk,
-                                idx->cfg.blocks_per_cu, idx->view(), idx->weights, sc->tau_words.as<uint64_t>(),
+                                per_cu, idx->view(), idx->weights, sc->tau_words.as<uint64_t>(),
                                 sc->hit_slot.as<uint32_t>(), s));
   } else {
     const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
-    CARVE_TRY(launch_k_scan<kFlags>(idx->sig_kind, src, n_words, chunk, idx->cfg.blocks_per_cu, idx->view(),
+    CARVE_TRY(launch_k_scan<kFlags>(idx->sig_kind, src, n_words, chunk, per_cu, idx->view(),
                                      idx->weights, sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>(), s,
                                      idx->layout));
   }
@@ -1790,6 +1792,20 @@ extern "C" int scan_batch(const carve_index* idx, const carve_image_desc* images
   if ((rc = launch_scan(b, many_images(b)))) return bail(rc);
   *io = b;
   return CARVE_OK;
+}
+
+CARVE_HIDDEN int carve_batch_set_grid(carve_batch* b, uint32_t blocks_per_cu) {
+  if (!b || !b->batch) return fail(CARVE_EINVAL, "carve_batch_set_grid: not a batch");
+  b->grid_per_cu = blocks_per_cu;
+  return CARVE_OK;
+}
+
+CARVE_HIDDEN uint32_t carve_batch_scan_blocks_per_cu(void) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scan<kFlags, kSigDjb2, ManyImages, kLayoutBucketed>,
+                                                   kScanThreads, 0) != hipSuccess || per_cu <= 0)
+    per_cu = 1;
+  return (uint32_t)per_cu;
 }
 
 extern "C" int scan_set_timing(carve_scan* sc, int enable) {

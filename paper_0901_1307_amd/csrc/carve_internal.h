@@ -38,3 +38,10 @@ struct carve_stage_out {
 // (more matches than that must be fetched with batch_confirm_matches).
 CARVE_HIDDEN int carve_batch_stage_out(carve_batch* b, int with_matches, const carve_stage_out* st,
                                        uint64_t* match_room);
+
+// Scan blocks per CU for a batch object's later launches (0: the index's
+// setting), and how many blocks per CU the batch scan kernel can keep resident.
+// The server gives a lane that starts while another lane runs half the CUs'
+// slots, so the two lanes' persistent grids are resident together.
+CARVE_HIDDEN int carve_batch_set_grid(carve_batch* b, uint32_t blocks_per_cu);
+CARVE_HIDDEN uint32_t carve_batch_scan_blocks_per_cu(void);

@@ -118,6 +118,7 @@ struct carve_server {
   double t_launch = 0, t_retire = 0;
   std::vector<carve_image_desc> descs;
   std::vector<uint64_t> counts;
+  uint32_t scan_per_cu = 1;   // scan blocks per CU that stay resident (the batch scan kernel's occupancy)
   std::vector<std::unique_ptr<Results>> spare;   // recycled result buffers
 
   // Recycled buffers with room for `n` ids and records: the smallest spare
@@ -254,7 +255,14 @@ int launch(carve_server* s, Lane& ln) {
     s->queue.pop_front();
   }
   if (ln.jobs.empty()) return CARVE_OK;
-  int rc = stage_host_jobs(s, ln);
+  // A lane that starts while another lane's batch runs takes half of the
+  // CUs' scan slots: two persistent grids then stay resident together instead
+  // of one waiting for the other's blocks to drain. Alone it takes them all.
+  bool others = false;
+  for (const Lane& o : s->lanes) others = others || (&o != &ln && o.busy);
+  const uint32_t half = s->scan_per_cu > 1 ? s->scan_per_cu / 2 : 1;
+  int rc = carve_batch_set_grid(ln.batch, others ? half : 0);
+  if (rc == CARVE_OK) rc = stage_host_jobs(s, ln);
   if (rc == CARVE_OK) rc = scan_batch(s->idx, s->descs.data(), (uint32_t)s->descs.size(), ln.stream, &ln.batch);
   if (rc == CARVE_OK && s->p.confirm) rc = batch_confirm_enqueue(s->idx, ln.batch);
   if (rc == CARVE_OK) ln.res = s->new_results(results_room(ln.bytes / 512), &rc);
@@ -295,7 +303,7 @@ extern "C" int server_create(const carve_index* idx, const carve_server_params* 
   if (params) p = *params;
   for (uint32_t r : p.reserved)
     if (r) return carve_fail_msg(CARVE_EINVAL, "server_create: reserved params must be zero");
-  if (!p.n_streams) p.n_streams = 4;
+  if (!p.n_streams) p.n_streams = 2;
   if (!p.max_jobs_per_batch) p.max_jobs_per_batch = 4096;
   if (!p.budget_bytes) p.budget_bytes = 32ull << 30;
   if (p.n_streams > 64) return carve_fail_msg(CARVE_EINVAL, "server_create: at most 64 streams");
@@ -303,6 +311,7 @@ extern "C" int server_create(const carve_index* idx, const carve_server_params* 
   carve_server* s = new carve_server();
   s->idx = idx;
   s->p = p;
+  s->scan_per_cu = carve_batch_scan_blocks_per_cu();
   s->lanes.resize(p.n_streams);
   // each lane sized for its share of the budget (a larger single job grows it)
   const uint64_t share_sectors = p.budget_bytes / p.n_streams / 512;
