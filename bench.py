@@ -328,9 +328,10 @@ def run_fragments(args):
     ev0.record()
     for _ in range(args.steps):
         assert step() == (n_flag, n_match)
-        kms.append(sc.kernel_ms())
     ev1.record()
     torch.cuda.synchronize()
+    kms = sc.kernel_ms_recent(args.steps)   # every timed launch, read after the timed region
+    assert len(kms) == args.steps
     sc.set_timing(False)
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     k_avg = sum(kms) / len(kms)
@@ -728,10 +729,11 @@ def main():
     for _ in range(args.steps):
         nf, nm = step()
         assert (nf, nm) == (n_flag, n_match)
-        kernel_ms.append(sc.kernel_ms())
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    kernel_ms = sc.kernel_ms_recent(args.steps)   # every timed launch, read after the timed region
+    assert len(kernel_ms) == args.steps
     sc.set_timing(False)
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (event), wall {wall * 1e3 / args.steps:.3f} ms/step")

@@ -346,6 +346,14 @@ int scan_set_timing(carve_scan* sc, int enable);
  * scan was not timed. */
 int scan_kernel_ms(carve_scan* sc, float* ms);
 
+/* scan_kernel_ms_recent -- durations of the signature/probe kernels of the
+ * last min(n, timed launches, 256) timed scans since timing was switched on, oldest
+ * first, into ms (host, n floats); *n_out receives how many. Synchronizes once,
+ * on the end event of the latest, so a timed loop can read them all after it
+ * ends. A scan replayed from a captured graph re-records the events of the
+ * launch that was captured. */
+int scan_kernel_ms_recent(carve_scan* sc, float* ms, uint32_t n, uint32_t* n_out);
+
 /* ---------------------------------------------------------------- serving
  * A request loop over one resident index: scan jobs (disk-image chunks or
  * flow buffers) are queued, admitted in arrival order while the image bytes

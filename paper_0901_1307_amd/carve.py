@@ -33,7 +33,7 @@ JOB_DONE_DTYPE = np.dtype([("job_id", "<u8"), ("n_flagged", "<u8"), ("n_confirme
 EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_matches", "sector_signatures",
            "sector_signatures_kind", "index_stats", "index_set_scan_config", "index_get_scan_config",
            "autotune_scan", "scan_batch", "batch_flag_counts", "batch_flagged_sectors", "batch_confirm_matches",
-           "scan_set_timing", "scan_kernel_ms", "confirm_enqueue", "batch_confirm_enqueue", "server_create",
+           "scan_set_timing", "scan_kernel_ms", "scan_kernel_ms_recent", "confirm_enqueue", "batch_confirm_enqueue", "server_create",
            "server_submit", "server_submit_many", "server_poll", "server_job_flags", "server_job_matches",
            "server_release", "server_release_many", "server_stats", "server_free", "free_index", "free_scan",
            "free_batch", "carve_last_error", "build_fragment_index", "scan_fragments", "ingest_create",
@@ -187,6 +187,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scan_set_timing.argtypes = [P, I32]
     lib.scan_kernel_ms.restype = I32
     lib.scan_kernel_ms.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
+    lib.scan_kernel_ms_recent.restype = I32
+    lib.scan_kernel_ms_recent.argtypes = [P, ctypes.POINTER(ctypes.c_float), U32, ctypes.POINTER(ctypes.c_uint32)]
     lib.free_index.restype = None
     lib.free_index.argtypes = [P]
     lib.free_scan.restype = None
@@ -283,6 +285,13 @@ class Scan:
         _check(load_library().scan_kernel_ms(self.handle, ctypes.byref(ms)))
         return float(ms.value)
 
+    def kernel_ms_recent(self, n: int) -> list:
+        """Kernel durations (ms) of the last n timed launches, oldest first (one synchronization)."""
+        buf = (ctypes.c_float * max(1, n))()
+        got = ctypes.c_uint32()
+        _check(load_library().scan_kernel_ms_recent(self.handle, buf, n, ctypes.byref(got)))
+        return [float(buf[i]) for i in range(got.value)]
+
     def close(self):
         h, self.handle = self.handle, None
         if h:
@@ -309,6 +318,13 @@ class Batch:
         ms = ctypes.c_float()
         _check(load_library().scan_kernel_ms(self.handle, ctypes.byref(ms)))
         return float(ms.value)
+
+    def kernel_ms_recent(self, n: int) -> list:
+        """Kernel durations (ms) of the last n timed launches, oldest first (one synchronization)."""
+        buf = (ctypes.c_float * max(1, n))()
+        got = ctypes.c_uint32()
+        _check(load_library().scan_kernel_ms_recent(self.handle, buf, n, ctypes.byref(got)))
+        return [float(buf[i]) for i in range(got.value)]
 
     def close(self):
         h, self.handle = self.handle, None

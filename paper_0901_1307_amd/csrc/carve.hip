@@ -59,6 +59,9 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be pla
 // confirmation; the host checks it before reusing one.
 constexpr uint32_t kConfirmedWord = 2;
 
+// Timed launches whose kernel durations a scan object keeps (the most recent).
+constexpr uint64_t kTimedRing = 256;
+
 // -------------------------------------------------------- prefix sums
 // An item count known on the host (dev == null) or read on the device, so work
 // sized by a count the host has not seen can be enqueued without waiting.
@@ -998,7 +1001,10 @@ struct carve_scan {
   DevBuf n_match, match_mask, out_off, matches, cws;   // matches: records, rec_cap of them
   bool confirm_enqueued = false;
   uint64_t rec_cap = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // timing: launch k brackets its scan kernel with ev[2 (k mod kTimedRing)]
+  // and ev[2 (k mod kTimedRing) + 1]; n_timed launches so far
+  std::vector<hipEvent_t> ev;
+  uint64_t n_timed = 0;
   bool timing = false, timed = false;
 };
 struct carve_batch : carve_scan {};
@@ -1078,7 +1084,8 @@ int launch_scan(carve_scan* sc, const Src& src) {
     one = src.d;
     split = one.any_tau == 0 && idx->bloom_tau.bytes != 0;
   }
-  if (sc->timing) HIP_TRY(hipEventRecord(sc->ev0, s));
+  const uint64_t slot = 2 * (sc->n_timed % kTimedRing);
+  if (sc->timing) HIP_TRY(hipEventRecord(sc->ev[slot], s));
   if constexpr (std::is_same<Src, FragmentWindows>::value) {
     const uint64_t n_tasks = cdiv(src.d.n_sectors, kWaveWindows);
     const int grid = resident_grid(k_frag_scan, kFragThreads, cdiv(n_tasks, kFragWaves), per_cu);
@@ -1097,7 +1104,8 @@ int launch_scan(carve_scan* sc, const Src& src) {
                                      idx->layout));
   }
   if (sc->timing) {
-    HIP_TRY(hipEventRecord(sc->ev1, s));
+    HIP_TRY(hipEventRecord(sc->ev[slot + 1], s));
+    ++sc->n_timed;
     sc->timed = true;
   }
   const uint64_t nb = cdiv(n_words, kItemsPerBlock);
@@ -1141,9 +1149,9 @@ int reserve_scan(carve_scan* sc) {
     CARVE_TRY(sc->img_of.reserve(n_words * kTileSectors * 4));
     CARVE_TRY(sc->img_off.reserve((sc->n_images + 1) * 8));
   }
-  if (sc->timing && !sc->ev0) {
-    HIP_TRY(hipEventCreate(&sc->ev0));
-    HIP_TRY(hipEventCreate(&sc->ev1));
+  if (sc->timing && sc->ev.empty()) {
+    sc->ev.assign(2 * kTimedRing, nullptr);
+    for (hipEvent_t& e : sc->ev) HIP_TRY(hipEventCreate(&e));
   }
   return CARVE_OK;
 }
@@ -1656,8 +1664,7 @@ extern "C" void free_scan(carve_scan* sc) {
   sc->h_desc.release();
   sc->h_small.release();
   sc->h_img_off.release();
-  if (sc->ev0) (void)hipEventDestroy(sc->ev0);
-  if (sc->ev1) (void)hipEventDestroy(sc->ev1);
+  for (hipEvent_t e : sc->ev) (void)hipEventDestroy(e);
   if (sc->batch) delete static_cast<carve_batch*>(sc);
   else delete sc;
 }
@@ -1810,19 +1817,39 @@ CARVE_HIDDEN uint32_t carve_batch_scan_blocks_per_cu(void) {
 
 extern "C" int scan_set_timing(carve_scan* sc, int enable) {
   if (!sc) return fail(CARVE_EINVAL, "scan_set_timing: null scan");
-  sc->timing = enable != 0;
-  if (sc->timing && !sc->ev0) {
-    HIP_TRY(hipEventCreate(&sc->ev0));
-    HIP_TRY(hipEventCreate(&sc->ev1));
+  if (enable && sc->ev.empty()) {
+    sc->ev.assign(2 * kTimedRing, nullptr);
+    for (hipEvent_t& e : sc->ev) HIP_TRY(hipEventCreate(&e));
   }
+  if (enable && !sc->timing) {   // a new timed series
+    sc->n_timed = 0;
+    sc->timed = false;
+  }
+  sc->timing = enable != 0;
   return CARVE_OK;
 }
 
 extern "C" int scan_kernel_ms(carve_scan* sc, float* ms) {
   if (!sc || !ms) return fail(CARVE_EINVAL, "scan_kernel_ms: null argument");
   if (!sc->timed) return fail(CARVE_EINVAL, "scan_kernel_ms: the last scan was not timed");
-  HIP_TRY(hipEventSynchronize(sc->ev1));
-  HIP_TRY(hipEventElapsedTime(ms, sc->ev0, sc->ev1));
+  const uint64_t slot = 2 * ((sc->n_timed - 1) % kTimedRing);
+  HIP_TRY(hipEventSynchronize(sc->ev[slot + 1]));
+  HIP_TRY(hipEventElapsedTime(ms, sc->ev[slot], sc->ev[slot + 1]));
+  return CARVE_OK;
+}
+
+extern "C" int scan_kernel_ms_recent(carve_scan* sc, float* ms, uint32_t n, uint32_t* n_out) {
+  if (!sc || !n_out || (n && !ms)) return fail(CARVE_EINVAL, "scan_kernel_ms_recent: null argument");
+  *n_out = 0;
+  const uint64_t have = sc->n_timed < kTimedRing ? sc->n_timed : kTimedRing;
+  const uint32_t k = (uint32_t)(n < have ? n : have);
+  if (!k) return CARVE_OK;
+  HIP_TRY(hipEventSynchronize(sc->ev[2 * ((sc->n_timed - 1) % kTimedRing) + 1]));   // the latest ends last
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint64_t slot = 2 * ((sc->n_timed - k + i) % kTimedRing);
+    HIP_TRY(hipEventElapsedTime(&ms[i], sc->ev[slot], sc->ev[slot + 1]));
+  }
+  *n_out = k;
   return CARVE_OK;
 }
 

@@ -315,6 +315,26 @@ def test_compaction_chunk_edges(n_planted):
     assert_same_matches(m, wm)
 
 
+def test_kernel_timing_series(tiny_gpu):
+    """Every timed launch's kernel duration can be read after the loop."""
+    cfg, ms, img, idx = tiny_gpu
+    sc = carve.scan_image(idx, img.data)
+    sc.set_timing(True)
+    for _ in range(3):
+        carve.scan_image(idx, img.data, scan=sc)
+    got = sc.kernel_ms_recent(8)
+    assert len(got) == 3 and all(t > 0 for t in got)
+    assert got[-1] == sc.kernel_ms()
+    assert sc.kernel_ms_recent(2) == got[1:]
+    sc.set_timing(False)
+    carve.scan_image(idx, img.data, scan=sc)           # untimed: the series stays
+    assert sc.kernel_ms_recent(8) == got
+    sc.set_timing(True)                                # a new series
+    assert sc.kernel_ms_recent(8) == []
+    carve.scan_image(idx, img.data, scan=sc)
+    assert len(sc.kernel_ms_recent(8)) == 1
+
+
 def test_invalid_arguments():
     img = torch.zeros(4 * SECTOR + 16, dtype=torch.uint8, device="cuda")
     idx = carve.build_master_index(torch.zeros(SECTOR, dtype=torch.uint8, device="cuda"), [0, 1])
