@@ -337,8 +337,11 @@ int batch_confirm_matches(const carve_index* idx, carve_batch* b, carve_batch_ma
  * graphs holding only scan_batch). */
 int batch_confirm_enqueue(const carve_index* idx, carve_batch* b);
 
-/* scan_set_timing -- when enable != 0, later scan_image calls bracket the
- * signature/probe kernel with HIP events on the scan's stream. */
+/* scan_set_timing -- when enable != 0, later scans through this object
+ * (scan_image, scan_fragments, scan_batch) bracket the signature/probe kernel
+ * with HIP events on the scan's stream; switching it on when it was off starts
+ * a new series for scan_kernel_ms_recent. EDEVICE if the events cannot be
+ * created. */
 int scan_set_timing(carve_scan* sc, int enable);
 
 /* scan_kernel_ms -- duration of the signature/probe kernel of the last timed
