@@ -1068,7 +1068,7 @@ template <class Src>
 int launch_scan(carve_scan* sc, const Src& src) {
   const carve_index* idx = sc->idx;
   hipStream_t s = sc->stream;
-  const uint32_t per_cu = sc->grid_per_cu ? sc->grid_per_cu : per_cu;
+  const uint32_t per_cu = sc->grid_per_cu ? sc->grid_per_cu : idx->cfg.blocks_per_cu;
   const uint64_t n_words = sc->n_tiles;
   uint64_t* d_count = sc->count.as<uint64_t>();
   if (n_words == 0) {   // nothing to scan: the count is zero (and the confirmation marker cleared)
