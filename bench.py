@@ -701,6 +701,9 @@ def main():
     sig_name = "CRC-64/GO-ISO" if args.sig == "crc64" else "djb2-64"
     idx = carve.build_master_index(ms.sectors, ms.file_offsets, sig_kind=sig_kind)
     log(f"[bench] index built in {time.perf_counter() - t0:.2f} s: {idx.stats()}")
+    # the library's launch-shape autotuner on the image itself (untimed, as the batched mode does)
+    shape = idx.autotune(img.data)
+    log(f"[bench] autotuned launch shape: {shape}")
 
     n_sectors = cfg.n_disk_sectors
     image_bytes = img.data.numel()
@@ -781,6 +784,7 @@ def main():
             "n_sectors": n_sectors,
             "n_master_sectors": cfg.n_master_sectors,
             "seed": cfg.seed,
+            "launch_shape": shape,
         },
         "sectors_per_s": round(n_sectors / (ms_per_step * 1e-3)),
         "ms_per_step_host_outputs": round(ms_host, 4),

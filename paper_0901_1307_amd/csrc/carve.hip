@@ -2024,7 +2024,7 @@ extern "C" int autotune_scan(carve_index* idx, const void* sample_image, uint64_
     for (uint32_t ch : chunks) {
       idx->cfg = carve_scan_config{bpc, ch, {0, 0}};
       float total = 0.f;
-      for (int rep = 0; rep < 4 && rc == CARVE_OK; ++rep) {
+      for (int rep = 0; rep < 6 && rc == CARVE_OK; ++rep) {   // 1 warm-up, 5 timed
         rc = scan_image(idx, sample_image, n_bytes, 0, CARVE_TAU_PER_CLUSTER, stream, &sc);
         if (rc == CARVE_OK && rep == 0) rc = scan_set_timing(sc, 1);   // the first run only warms up
         float ms = 0.f;
