@@ -2023,16 +2023,22 @@ extern "C" int autotune_scan(carve_index* idx, const void* sample_image, uint64_
   for (uint32_t bpc : blocks) {
     for (uint32_t ch : chunks) {
       idx->cfg = carve_scan_config{bpc, ch, {0, 0}};
+      // one warm-up run, then at least 5 timed runs and about 8 ms of kernel
+      // time per shape (a small sample needs more runs to rank the shapes)
       float total = 0.f;
-      for (int rep = 0; rep < 6 && rc == CARVE_OK; ++rep) {   // 1 warm-up, 5 timed
+      int timed = 0;
+      for (int rep = 0; rc == CARVE_OK; ++rep) {
         rc = scan_image(idx, sample_image, n_bytes, 0, CARVE_TAU_PER_CLUSTER, stream, &sc);
         if (rc == CARVE_OK && rep == 0) rc = scan_set_timing(sc, 1);   // the first run only warms up
         float ms = 0.f;
         if (rc == CARVE_OK && rep > 0) {
           rc = scan_kernel_ms(sc, &ms);
           total += ms;
+          ++timed;
         }
+        if (timed >= 5 && (total >= 8.f || timed >= 64)) break;
       }
+      total /= timed ? (float)timed : 1.f;   // mean per run
       if (rc != CARVE_OK) break;
       if (total < winner_ms) {
         winner_ms = total;
