@@ -11,15 +11,19 @@ from .workloads import (  # noqa: F401
     FragmentConfig,
     DiskImage,
     MasterSet,
+    TUNING_IMAGE_ID,
     batch_image_specs,
+    batch_images,
     disk_image,
     disk_sectors,
     fragment_files,
     fragment_image,
+    fragment_placements,
     master_set,
     master_sectors,
     scaled,
     served_job_slices,
     served_job_specs,
+    tuning_sample,
     words,
 )

@@ -23,6 +23,7 @@ configured, low-entropy sectors from the same pattern pool.
 """
 from __future__ import annotations
 
+import bisect
 import hashlib
 import math
 from dataclasses import dataclass, field, replace
@@ -373,6 +374,29 @@ def batch_image_specs(seed: int = 1, n_images: int = 256, min_bytes: int = 1 << 
     return specs
 
 
+def batch_images(cfg: CarveConfig, ms: MasterSet, device="cpu", n_images: int = 256) -> List[torch.Tensor]:
+    """The batched workload's images: sizes and hit rates from
+    batch_image_specs(cfg.seed, n_images), each image drawn with cfg's recipe
+    (its own image_id)."""
+    out = []
+    for i, (n_sec, hit) in enumerate(batch_image_specs(seed=cfg.seed, n_images=n_images)):
+        c = replace(cfg, n_disk_sectors=n_sec, p_master_cluster=hit)
+        out.append(disk_image(c, ms, device=device, image_id=i).data)
+    return out
+
+
+# image ids reserved for samples that are never the measured image
+TUNING_IMAGE_ID = 1 << 20
+
+
+def tuning_sample(cfg: CarveConfig, ms: MasterSet, device="cpu", max_sectors: int = 1 << 22) -> torch.Tensor:
+    """An image with cfg's recipe but other bytes than the benchmark's image
+    (its own image_id), of at most max_sectors sectors (2 GiB): what a
+    launch-shape or layout autotuner times instead of the image it will scan."""
+    c = replace(cfg, n_disk_sectors=min(cfg.n_disk_sectors, max_sectors), tail_bytes=0)
+    return disk_image(c, ms, device=device, image_id=TUNING_IMAGE_ID).data
+
+
 def served_job_specs(seed: int = 1, rate: float = 2000.0, duration: float = 60.0,
                      min_bytes: int = 64 << 10, max_bytes: int = 256 << 20,
                      any_tau_below: int = 1 << 20):
@@ -453,17 +477,58 @@ def fragment_image(cfg: FragmentConfig, files: List[torch.Tensor], device="cpu",
         w1 = min(n_words, w0 + chunk_words)
         b = _words_to_bytes(words(k, torch.arange(w0, w1, dtype=torch.int64, device=device)))
         img[4 * w0: min(n, 4 * w1)] = b[: min(n, 4 * w1) - 4 * w0]
+    places = fragment_placements(cfg, [f.numel() for f in files])
+    # The copies are placed in order, a later one overwriting an earlier one
+    # where they overlap; the bytes each copy keeps (those no later copy
+    # covers) are found on the host, so that every image byte is written at
+    # most once and all copies go in with one device scatter.
+    starts, ends = [], []            # disjoint intervals covered by later copies, ascending
+    pieces = []                      # (image offset, file, offset in the file, length)
+    for o, f in reversed(places):
+        a, b = o, o + files[f].numel()
+        i = j = bisect.bisect_right(ends, a)
+        cur = a
+        while j < len(starts) and starts[j] < b:
+            if starts[j] > cur:
+                pieces.append((cur, f, cur - o, starts[j] - cur))
+            cur = max(cur, ends[j])
+            j += 1
+        if cur < b:
+            pieces.append((cur, f, cur - o, b - cur))
+        na, nb = (min(a, starts[i]), max(b, ends[j - 1])) if j > i else (a, b)
+        starts[i:j], ends[i:j] = [na], [nb]
+    if not pieces:
+        return img
+    file_start = [0]
+    for f in files:
+        file_start.append(file_start[-1] + f.numel())
+    src = torch.cat([f.to(device) for f in files])
+    dst0 = torch.tensor([p[0] for p in pieces], dtype=torch.int64, device=device)
+    src0 = torch.tensor([file_start[p[1]] + p[2] for p in pieces], dtype=torch.int64, device=device)
+    lens = torch.tensor([p[3] for p in pieces], dtype=torch.int64, device=device)
+    within = torch.arange(int(lens.sum()), dtype=torch.int64, device=device) - torch.repeat_interleave(
+        torch.cumsum(lens, 0) - lens, lens)
+    img[torch.repeat_interleave(dst0, lens) + within] = src[torch.repeat_interleave(src0, lens) + within]
+    return img
+
+
+def fragment_placements(cfg: FragmentConfig, file_sizes: List[int]):
+    """(image offset, file) of each embedded copy, in placement order: an
+    offset that is a multiple of 4 with probability p_aligned, else 1-3 past
+    one; copies that would not fit are skipped."""
+    n = cfg.image_bytes
     kp = _key(cfg.seed, cfg.name, "frag-plant")
     r = words(kp, torch.arange(3 * cfg.n_embedded, dtype=torch.int64)).view(-1, 3).tolist()
     thr = _threshold(cfg.p_aligned)
+    out = []
     for fsel, osel, asel in r:
-        data = files[fsel % len(files)]
-        room = n - data.numel()
+        f = fsel % len(file_sizes)
+        room = n - file_sizes[f]
         if room <= 4:
             continue
         o = osel % (room - 4)
         o -= o % 4
         if asel >= thr:
             o += 1 + asel % 3
-        img[o: o + data.numel()] = data
-    return img
+        out.append((o, f))
+    return out

@@ -1,11 +1,14 @@
-"""The serving loop: every job's result in the mix equals the job scanned and
-confirmed alone; admission respects the byte budget."""
+"""The serving loop: every job's flags and records in the mix equal the CPU
+oracle's on that job's own bytes (Section 3.1: flag by S_tau, confirm byte for
+byte) and the job scanned and confirmed alone; admission respects the byte
+budget."""
 import random
 
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import synth
 from gpu_util import assert_same_matches, gpu_flags_and_matches
 from paper_0901_1307_amd import carve
@@ -20,7 +23,25 @@ def pool():
     ms = synth.master_set(cfg, device="cuda")
     img = synth.disk_image(cfg, ms, device="cuda").data        # 256 MiB pool
     idx = carve.build_master_index(ms.sectors, ms.file_offsets)
-    return ms, idx, img
+    ox = oracle.Index(ms.sectors.cpu().numpy(), ms.file_offsets, threads=oracle.default_threads())
+    return ms, idx, img, ox
+
+
+def _check_job(srv, jid, done_counts, ox, idx, t, tau0, mode, given=None):
+    """A served job against the oracle on its own bytes (`given`: the host
+    tensor the server was handed, else the device tensor t) and against the
+    job scanned alone on the GPU (t)."""
+    any_tau = mode == carve.CARVE_TAU_ANY
+    host = (t if given is None else given).cpu().numpy()
+    wf = ox.flag_image(host, tau0, any_tau, threads=oracle.default_threads())
+    wm = ox.confirm_image(host, wf, tau0, any_tau)
+    assert done_counts == (len(wf), len(wm))
+    assert np.array_equal(srv.flags(jid), wf)
+    assert_same_matches(srv.matches(jid), wm)
+    f, m, _ = gpu_flags_and_matches(idx, t, tau0, any_tau)
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
+    return len(wf)
 
 
 def _jobs(img, n, seed, max_bytes=8 << 20):
@@ -48,7 +69,7 @@ def _drain(srv, ids):
 
 @pytest.mark.parametrize("n_streams,budget", [(4, 0), (2, 24 << 20), (1, 0)])
 def test_served_equals_alone(pool, n_streams, budget):
-    ms, idx, img = pool
+    ms, idx, img, ox = pool
     jobs = _jobs(img, 60, seed=n_streams)
     srv = carve.Server(idx, n_streams=n_streams, budget_bytes=budget)
     ids = [srv.submit(t, tau0, mode) for t, tau0, mode in jobs]
@@ -58,11 +79,7 @@ def test_served_equals_alone(pool, n_streams, budget):
     assert st["batches_launched"] >= 1
     total_flags = 0
     for jid, (t, tau0, mode) in zip(ids, jobs):
-        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
-        assert done[jid] == (len(f), len(m))
-        assert np.array_equal(srv.flags(jid), f)
-        assert_same_matches(srv.matches(jid), m)
-        total_flags += len(f)
+        total_flags += _check_job(srv, jid, done[jid], ox, idx, t, tau0, mode)
         srv.release(jid)
     assert total_flags > 0
     srv.close()
@@ -70,7 +87,7 @@ def test_served_equals_alone(pool, n_streams, budget):
 
 def test_jobs_arriving_while_others_run(pool):
     """Jobs submitted between polls join later batches; results are unchanged."""
-    ms, idx, img = pool
+    ms, idx, img, ox = pool
     jobs = _jobs(img, 80, seed=9)
     srv = carve.Server(idx, n_streams=3)
     ids, done = [], {}
@@ -82,14 +99,12 @@ def test_jobs_arriving_while_others_run(pool):
     done.update(_drain(srv, [i for i in ids if i not in done]))
     assert srv.stats()["batches_launched"] > 1
     for jid, (t, tau0, mode) in zip(ids, jobs):
-        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
-        assert np.array_equal(srv.flags(jid), f)
-        assert_same_matches(srv.matches(jid), m)
+        _check_job(srv, jid, done[jid], ox, idx, t, tau0, mode)
     srv.close()
 
 
 def test_budget_and_errors(pool):
-    ms, idx, img = pool
+    ms, idx, img, ox = pool
     srv = carve.Server(idx, n_streams=2, budget_bytes=1 << 20)
     with pytest.raises(carve.CarveError) as e:
         srv.submit(img[: 2 << 20])                               # larger than the whole budget
@@ -123,6 +138,7 @@ def test_results_beyond_staged_room():
         offsets.append(len(masters))
     ms = torch.tensor(list(b"".join(masters)), dtype=torch.uint8, device="cuda")
     idx = carve.build_master_index(ms, offsets)
+    ox = oracle.Index(ms.cpu().numpy(), offsets, threads=4)
     zeros = torch.zeros(4 << 20, dtype=torch.uint8, device="cuda")
     jobs = [(zeros[: n * SECTOR], n % 8, carve.CARVE_TAU_ANY if n % 2 else carve.CARVE_TAU_PER_CLUSTER)
             for n in (1, 7, 64, 999, 4096, 8191)]
@@ -130,17 +146,14 @@ def test_results_beyond_staged_room():
     ids = [srv.submit(t, tau0, mode) for t, tau0, mode in jobs]
     done = _drain(srv, ids)
     for jid, (t, tau0, mode) in zip(ids, jobs):
-        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
+        n_f = _check_job(srv, jid, done[jid], ox, idx, t, tau0, mode)
         if mode == carve.CARVE_TAU_ANY:
-            assert len(f) == t.numel() // SECTOR
-        assert done[jid] == (len(f), len(m))
-        assert np.array_equal(srv.flags(jid), f)
-        assert_same_matches(srv.matches(jid), m)
+            assert n_f == t.numel() // SECTOR
     srv.close()
 
 
 def test_bulk_submit_poll_release(pool):
-    ms, idx, img = pool
+    ms, idx, img, ox = pool
     jobs = _jobs(img, 50, seed=21)
     srv = carve.Server(idx, n_streams=3)
     bad = carve.image_descs(jobs[:5])
@@ -158,10 +171,7 @@ def test_bulk_submit_poll_release(pool):
             assert r["status"] == carve.CARVE_OK
             done[int(r["job_id"])] = (int(r["n_flagged"]), int(r["n_confirmed"]))
     for jid, (t, tau0, mode) in zip(ids.tolist(), jobs):
-        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
-        assert done[jid] == (len(f), len(m))
-        assert np.array_equal(srv.flags(jid), f)
-        assert_same_matches(srv.matches(jid), m)
+        _check_job(srv, jid, done[jid], ox, idx, t, tau0, mode)
     with pytest.raises(carve.CarveError):
         srv.release_many(np.array([ids[0], 987654321], dtype=np.uint64))   # stops at the unknown id
     srv.release_many(ids[1:])
@@ -175,7 +185,7 @@ def test_host_memory_jobs(pool):
     """Jobs in host memory (pinned and pageable) beside device jobs: each is
     copied to its lane's device arena at launch, and every result equals the
     same bytes scanned alone on the GPU."""
-    ms, idx, img = pool
+    ms, idx, img, ox = pool
     part = img[: 64 << 20]
     pinned = torch.empty(part.numel(), dtype=torch.uint8, pin_memory=True)
     pinned.copy_(part.cpu())
@@ -192,10 +202,10 @@ def test_host_memory_jobs(pool):
         where.append(k % 3)
     done = _drain(srv, ids)
     assert srv.stats()["batches_launched"] > 1
-    for jid, (t, tau0, mode) in zip(ids, jobs):
-        f, m, _ = gpu_flags_and_matches(idx, t, tau0, mode == carve.CARVE_TAU_ANY)
-        assert done[jid] == (len(f), len(m))
-        assert np.array_equal(srv.flags(jid), f)
-        assert_same_matches(srv.matches(jid), m)
+    for jid, (t, tau0, mode), w in zip(ids, jobs, where):
+        # the oracle reads the bytes the server was given (device, pinned or pageable)
+        off = t.data_ptr() - part.data_ptr()
+        src = (t, pinned[off: off + t.numel()], pageable[off: off + t.numel()])[w]
+        _check_job(srv, jid, done[jid], ox, idx, t, tau0, mode, given=src if w else None)
     assert sum(done[j][0] for j, w in zip(ids, where) if w) > 0     # host jobs found something
     srv.close()
