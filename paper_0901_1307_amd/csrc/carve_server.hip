@@ -276,6 +276,11 @@ int launch(carve_server* s, Lane& ln) {
   if (rc == CARVE_OK && hipEventRecord(ln.done, ln.stream) != hipSuccess)
     rc = carve_fail_msg(CARVE_EDEVICE, "server: event record failed");
   if (rc != CARVE_OK) {   // the jobs fail with the batch's error
+    // Work enqueued before the failure (host-job copies, the scan, the
+    // confirmation, the stage-out) may still read the jobs' images and write
+    // the results buffer: wait for it before the jobs and the buffer are
+    // handed back.
+    (void)hipStreamSynchronize(ln.stream);
     ln.res.reset();
     for (uint64_t id : ln.jobs) {
       Job& j = s->jobs[id];
