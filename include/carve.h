@@ -285,6 +285,28 @@ int ingest_matches(const carve_ingest* in, carve_match* out, uint64_t cap, uint6
 int ingest_stats(const carve_ingest* in, carve_ingest_stats* out);
 void ingest_free(carve_ingest* in);   /* NULL is a no-op; waits for transfers and scans in flight */
 
+/*
+ * scan_image_noalloc -- scan_image followed by flagged_sectors into device
+ * memory, for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc). It allocates nothing:
+ * its work buffers are one fixed device array of the library, 32 MiB + 16 KiB,
+ * that every GPU running the library holds until the process ends. It records
+ * no confirmation data (there is no scan object for confirm_matches).
+ *   idx, image, n_bytes, tau0, tau_mode, stream   as scan_image; at most 2^27
+ *          sectors (64 GiB), EINVAL beyond.
+ *   ids    device, room for cap ids (may be NULL when cap == 0): receives the
+ *          first min(count, cap) flagged sector ids, ascending.
+ *   count  device, one uint64_t: receives the number of flagged sectors (the
+ *          full count, also when it exceeds cap).
+ * Asynchronous on `stream`: nothing is read back. Every call on one GPU uses
+ * that GPU's one array, so calls that overlap on a GPU (on any streams) race:
+ * the caller orders them (e.g. one stream).
+ * Errors: EINVAL (as scan_image; also ids or count not 8-byte aligned or not
+ * device memory, a fragment index, too many sectors), EDEVICE.
+ */
+int scan_image_noalloc(const carve_index* idx, const void* image, uint64_t n_bytes, uint32_t tau0, uint32_t tau_mode,
+                       void* stream, uint64_t* ids, uint64_t cap, uint64_t* count);
+
 /* index_stats -- sizes of a built index (host struct). */
 int index_stats(const carve_index* idx, carve_index_stats* out);
 

@@ -37,7 +37,8 @@ EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_match
            "server_submit", "server_submit_many", "server_poll", "server_job_flags", "server_job_matches",
            "server_release", "server_release_many", "server_stats", "server_free", "free_index", "free_scan",
            "free_batch", "carve_last_error", "build_fragment_index", "scan_fragments", "ingest_create",
-           "ingest_scan", "ingest_flagged_sectors", "ingest_matches", "ingest_stats", "ingest_free")
+           "ingest_scan", "ingest_flagged_sectors", "ingest_matches", "ingest_stats", "ingest_free",
+           "scan_image_noalloc")
 
 
 class CarveError(RuntimeError):
@@ -117,6 +118,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.build_master_index.argtypes = [P, P, U32, ctypes.POINTER(_IndexParams), P, PP]
     lib.scan_image.restype = I32
     lib.scan_image.argtypes = [P, P, U64, U32, U32, P, PP]
+    lib.scan_image_noalloc.restype = I32
+    lib.scan_image_noalloc.argtypes = [P, P, U64, U32, U32, P, P, U64, P]
     lib.flagged_sectors.restype = I32
     lib.flagged_sectors.argtypes = [P, P, U64, PU64]
     lib.confirm_matches.restype = I32
@@ -378,6 +381,28 @@ def scan_image(index: Index, image: torch.Tensor, tau0: int = 0, tau_mode: int =
     sc.image = img
     sc.index = index
     return sc
+
+
+def scan_image_noalloc(index: Index, image: torch.Tensor, ids: torch.Tensor, count: torch.Tensor, tau0: int = 0,
+                       tau_mode: int = CARVE_TAU_PER_CLUSTER, stream=None, n_bytes: Optional[int] = None) -> None:
+    """scan_image + flagged_sectors with no allocation (asynchronous): the
+    ascending flagged ids into `ids` (int64 device tensor, the first
+    ids.numel() of them) and their number into `count` (int64 device tensor,
+    one element)."""
+    lib = load_library()
+    img = _dev_u8(image, "image")
+    nb = img.numel() if n_bytes is None else int(n_bytes)
+    if nb > img.numel():
+        raise ValueError("n_bytes exceeds the image tensor")
+    for t, what in ((ids, "ids"), (count, "count")):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.int64 or \
+                not t.is_contiguous():
+            raise TypeError(f"{what} must be a contiguous int64 CUDA (HIP) tensor")
+    if count.numel() < 1:
+        raise ValueError("count needs one element")
+    _check(lib.scan_image_noalloc(index.handle, img.data_ptr() if nb else None, nb, tau0, tau_mode,
+                                  _stream_ptr(stream), ids.data_ptr() if ids.numel() else None, ids.numel(),
+                                  count.data_ptr()))
 
 
 FRAGMENT = 64      # bytes of a master fragment and of an image window

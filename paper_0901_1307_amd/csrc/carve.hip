@@ -31,6 +31,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,11 +45,24 @@
 
 using namespace carve;
 
+// Work buffers of scan_image_noalloc, for callers that cannot allocate: hit
+// words (and the position-split scan's per-position words) of images up to
+// 2^27 sectors, and the compaction's chunk sums. Every GPU that runs the
+// library holds its own copy until the process ends. In host code this name
+// is a host-side stand-in, never a device address: kernels get the address
+// that noalloc_scratch() looks up per device.
+constexpr uint64_t kNoAllocMaxSectors = 1ull << 27;                        // 64 GiB of image
+constexpr uint64_t kNoAllocMaxWords = kNoAllocMaxSectors / kTileSectors;    // 2^21 hit words
+constexpr uint64_t kNoAllocMaxChunks = kNoAllocMaxWords / 2048;             // compaction chunks of 2048 words
+constexpr uint64_t kScratchWords = 2 * kNoAllocMaxWords + 2 * kNoAllocMaxChunks;   // 32 MiB + 16 KiB
+static __device__ __align__(256) uint64_t scratch[kScratchWords];
+
 namespace {
 
 constexpr int kBlockThreads = 256;
 constexpr int kItemsPerThread = 8;
 constexpr int kItemsPerBlock = kBlockThreads * kItemsPerThread;   // 2048
+static_assert(kNoAllocMaxChunks * kItemsPerBlock == kNoAllocMaxWords, "scratch holds every chunk sum");
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be placed
 
@@ -166,7 +180,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_scan_blocks(const uint64_t* _
 }
 
 // Hit words -> ascending ids of the flagged sectors, relative to their image
-// (and, for batches, the image of each). An Emit type gives k_apply an item's
+// (and, for batches, the image of each); ids at positions cap and beyond are
+// not written (the count is still complete). An Emit type gives k_apply an item's
 // raw value (load), its count (count_of; 0 for the value 0) and what to write
 // for it at its exclusive position (emit); finish(n, end) runs once per scan
 // of n items, with end = the total.
@@ -177,13 +192,14 @@ struct EmitIds {
   const uint64_t* words;
   uint64_t* ids;
   uint32_t* img_of;   // null for one image
+  uint64_t cap;       // room in ids (and img_of)
   __device__ __forceinline__ uint64_t load(uint64_t i) const { return words[i]; }
   __device__ __forceinline__ uint64_t count_of(uint64_t x) const { return (uint64_t)__popcll(x); }
   __device__ __forceinline__ void emit(uint64_t i, uint64_t x, uint64_t pos) const {
-    if (!x) return;
+    if (!x || pos >= cap) return;
     const uint32_t im = src.image_of_tile(i);
     const uint64_t first = (i - src.image(im).tile_begin) * kTileSectors;
-    while (x) {
+    while (x && pos < cap) {
       const int b = __ffsll((long long)x) - 1;
       ids[pos] = first + (uint64_t)b;
       if (img_of) img_of[pos] = im;
@@ -879,7 +895,7 @@ void launch_k_scan_as(const Src& src, uint64_t want, uint32_t chunk, uint32_t pe
 template <int kMode, int kSig, class Src>
 void launch_k_scan_sig(uint32_t layout, const Src& src, uint64_t want, uint32_t chunk, uint32_t per_cu_cap,
                        const IndexView& ix, uint64_t wt, uint64_t* out, uint32_t* hit_slot, hipStream_t s) {
-  if constexpr (kMode == kFlags) {
+  if constexpr (kMode == kFlags || kMode == kFlagBits) {
     if (layout == CARVE_LAYOUT_LINEAR)
       return launch_k_scan_as<kMode, kSig, kLayoutLinear>(src, want, chunk, per_cu_cap, ix, wt, out, hit_slot, s);
     if (layout == CARVE_LAYOUT_SORTED)
@@ -903,36 +919,46 @@ int launch_k_scan(uint32_t kind, const Src& src, uint64_t n_tiles, uint32_t chun
 
 // The position-split scan of one image (k_scan_tau): a persistent grid whose
 // size is a multiple of 8, one eighth of it per cluster position.
-template <int kSig, int kLayout>
+template <int kSig, int kLayout, bool kSlots>
 void launch_k_scan_tau_as(const ImageDesc& d, uint64_t words_per_pos, uint32_t chunk, uint32_t per_cu_cap,
                           const IndexView& ix, uint64_t wt, uint64_t* tau_words, uint32_t* hit_slot, hipStream_t s) {
   const uint64_t want = kPositions * cdiv(cdiv(words_per_pos, chunk), kScanWaves);
-  int grid = resident_grid(k_scan_tau<kSig, kLayout>, kScanThreads, want, per_cu_cap);
+  int grid = resident_grid(k_scan_tau<kSig, kLayout, kSlots>, kScanThreads, want, per_cu_cap);
   grid = grid < (int)kPositions ? (int)kPositions : grid - grid % (int)kPositions;
-  k_scan_tau<kSig, kLayout><<<grid, kScanThreads, 0, s>>>(d.base, d.n_sectors, d.tau0, words_per_pos, chunk, ix,
-                                                           wt, tau_words, hit_slot);
+  k_scan_tau<kSig, kLayout, kSlots><<<grid, kScanThreads, 0, s>>>(d.base, d.n_sectors, d.tau0, words_per_pos, chunk,
+                                                                   ix, wt, tau_words, hit_slot);
 }
 
-template <int kSig>
+template <int kSig, bool kSlots>
 void launch_k_scan_tau_sig(uint32_t layout, const ImageDesc& d, uint64_t words_per_pos, uint32_t chunk,
                            uint32_t per_cu_cap, const IndexView& ix, uint64_t wt, uint64_t* tau_words,
                            uint32_t* hit_slot, hipStream_t s) {
   if (layout == CARVE_LAYOUT_LINEAR)
-    return launch_k_scan_tau_as<kSig, kLayoutLinear>(d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
-                                                      hit_slot, s);
+    return launch_k_scan_tau_as<kSig, kLayoutLinear, kSlots>(d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
+                                                              hit_slot, s);
   if (layout == CARVE_LAYOUT_SORTED)
-    return launch_k_scan_tau_as<kSig, kLayoutSorted>(d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
-                                                      hit_slot, s);
-  launch_k_scan_tau_as<kSig, kLayoutBucketed>(d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words, hit_slot, s);
+    return launch_k_scan_tau_as<kSig, kLayoutSorted, kSlots>(d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
+                                                              hit_slot, s);
+  launch_k_scan_tau_as<kSig, kLayoutBucketed, kSlots>(d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
+                                                       hit_slot, s);
 }
 
+// hit_slot null: no slot records (the flags are not confirmed afterwards).
 int launch_k_scan_tau(uint32_t kind, uint32_t layout, const ImageDesc& d, uint64_t words_per_pos, uint32_t chunk,
                       uint32_t per_cu_cap, const IndexView& ix, uint64_t wt, uint64_t* tau_words, uint32_t* hit_slot,
                       hipStream_t s) {
-  if (kind == CARVE_SIG_CRC64_ISO)
-    launch_k_scan_tau_sig<kSigCrc64>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words, hit_slot, s);
-  else
-    launch_k_scan_tau_sig<kSigDjb2>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words, hit_slot, s);
+  const bool crc = kind == CARVE_SIG_CRC64_ISO;
+  if (hit_slot) {
+    if (crc) launch_k_scan_tau_sig<kSigCrc64, true>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
+                                                     hit_slot, s);
+    else launch_k_scan_tau_sig<kSigDjb2, true>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
+                                                hit_slot, s);
+  } else {
+    if (crc) launch_k_scan_tau_sig<kSigCrc64, false>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
+                                                      nullptr, s);
+    else launch_k_scan_tau_sig<kSigDjb2, false>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
+                                                 nullptr, s);
+  }
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
@@ -1120,7 +1146,8 @@ int launch_scan(carve_scan* sc, const Src& src) {
     k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{sc->bitmap.as<uint64_t>()}, Count{n_words, nullptr}, sums);
   k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n_words, nullptr}, offs, d_count, d_count + kConfirmedWord);
   k_apply<<<nb, kBlockThreads, 0, s>>>(
-      EmitIds<Src>{src, sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr},
+      EmitIds<Src>{src, sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr,
+                   ~0ull},
       Count{n_words, nullptr}, offs);
   if constexpr (std::is_same<Src, ManyImages>::value) {
     const uint64_t per_block = kBlockThreads / kWave;
@@ -1705,6 +1732,80 @@ extern "C" int scan_image(const carve_index* idx, const void* image, uint64_t n_
     return rc;
   }
   *io = sc;
+  return CARVE_OK;
+}
+
+namespace {
+std::mutex g_scratch_mu;
+uint64_t* g_scratch_dev[64] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current (each GPU has its own copy of the array).
+int noalloc_scratch(uint64_t** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(CARVE_EUNSUPPORTED, "scan_image_noalloc: device %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    uint64_t* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CARVE_EDEVICE, "scan_image_noalloc: hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return CARVE_OK;
+}
+}  // namespace
+
+extern "C" int scan_image_noalloc(const carve_index* idx, const void* image, uint64_t n_bytes, uint32_t tau0,
+                                  uint32_t tau_mode, void* stream, uint64_t* ids, uint64_t cap, uint64_t* count) {
+  if (!idx || !count) return fail(CARVE_EINVAL, "scan_image_noalloc: null idx or count");
+  if (cap && !ids) return fail(CARVE_EINVAL, "scan_image_noalloc: null ids with cap > 0");
+  const uint64_t n_sectors = n_bytes / kSectorBytes;
+  if (n_sectors > kNoAllocMaxSectors)
+    return fail(CARVE_EINVAL, "scan_image_noalloc: %llu sectors, at most %llu (64 GiB) without allocation",
+                (unsigned long long)n_sectors, (unsigned long long)kNoAllocMaxSectors);
+  if (idx->unit_bytes != kSectorBytes) return fail(CARVE_EINVAL, "scan_image_noalloc: a fragment index");
+  CARVE_TRY(validate_image(image, n_bytes, tau0, tau_mode, "scan_image_noalloc", -1));
+  if (n_sectors && !gpu_readable(image)) return fail(CARVE_EINVAL, "scan_image_noalloc: image is not in device memory");
+  if ((uintptr_t)count % 8 || (uintptr_t)ids % 8)
+    return fail(CARVE_EINVAL, "scan_image_noalloc: ids and count must be 8-byte aligned");
+  if (!is_device_memory(count) || (cap && !is_device_memory(ids)))
+    return fail(CARVE_EINVAL, "scan_image_noalloc: ids and count must be device memory");
+  uint64_t* sw = nullptr;
+  CARVE_TRY(noalloc_scratch(&sw));
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t n_words = cdiv(n_sectors, kTileSectors);
+  if (n_words == 0) {
+    k_fill_u64<<<1, 64, 0, s>>>(count, 1, 0);
+    HIP_TRY(hipGetLastError());
+    return CARVE_OK;
+  }
+  // every word read below is written first by this call's own kernels
+  uint64_t* bitmap = sw;
+  uint64_t* tau_words = sw + kNoAllocMaxWords;
+  uint64_t* sums = sw + 2 * kNoAllocMaxWords;
+  uint64_t* offs = sums + kNoAllocMaxChunks;
+  const OneImage src{ImageDesc{(const uint8_t*)image, n_sectors, 0, tau0, tau_mode == CARVE_TAU_ANY ? 1u : 0u}};
+  const uint32_t per_cu = idx->cfg.blocks_per_cu;
+  const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
+  const uint64_t nb = cdiv(n_words, kItemsPerBlock);
+  if (src.d.any_tau == 0 && idx->bloom_tau.bytes != 0) {   // as scan_image: the position-split scan
+    CARVE_TRY(launch_k_scan_tau(idx->sig_kind, idx->layout, src.d, cdiv(n_words, kPositions), chunk, per_cu,
+                                idx->view(), idx->weights, tau_words, nullptr, s));
+    k_reduce<<<nb, kBlockThreads, 0, s>>>(TauMergeItems{tau_words, cdiv(n_words, kPositions), bitmap, n_words,
+                                                        tau0, (uint32_t)(n_sectors % kTileSectors)},
+                                          Count{n_words, nullptr}, sums);
+  } else {
+    CARVE_TRY(launch_k_scan<kFlagBits>(idx->sig_kind, src, n_words, chunk, per_cu, idx->view(), idx->weights, bitmap,
+                                        nullptr, s, idx->layout));
+    k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{bitmap}, Count{n_words, nullptr}, sums);
+  }
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n_words, nullptr}, offs, count);
+  k_apply<<<nb, kBlockThreads, 0, s>>>(EmitIds<OneImage>{src, bitmap, ids, nullptr, cap}, Count{n_words, nullptr},
+                                       offs);
+  HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
 

@@ -420,15 +420,16 @@ __device__ __forceinline__ bool tau_ok(uint32_t mask, uint32_t tau, bool any_tau
 // The linear and sorted layouts probe lane by lane, after the filter if there
 // is one.
 // bloom / log2_bloom: the filter to consult (the index's, or one position's
-// slice of it), or null.
-template <int kLayout = kLayoutBucketed, uint32_t kSlotStride = 1>
+// slice of it), or null. kSlots = false records no slots (slot_out unused),
+// for scans whose flags are not confirmed afterwards.
+template <int kLayout = kLayoutBucketed, uint32_t kSlotStride = 1, bool kSlots = true>
 __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, uint32_t tau, bool any_tau,
                                                uint32_t* __restrict__ slot_out, const uint64_t* bloom,
                                                uint32_t log2_bloom) {
   const uint32_t l = lane_id();
   // signature 0 cannot be stored in the table (it marks free slots)
   const bool ok_zero = (h == kEmptyKey) && tau_ok(ix.zero_sig_mask, tau, any_tau);
-  if (ok_zero) slot_out[l * kSlotStride] = ix.zero_slot;
+  if (kSlots && ok_zero) slot_out[l * kSlotStride] = ix.zero_slot;
   if (kLayout != kLayoutBucketed || bloom) {
     bool maybe = h != kEmptyKey;
     if (bloom) {
@@ -441,7 +442,7 @@ __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, 
     if (maybe) {
       const int64_t slot = find_slot_in<kLayout>(ix, h);
       ok = slot >= 0 && tau_ok(ix.tau_mask[slot], tau, any_tau);
-      if (ok) slot_out[l * kSlotStride] = (uint32_t)slot;
+      if (kSlots && ok) slot_out[l * kSlotStride] = (uint32_t)slot;
     }
     return ballot(ok) | ballot(ok_zero);
   }
@@ -471,7 +472,7 @@ __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, 
     const bool ok = (m0 | m1) && tau_ok(mask, ts, any_tau);
     // cross-lane reads only with every lane active: lane s may be idle inside `if (ok)`
     const uint32_t slot0 = (uint32_t)__shfl((int)bkt, (int)s, kWave) * kBucketSlots + 2u * (l & 7u);
-    if (ok) slot_out[s * kSlotStride] = slot0 + (m1 ? 1u : 0u);
+    if (kSlots && ok) slot_out[s * kSlotStride] = slot0 + (m1 ? 1u : 0u);
     hits |= (uint64_t)bytes_nonzero(ballot(ok)) << (8 * r);
     unresolved |= (uint64_t)(~bytes_nonzero(ballot(m0 | m1 | empty)) & 0xFFu) << (8 * r);
   }
@@ -480,7 +481,7 @@ __device__ __forceinline__ uint64_t tile_probe(const IndexView& ix, uint64_t h, 
   if ((unresolved >> l) & 1u) {
     const int64_t slot = find_slot(ix, h);
     ok_more = slot >= 0 && tau_ok(ix.tau_mask[slot], tau, any_tau);
-    if (ok_more) slot_out[l * kSlotStride] = (uint32_t)slot;
+    if (kSlots && ok_more) slot_out[l * kSlotStride] = (uint32_t)slot;
   }
   return hits | ballot(ok_more) | ballot(ok_zero);
 }

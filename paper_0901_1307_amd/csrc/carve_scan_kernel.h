@@ -12,7 +12,9 @@ namespace carve {
 
 constexpr int kScanThreads = 256;
 constexpr int kScanWaves = kScanThreads / (int)kWave;
-enum { kFlags = 0, kSigs = 1 };
+// kFlags: hit words and the matched slot of each flagged sector (for
+// confirmation); kFlagBits: hit words only; kSigs: the signatures themselves.
+enum { kFlags = 0, kSigs = 1, kFlagBits = 2 };
 
 // ------------------------------------------------------------ images
 // One image of a scan. tile_begin: its first tile in the scan's tile space.
@@ -133,10 +135,11 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
       h = tile_crc_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, A, B, prefetch);
     else
       h = tile_signature_pipelined<true>(ContiguousRows{tr.base, tr.n_valid}, my, wt, A, B, prefetch);
-    if constexpr (kMode == kFlags) {
+    if constexpr (kMode == kFlags || kMode == kFlagBits) {
       const uint32_t tau = (tr.tau_first + l) & (kClusterSectors - 1);
-      uint64_t hits = tile_probe<kLayout>(ix, h, tau, tr.any_tau != 0, hit_slot + g * kTileSectors, ix.bloom,
-                                          ix.log2_bloom_words);
+      uint64_t hits = tile_probe<kLayout, 1, kMode == kFlags>(
+          ix, h, tau, tr.any_tau != 0, kMode == kFlags ? hit_slot + g * kTileSectors : nullptr, ix.bloom,
+          ix.log2_bloom_words);
       if (tr.n_valid < kTileSectors) hits &= (1ull << tr.n_valid) - 1ull;
       if (l == 0) out[g] = hits;
     } else {
@@ -164,7 +167,8 @@ __device__ __forceinline__ uint64_t position_count(uint64_t n_sectors, uint32_t 
   return n_sectors > r ? (n_sectors - r + kPositions - 1) / kPositions : 0;
 }
 
-template <int kSig, int kLayout = kLayoutBucketed>
+// kSlots = false: no slot records (hit_slot unused).
+template <int kSig, int kLayout = kLayoutBucketed, bool kSlots = true>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan_tau(
     const uint8_t* __restrict__ image, uint64_t n_sectors, uint32_t tau0, uint64_t words_per_pos, uint32_t chunk,
     IndexView ix, uint64_t wt, uint64_t* __restrict__ tau_words, uint32_t* __restrict__ hit_slot) {
@@ -205,8 +209,8 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
       h = tile_crc_pipelined<true>(tr, my, A, B, prefetch);
     else
       h = tile_signature_pipelined<true>(tr, my, wt, A, B, prefetch);
-    uint64_t hits = tile_probe<kLayout, kPositions>(ix, h, p, false,
-                                                    hit_slot + (g * kTileSectors * kPositions + r), bloom, log2_bloom);
+    uint64_t hits = tile_probe<kLayout, kPositions, kSlots>(
+        ix, h, p, false, kSlots ? hit_slot + (g * kTileSectors * kPositions + r) : nullptr, bloom, log2_bloom);
     if (tr.n_valid < kTileSectors) hits &= (1ull << tr.n_valid) - 1ull;
     if (l == 0) tau_words[p * words_per_pos + g] = hits;
     if (!more) break;
