@@ -109,8 +109,18 @@ typedef struct {
 typedef struct {
   uint32_t blocks_per_cu;   /* work-groups of the persistent scan grid per compute unit; 0 = as many as fit */
   uint32_t tiles_per_chunk; /* consecutive 64-sector tiles a wave takes before striding; 0 = 1 */
-  uint32_t reserved[2];     /* must be zero */
+  uint32_t split;           /* carve_split_mode: how scans of one image under the per-cluster rule walk it */
+  uint32_t reserved;        /* must be zero */
 } carve_scan_config;
+
+/* The per-cluster rule (Section 3.1) lets a scan of one image be split by
+ * cluster position: position p's sectors only need S_p, so the chip's 8 XCDs
+ * each scan one position and keep one eighth of the prefilter in their L2. */
+typedef enum {
+  CARVE_SPLIT_AUTO = 0,     /* split when the prefilter is 4 MiB or more (too large for one XCD's L2) */
+  CARVE_SPLIT_OFF = 1,      /* always scan contiguously */
+  CARVE_SPLIT_ON = 2        /* always split (when the index has a prefilter) */
+} carve_split_mode;
 
 typedef struct {
   uint64_t n_master_sectors;
@@ -307,6 +317,22 @@ void ingest_free(carve_ingest* in);   /* NULL is a no-op; waits for transfers an
 int scan_image_noalloc(const carve_index* idx, const void* image, uint64_t n_bytes, uint32_t tau0, uint32_t tau_mode,
                        void* stream, uint64_t* ids, uint64_t cap, uint64_t* count);
 
+/*
+ * read_ceiling_probe -- the streaming-read rate the scan kernels are measured
+ * against: one kernel reads the whole sectors of a device image once with a
+ * scan kernel's access pattern (64-sector tiles, 16 B per lane with
+ * non-temporal loads, two phases of a tile in flight, a resident grid) and no
+ * other work. Not a step of the method; a measurement of the chip.
+ *   pattern        0: contiguous tiles (as the contiguous scan); 1: split by
+ *                  cluster position (as the position-split scan).
+ *   blocks_per_cu  resident work-groups per CU; 0 = as many as fit.
+ *   ms             host; receives the kernel's duration (HIP events).
+ * Synchronizes `stream`. EINVAL for fewer than 512 whole sectors, a
+ * misaligned or non-device image, a bad pattern.
+ */
+int read_ceiling_probe(const void* image, uint64_t n_bytes, uint32_t pattern, uint32_t blocks_per_cu, void* stream,
+                       float* ms);
+
 /* index_stats -- sizes of a built index (host struct). */
 int index_stats(const carve_index* idx, carve_index_stats* out);
 
@@ -324,6 +350,53 @@ int index_get_scan_config(const carve_index* idx, carve_scan_config* cfg);
  * for the index; *best (host, may be NULL) receives it. Synchronizes stream.
  */
 int autotune_scan(carve_index* idx, const void* sample_image, uint64_t n_bytes, void* stream, carve_scan_config* best);
+
+/*
+ * autotune_index -- build_master_index with the index layout, the prefilter
+ * size and the scan's launch shape picked by timing them on a sample image
+ * (the occupancy and layout study of Section 4, the probe of Eq. (3)). Every
+ * choice gives the same results; only the time differs.
+ *   Stage 1 builds each candidate (layout x prefilter bits per signature) from
+ *   `base` and times its scan of the sample at one launch shape, contiguous
+ *   and position-split; stage 2 sweeps the fastest candidate's launch shapes
+ *   (as autotune_scan). The pick is cached for the process under the device's
+ *   architecture, the signature kind, the master count's power-of-two class,
+ *   max_load and the space: a later call with the same key builds the cached
+ *   pick without timing.
+ *   master_sectors, file_sector_offsets, n_files, base   as build_master_index
+ *                  (base: host or NULL; its layout and bloom_bits_per_key are
+ *                  replaced by each candidate's).
+ *   space          host or NULL (every layout; the automatic prefilter and 8,
+ *                  16 and 32 bits per signature).
+ *   sample_image   device, 16-B aligned, at least one sector: an image like
+ *                  the ones to be scanned (not necessarily one of them).
+ *   out            receives the picked index with the picked launch shape.
+ *   result         host or NULL: what was picked.
+ * Synchronizes `stream`. Errors as build_master_index and autotune_scan.
+ */
+#define CARVE_TUNE_NO_CACHE 1u    /* time the candidates even when the key is cached (and cache the new pick) */
+#define CARVE_TUNE_CONTIGUOUS 2u  /* the index will serve batches (scan_batch, the server): time the batch
+                                     kernel, over the sample cut into 16 images of uneven sizes */
+typedef struct {
+  uint32_t layouts;        /* bit l: try carve_index_layout l; 0 = all three */
+  uint32_t n_bloom;        /* entries of bloom_bits (at most 8); 0 = {0 (automatic), 8, 16, 32} */
+  uint32_t bloom_bits[8];  /* bloom_bits_per_key candidates (0 = automatic, CARVE_BLOOM_OFF = none, 4..64) */
+  uint32_t flags;          /* CARVE_TUNE_* */
+  uint32_t reserved[2];    /* must be zero */
+} carve_tune_space;
+
+typedef struct {
+  carve_index_params params;  /* the picked build parameters */
+  carve_scan_config config;   /* the picked launch shape (already set on the index) */
+  float kernel_ms;            /* mean scan-kernel time of the pick on the sample (cached: when it was timed) */
+  uint32_t candidates;        /* indexes built and timed (0 when taken from the cache) */
+  uint32_t from_cache;        /* 1: the pick came from the cache */
+  uint32_t reserved;
+} carve_tune_result;
+
+int autotune_index(const void* master_sectors, const uint64_t* file_sector_offsets, uint32_t n_files,
+                   const carve_index_params* base, const carve_tune_space* space, const void* sample_image,
+                   uint64_t n_bytes, void* stream, carve_index** out, carve_tune_result* result);
 
 /*
  * scan_batch -- scan_image over n_images images at once: one persistent

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRCS = [os.path.join(HERE, "csrc", "carve.hip"), os.path.join(HERE, "csrc", "carve_server.hip"),
-        os.path.join(HERE, "csrc", "carve_ingest.hip")]
+        os.path.join(HERE, "csrc", "carve_ingest.hip"), os.path.join(HERE, "csrc", "carve_probe.hip")]
 LIB = os.path.join(HERE, "libcarve.so")
 ARCH = "gfx950"
 

@@ -21,6 +21,7 @@ CARVE_OK, CARVE_EINVAL, CARVE_ENOMEM, CARVE_ETRUNC, CARVE_EDEVICE, CARVE_EUNSUPP
 CARVE_SIG_DJB2_64, CARVE_SIG_CRC64_ISO = 0, 1
 CARVE_TAU_PER_CLUSTER, CARVE_TAU_ANY = 0, 1
 CARVE_LAYOUT_BUCKETED, CARVE_LAYOUT_LINEAR, CARVE_LAYOUT_SORTED = 0, 1, 2
+CARVE_SPLIT_AUTO, CARVE_SPLIT_OFF, CARVE_SPLIT_ON = 0, 1, 2
 
 MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4")])
 BATCH_MATCH_DTYPE = np.dtype([("disk_sector", "<u8"), ("file_id", "<u4"), ("sector_in_file", "<u4"),
@@ -38,7 +39,7 @@ EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_match
            "server_release", "server_release_many", "server_stats", "server_free", "free_index", "free_scan",
            "free_batch", "carve_last_error", "build_fragment_index", "scan_fragments", "ingest_create",
            "ingest_scan", "ingest_flagged_sectors", "ingest_matches", "ingest_stats", "ingest_free",
-           "scan_image_noalloc")
+           "scan_image_noalloc", "read_ceiling_probe", "autotune_index")
 
 
 class CarveError(RuntimeError):
@@ -58,7 +59,20 @@ class _IndexParams(ctypes.Structure):
 
 class _ScanConfig(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("tiles_per_chunk", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("split", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _TuneSpace(ctypes.Structure):
+    _fields_ = [("layouts", ctypes.c_uint32), ("n_bloom", ctypes.c_uint32), ("bloom_bits", ctypes.c_uint32 * 8),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("params", _IndexParams), ("config", _ScanConfig), ("kernel_ms", ctypes.c_float),
+                ("candidates", ctypes.c_uint32), ("from_cache", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+CARVE_TUNE_NO_CACHE, CARVE_TUNE_CONTIGUOUS = 1, 2
 
 
 class _ImageDesc(ctypes.Structure):
@@ -118,6 +132,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.build_master_index.argtypes = [P, P, U32, ctypes.POINTER(_IndexParams), P, PP]
     lib.scan_image.restype = I32
     lib.scan_image.argtypes = [P, P, U64, U32, U32, P, PP]
+    lib.autotune_index.restype = I32
+    lib.autotune_index.argtypes = [P, P, U32, ctypes.POINTER(_IndexParams), ctypes.POINTER(_TuneSpace), P, U64, P, PP,
+                                   ctypes.POINTER(_TuneResult)]
+    lib.read_ceiling_probe.restype = I32
+    lib.read_ceiling_probe.argtypes = [P, U64, U32, U32, P, ctypes.POINTER(ctypes.c_float)]
     lib.scan_image_noalloc.restype = I32
     lib.scan_image_noalloc.argtypes = [P, P, U64, U32, U32, P, P, U64, P]
     lib.flagged_sectors.restype = I32
@@ -247,10 +266,11 @@ class Index:
     def scan_config(self) -> dict:
         c = _ScanConfig()
         _check(load_library().index_get_scan_config(self.handle, ctypes.byref(c)))
-        return {"blocks_per_cu": int(c.blocks_per_cu), "tiles_per_chunk": int(c.tiles_per_chunk)}
+        return {"blocks_per_cu": int(c.blocks_per_cu), "tiles_per_chunk": int(c.tiles_per_chunk),
+                "split": int(c.split)}
 
-    def set_scan_config(self, blocks_per_cu: int = 0, tiles_per_chunk: int = 0):
-        c = _ScanConfig(int(blocks_per_cu), int(tiles_per_chunk))
+    def set_scan_config(self, blocks_per_cu: int = 0, tiles_per_chunk: int = 0, split: int = CARVE_SPLIT_AUTO):
+        c = _ScanConfig(int(blocks_per_cu), int(tiles_per_chunk), int(split))
         _check(load_library().index_set_scan_config(self.handle, ctypes.byref(c)))
 
     def autotune(self, sample: torch.Tensor, stream=None) -> dict:
@@ -259,7 +279,8 @@ class Index:
         c = _ScanConfig()
         _check(load_library().autotune_scan(self.handle, img.data_ptr(), img.numel(), _stream_ptr(stream),
                                             ctypes.byref(c)))
-        return {"blocks_per_cu": int(c.blocks_per_cu), "tiles_per_chunk": int(c.tiles_per_chunk)}
+        return {"blocks_per_cu": int(c.blocks_per_cu), "tiles_per_chunk": int(c.tiles_per_chunk),
+                "split": int(c.split)}
 
     def close(self):
         h, self.handle = self.handle, None
@@ -365,6 +386,40 @@ def build_master_index(master_sectors: torch.Tensor, file_sector_offsets: Sequen
     return Index(h.value, m, off.tolist())
 
 
+def autotune_index(master_sectors: torch.Tensor, file_sector_offsets: Sequence[int], sample: torch.Tensor,
+                   sig_kind: int = CARVE_SIG_DJB2_64, max_load: float = 0.0, layouts: int = 0, bloom_bits=(),
+                   contiguous_only: bool = False, no_cache: bool = False, stream=None):
+    """build_master_index with the layout, prefilter size and launch shape
+    timed on a sample image (device tensor); returns (Index, pick) where pick
+    names the chosen parameters."""
+    lib = load_library()
+    m = _dev_u8(master_sectors, "master_sectors")
+    smp = _dev_u8(sample, "sample")
+    off = np.ascontiguousarray(file_sector_offsets, dtype=np.uint64)
+    if off.size < 1 or m.numel() != int(off[-1]) * SECTOR:
+        raise ValueError("master_sectors size does not match file_sector_offsets[-1] sectors")
+    base = _IndexParams(int(sig_kind), float(max_load), 0, 0)
+    bb = list(bloom_bits)
+    if len(bb) > 8:
+        raise ValueError("at most 8 bloom_bits candidates")
+    sp = _TuneSpace(int(layouts), len(bb), (ctypes.c_uint32 * 8)(*bb),
+                    (CARVE_TUNE_CONTIGUOUS if contiguous_only else 0) | (CARVE_TUNE_NO_CACHE if no_cache else 0))
+    h = ctypes.c_void_p()
+    r = _TuneResult()
+    _check(lib.autotune_index(m.data_ptr() if m.numel() else None, off.ctypes.data, off.size - 1, ctypes.byref(base),
+                              ctypes.byref(sp), smp.data_ptr(), smp.numel(), _stream_ptr(stream), ctypes.byref(h),
+                              ctypes.byref(r)))
+    names = {CARVE_LAYOUT_BUCKETED: "bucketed", CARVE_LAYOUT_LINEAR: "linear", CARVE_LAYOUT_SORTED: "sorted"}
+    bits = int(r.params.bloom_bits_per_key)
+    pick = {"layout": names.get(int(r.params.layout), str(r.params.layout)),
+            "bloom_bits_per_key": "auto" if bits == 0 else ("off" if bits == CARVE_BLOOM_OFF else bits),
+            "blocks_per_cu": int(r.config.blocks_per_cu), "tiles_per_chunk": int(r.config.tiles_per_chunk),
+            "split": {CARVE_SPLIT_AUTO: "auto", CARVE_SPLIT_OFF: "off", CARVE_SPLIT_ON: "on"}[int(r.config.split)],
+            "kernel_ms_on_sample": round(float(r.kernel_ms), 4), "candidates": int(r.candidates),
+            "from_cache": bool(r.from_cache)}
+    return Index(h.value, m, off.tolist()), pick
+
+
 def scan_image(index: Index, image: torch.Tensor, tau0: int = 0, tau_mode: int = CARVE_TAU_PER_CLUSTER,
                stream=None, scan: Optional[Scan] = None, n_bytes: Optional[int] = None) -> Scan:
     """Flag the sectors of a device-resident image (asynchronous on the stream)."""
@@ -403,6 +458,16 @@ def scan_image_noalloc(index: Index, image: torch.Tensor, ids: torch.Tensor, cou
     _check(lib.scan_image_noalloc(index.handle, img.data_ptr() if nb else None, nb, tau0, tau_mode,
                                   _stream_ptr(stream), ids.data_ptr() if ids.numel() else None, ids.numel(),
                                   count.data_ptr()))
+
+
+def read_ceiling_probe(image: torch.Tensor, split: bool = False, blocks_per_cu: int = 0, stream=None) -> float:
+    """Duration (ms) of one streaming read of the image's whole sectors with a
+    scan kernel's access pattern (contiguous, or split by cluster position)."""
+    img = _dev_u8(image, "image")
+    ms = ctypes.c_float()
+    _check(load_library().read_ceiling_probe(img.data_ptr(), img.numel(), int(bool(split)), int(blocks_per_cu),
+                                             _stream_ptr(stream), ctypes.byref(ms)))
+    return float(ms.value)
 
 
 FRAGMENT = 64      # bytes of a master fragment and of an image window

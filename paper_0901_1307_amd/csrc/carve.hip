@@ -418,12 +418,13 @@ __global__ void k_bloom_build(const uint64_t* __restrict__ keys, uint64_t n_slot
 
 // The filter split by cluster position: slice t holds the keys with a master
 // at position t (placed like the whole filter, in 2^log2_words words). Built
-// for filters of 2^kSplitMinLog2 words (4 MiB) and more, which cannot stay in
-// an XCD's 4 MB L2 beside the streamed image; per-cluster scans of one image
-// then run position-split (k_scan_tau), each XCD holding one eighth. Smaller
-// filters stay in L2 whole, and the contiguous scan is faster with them
-// (1.29 vs 1.35 ms on the 8 GiB mid workload, 2 MiB filter; the split took
-// the 64 GiB large workload, 8 MiB filter, from 11.79 to 10.86 ms).
+// for every sector index with a filter. A filter of 2^kSplitMinLog2 words
+// (4 MiB) or more cannot stay in an XCD's 4 MB L2 beside the streamed image,
+// so per-cluster scans of one image run position-split (k_scan_tau) by
+// default, each XCD holding one eighth; smaller filters stay in L2 whole and
+// the contiguous scan is faster with them (1.29 vs 1.35 ms on the 8 GiB mid
+// workload, 2 MiB filter; the split took the 64 GiB large workload, 8 MiB
+// filter, from 11.79 to 10.86 ms). carve_scan_config.split overrides it.
 constexpr uint32_t kSplitMinLog2 = 19;
 __global__ void k_bloom_tau_build(const uint64_t* __restrict__ keys, const uint8_t* __restrict__ tau_mask,
                                   uint64_t n_slots, uint32_t log2_words, uint64_t* bloom_tau) {
@@ -1038,9 +1039,21 @@ struct carve_batch : carve_scan {};
 namespace {
 
 OneImage one_image(const carve_scan* sc) { return OneImage{sc->desc[0]}; }
+
+// Whether a scan of one image under rule any_tau runs position-split
+// (k_scan_tau): never for the any-position rule or without the split filter;
+// else as the index's scan config says (automatic: filters of 4 MiB and more).
+bool use_split(const carve_index* idx, uint32_t any_tau);
 FragmentWindows fragment_windows(const carve_scan* sc) { return FragmentWindows{sc->desc[0]}; }
 ManyImages many_images(const carve_scan* sc) {
   return ManyImages{sc->d_desc.as<ImageDesc>(), sc->n_images};
+}
+
+bool use_split(const carve_index* idx, uint32_t any_tau) {
+  if (any_tau || !idx->bloom_tau.bytes) return false;
+  if (idx->cfg.split == CARVE_SPLIT_ON) return true;
+  if (idx->cfg.split == CARVE_SPLIT_OFF) return false;
+  return idx->log2_bloom_words >= kSplitMinLog2;
 }
 
 // n (at most 8) consecutive device words, in one copy.
@@ -1108,7 +1121,7 @@ int launch_scan(carve_scan* sc, const Src& src) {
   ImageDesc one{};
   if constexpr (std::is_same<Src, OneImage>::value) {
     one = src.d;
-    split = one.any_tau == 0 && idx->bloom_tau.bytes != 0;
+    split = use_split(idx, one.any_tau);
   }
   const uint64_t slot = 2 * (sc->n_timed % kTimedRing);
   if (sc->timing) HIP_TRY(hipEventRecord(sc->ev[slot], s));
@@ -1167,7 +1180,7 @@ int reserve_scan(carve_scan* sc) {
   CARVE_TRY(sc->ids.reserve(n_words * kTileSectors * 8));
   // a single image of sectors may be scanned split by position (k_scan_tau):
   // its tiles of 64 clusters reach slot 512 * ceil(n_words / 8)
-  const bool split = !sc->batch && !sc->fragments && sc->idx && sc->idx->bloom_tau.bytes;
+  const bool split = !sc->batch && !sc->fragments && sc->idx && use_split(sc->idx, sc->desc[0].any_tau);
   const uint64_t tau_tiles = cdiv(n_words, kPositions);
   CARVE_TRY(sc->hit_slot.reserve((split ? tau_tiles * kPositions : n_words) * kTileSectors * 4));
   if (split) CARVE_TRY(sc->tau_words.reserve(kPositions * tau_tiles * 8));
@@ -1619,8 +1632,23 @@ int build_index(const void* master_sectors, const uint64_t* file_sector_offsets,
       else
         k_bloom_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw,
                                                             ix->bloom.as<uint64_t>());
-      if (unit == kSectorBytes && lw >= kSplitMinLog2) {   // the same filter split by position: 8 eighths
-        const uint32_t ls = lw - 3;
+      // The filter split by position (sector indexes): slice t holds the keys
+      // with a master at position t, about an eighth of them, and each XCD of a
+      // position-split scan keeps only its slice in L2, so the slices are sized
+      // apart from the whole filter: automatically 16 bits per key of a slice,
+      // up to 4 MiB per slice (on the 64 GiB large workload, 16M keys: 10.57 ms
+      // at 16 bits per key against 10.82 ms at the whole filter's 4, whose
+      // false positives send 16% of the sectors to the table); else the
+      // requested bits per key. At least 2 words per slice (bloom_place needs
+      // log2_words >= 1: its shift by 64 - log2_words).
+      if (unit == kSectorBytes) {
+        constexpr uint64_t kSliceAutoBytes = 4ull << 20;
+        const uint64_t per_slice = cdiv(keys_n, kPositions);
+        const uint64_t bits = p.bloom_bits_per_key ? p.bloom_bits_per_key : 16;
+        uint32_t ls = 1;
+        while (ls < 32 && (64ull << ls) < bits * per_slice &&
+               (p.bloom_bits_per_key || (8ull << (ls + 1)) <= kSliceAutoBytes))
+          ++ls;
         if ((rc = ix->bloom_tau.reserve((8ull * kPositions) << ls))) return bail2(rc);
         ix->log2_bloom_tau = ls;
         if (hipMemsetAsync(ix->bloom_tau.p, 0, (8ull * kPositions) << ls, s) != hipSuccess)
@@ -1669,8 +1697,8 @@ extern "C" int index_stats(const carve_index* idx, carve_index_stats* out) {
 
 extern "C" int index_set_scan_config(carve_index* idx, const carve_scan_config* cfg) {
   if (!idx || !cfg) return fail(CARVE_EINVAL, "index_set_scan_config: null argument");
-  if (cfg->reserved[0] || cfg->reserved[1]) return fail(CARVE_EINVAL, "index_set_scan_config: reserved must be zero");
-  if (cfg->blocks_per_cu > 64 || cfg->tiles_per_chunk > (1u << 20))
+  if (cfg->reserved) return fail(CARVE_EINVAL, "index_set_scan_config: reserved must be zero");
+  if (cfg->blocks_per_cu > 64 || cfg->tiles_per_chunk > (1u << 20) || cfg->split > CARVE_SPLIT_ON)
     return fail(CARVE_EINVAL, "index_set_scan_config: out of range");
   idx->cfg = *cfg;
   return CARVE_OK;
@@ -1791,7 +1819,7 @@ extern "C" int scan_image_noalloc(const carve_index* idx, const void* image, uin
   const uint32_t per_cu = idx->cfg.blocks_per_cu;
   const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
   const uint64_t nb = cdiv(n_words, kItemsPerBlock);
-  if (src.d.any_tau == 0 && idx->bloom_tau.bytes != 0) {   // as scan_image: the position-split scan
+  if (use_split(idx, src.d.any_tau)) {   // as scan_image: the position-split scan
     CARVE_TRY(launch_k_scan_tau(idx->sig_kind, idx->layout, src.d, cdiv(n_words, kPositions), chunk, per_cu,
                                 idx->view(), idx->weights, tau_words, nullptr, s));
     k_reduce<<<nb, kBlockThreads, 0, s>>>(TauMergeItems{tau_words, cdiv(n_words, kPositions), bitmap, n_words,
@@ -2108,12 +2136,87 @@ CARVE_HIDDEN int carve_batch_stage_out(carve_batch* b, int with_matches, const c
   return CARVE_OK;
 }
 
-extern "C" int autotune_scan(carve_index* idx, const void* sample_image, uint64_t n_bytes, void* stream,
-                             carve_scan_config* best) {
-  if (!idx) return fail(CARVE_EINVAL, "autotune_scan: null index");
-  if (idx->unit_bytes != kSectorBytes) return fail(CARVE_EINVAL, "autotune_scan: a fragment index");
-  if (n_bytes < kSectorBytes) return fail(CARVE_EINVAL, "autotune_scan: the sample needs at least one sector");
-  CARVE_TRY(validate_image(sample_image, n_bytes, 0, CARVE_TAU_PER_CLUSTER, "autotune_scan", -1));
+namespace {
+// Mean kernel time of the scan of a sample image with the index's current
+// launch shape: one warm-up run, then at least 5 timed runs and about 8 ms of
+// kernel time (a small sample needs more runs to rank shapes). *sc is reused.
+int time_scan(carve_index* idx, const void* sample, uint64_t n_bytes, void* stream, carve_scan** sc, float* mean) {
+  float total = 0.f;
+  int timed = 0;
+  for (int rep = 0;; ++rep) {
+    CARVE_TRY(scan_image(idx, sample, n_bytes, 0, CARVE_TAU_PER_CLUSTER, stream, sc));
+    if (rep == 0) {
+      CARVE_TRY(scan_set_timing(*sc, 1));   // the first run only warms up
+      continue;
+    }
+    float ms = 0.f;
+    CARVE_TRY(scan_kernel_ms(*sc, &ms));
+    total += ms;
+    ++timed;
+    if (timed >= 5 && (total >= 8.f || timed >= 64)) break;
+  }
+  *mean = total / (float)timed;
+  return CARVE_OK;
+}
+
+// Mean kernel time of the batch scan (the kernel batches and the server run)
+// over the sample cut into 16 images of uneven sizes (piece i about (i + 1)/136
+// of it, cluster-aligned), timed as time_scan does. *b is reused.
+int time_batch(carve_index* idx, const void* sample, uint64_t n_bytes, void* stream, carve_batch** b, float* mean) {
+  constexpr uint32_t kPieces = 16;
+  const uint64_t n_sec = n_bytes / kSectorBytes;
+  carve_image_desc d[kPieces];
+  uint64_t at = 0;
+  for (uint32_t i = 0; i < kPieces; ++i) {
+    uint64_t len = n_sec * (i + 1) / (kPieces * (kPieces + 1) / 2);
+    len -= len % kClusterSectors;
+    if (i == kPieces - 1 || at + len > n_sec) len = n_sec - at;
+    d[i] = carve_image_desc{(const uint8_t*)sample + at * kSectorBytes, len * kSectorBytes, 0, CARVE_TAU_PER_CLUSTER};
+    at += len;
+  }
+  float total = 0.f;
+  int timed = 0;
+  for (int rep = 0;; ++rep) {
+    CARVE_TRY(scan_batch(idx, d, kPieces, stream, b));
+    if (rep == 0) {
+      CARVE_TRY(scan_set_timing(*b, 1));
+      continue;
+    }
+    float ms = 0.f;
+    CARVE_TRY(scan_kernel_ms(*b, &ms));
+    total += ms;
+    ++timed;
+    if (timed >= 5 && (total >= 8.f || timed >= 64)) break;
+  }
+  *mean = total / (float)timed;
+  return CARVE_OK;
+}
+
+// time_scan, or time_batch for an index that will serve batches.
+int time_walk(carve_index* idx, const void* sample, uint64_t n_bytes, void* stream, bool batches, carve_scan** sc,
+              float* mean) {
+  if (!batches) return time_scan(idx, sample, n_bytes, stream, sc, mean);
+  carve_batch* b = (*sc && (*sc)->batch) ? static_cast<carve_batch*>(*sc) : nullptr;
+  if (*sc && !(*sc)->batch) {
+    free_scan(*sc);
+    *sc = nullptr;
+  }
+  const int rc = time_batch(idx, sample, n_bytes, stream, &b, mean);
+  *sc = b;
+  return rc;
+}
+
+// The walks a per-cluster scan of one image can take with this index.
+std::vector<uint32_t> split_modes(const carve_index* idx, bool contiguous_only) {
+  if (!idx->bloom_tau.bytes || contiguous_only) return {CARVE_SPLIT_OFF};
+  return {CARVE_SPLIT_OFF, CARVE_SPLIT_ON};
+}
+
+// Every launch shape (blocks per CU x tiles per chunk x walk) timed on the
+// sample (contiguous_only: the batch kernel, on the sample cut into images);
+// the index keeps the fastest. *best_ms receives its mean kernel time.
+int tune_shapes(carve_index* idx, const void* sample, uint64_t n_bytes, void* stream, bool contiguous_only,
+                carve_scan_config* best, float* best_ms) {
   const carve_scan_config saved = idx->cfg;
   carve_scan* sc = nullptr;
   carve_scan_config winner = saved;
@@ -2121,37 +2224,188 @@ extern "C" int autotune_scan(carve_index* idx, const void* sample_image, uint64_
   const uint32_t blocks[] = {0, 3, 2};
   const uint32_t chunks[] = {1, 2, 4, 8, 16};
   int rc = CARVE_OK;
-  for (uint32_t bpc : blocks) {
-    for (uint32_t ch : chunks) {
-      idx->cfg = carve_scan_config{bpc, ch, {0, 0}};
-      // one warm-up run, then at least 5 timed runs and about 8 ms of kernel
-      // time per shape (a small sample needs more runs to rank the shapes)
-      float total = 0.f;
-      int timed = 0;
-      for (int rep = 0; rc == CARVE_OK; ++rep) {
-        rc = scan_image(idx, sample_image, n_bytes, 0, CARVE_TAU_PER_CLUSTER, stream, &sc);
-        if (rc == CARVE_OK && rep == 0) rc = scan_set_timing(sc, 1);   // the first run only warms up
-        float ms = 0.f;
-        if (rc == CARVE_OK && rep > 0) {
-          rc = scan_kernel_ms(sc, &ms);
-          total += ms;
-          ++timed;
+  for (uint32_t sp : split_modes(idx, contiguous_only)) {
+    for (uint32_t bpc : blocks) {
+      for (uint32_t ch : chunks) {
+        idx->cfg = carve_scan_config{bpc, ch, sp, 0};
+        float mean = 0.f;
+        if ((rc = time_walk(idx, sample, n_bytes, stream, contiguous_only, &sc, &mean)) != CARVE_OK) break;
+        if (mean < winner_ms) {
+          winner_ms = mean;
+          winner = idx->cfg;
         }
-        if (timed >= 5 && (total >= 8.f || timed >= 64)) break;
       }
-      total /= timed ? (float)timed : 1.f;   // mean per run
       if (rc != CARVE_OK) break;
-      if (total < winner_ms) {
-        winner_ms = total;
-        winner = idx->cfg;
-      }
     }
     if (rc != CARVE_OK) break;
   }
   free_scan(sc);
   idx->cfg = rc == CARVE_OK ? winner : saved;
-  if (rc == CARVE_OK && best) *best = winner;
+  if (rc == CARVE_OK) {
+    if (best) *best = winner;
+    if (best_ms) *best_ms = winner_ms;
+  }
   return rc;
+}
+
+int check_sample(const carve_index* idx, const void* sample, uint64_t n_bytes, const char* who) {
+  if (idx && idx->unit_bytes != kSectorBytes) return fail(CARVE_EINVAL, "%s: a fragment index", who);
+  if (n_bytes < kSectorBytes) return fail(CARVE_EINVAL, "%s: the sample needs at least one sector", who);
+  CARVE_TRY(validate_image(sample, n_bytes, 0, CARVE_TAU_PER_CLUSTER, who, -1));
+  if (!gpu_readable(sample)) return fail(CARVE_EINVAL, "%s: the sample is not in device memory", who);
+  return CARVE_OK;
+}
+}  // namespace
+
+extern "C" int autotune_scan(carve_index* idx, const void* sample_image, uint64_t n_bytes, void* stream,
+                             carve_scan_config* best) {
+  if (!idx) return fail(CARVE_EINVAL, "autotune_scan: null index");
+  CARVE_TRY(check_sample(idx, sample_image, n_bytes, "autotune_scan"));
+  return tune_shapes(idx, sample_image, n_bytes, stream, false, best, nullptr);
+}
+
+// ------------------------------------------------------------ index autotuner
+namespace {
+struct TunePick {
+  carve_index_params params;
+  carve_scan_config cfg;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, TunePick>> g_tune_cache;
+
+// The cache key: the device's architecture, the signature kind, the master
+// count's power-of-two class, the load ceiling and the candidate space.
+int tune_key(const carve_index_params& base, const carve_tune_space& sp, uint64_t n_masters, std::string* key) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  uint32_t cls = 0;
+  while ((1ull << cls) < n_masters) ++cls;
+  char buf[512];
+  int n = snprintf(buf, sizeof buf, "%s|sig%u|m2^%u|load%.3f|lay%x|flags%x|bloom", prop.gcnArchName, base.sig_kind, cls,
+                   (double)base.max_load, sp.layouts, sp.flags & ~(uint32_t)CARVE_TUNE_NO_CACHE);
+  for (uint32_t i = 0; i < sp.n_bloom && n > 0 && n < (int)sizeof buf; ++i)
+    n += snprintf(buf + n, sizeof buf - n, ",%u", sp.bloom_bits[i]);
+  *key = buf;
+  return CARVE_OK;
+}
+}  // namespace
+
+extern "C" int autotune_index(const void* master_sectors, const uint64_t* file_sector_offsets, uint32_t n_files,
+                              const carve_index_params* base, const carve_tune_space* space, const void* sample_image,
+                              uint64_t n_bytes, void* stream, carve_index** out, carve_tune_result* result) {
+  if (!out) return fail(CARVE_EINVAL, "autotune_index: out is null");
+  *out = nullptr;
+  CARVE_TRY(check_sample(nullptr, sample_image, n_bytes, "autotune_index"));
+  carve_index_params b{};
+  if (base) b = *base;
+  carve_tune_space sp{};
+  if (space) sp = *space;
+  if (sp.n_bloom > 8 || sp.reserved[0] || sp.reserved[1] || (sp.layouts & ~7u))
+    return fail(CARVE_EINVAL, "autotune_index: bad tuning space");
+  if (sp.flags & ~(uint32_t)(CARVE_TUNE_NO_CACHE | CARVE_TUNE_CONTIGUOUS))
+    return fail(CARVE_EINVAL, "autotune_index: unknown flags");
+  if (!sp.layouts) sp.layouts = 7u;
+  if (!sp.n_bloom) {   // the automatic size, then 8, 16 and 32 bits per signature
+    const uint32_t dflt[] = {0, 8, 16, 32};
+    sp.n_bloom = 4;
+    for (uint32_t i = 0; i < 4; ++i) sp.bloom_bits[i] = dflt[i];
+  }
+  if (b.max_load == 0.f) b.max_load = 0.5f;
+  const bool contiguous = (sp.flags & CARVE_TUNE_CONTIGUOUS) != 0;
+  const uint64_t n_masters = n_files && file_sector_offsets ? file_sector_offsets[n_files] : 0;
+  std::string key;
+  CARVE_TRY(tune_key(b, sp, n_masters, &key));
+  carve_tune_result res{};
+  if (!(sp.flags & CARVE_TUNE_NO_CACHE)) {
+    TunePick hit{};
+    bool found = false;
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      for (const auto& e : g_tune_cache)
+        if (e.first == key) {
+          hit = e.second;
+          found = true;
+        }
+    }
+    if (found) {   // the pick of an earlier tuning of this class: build it, no timing
+      carve_index* ix = nullptr;
+      CARVE_TRY(build_master_index(master_sectors, file_sector_offsets, n_files, &hit.params, stream, &ix));
+      ix->cfg = hit.cfg;
+      res.params = hit.params;
+      res.config = hit.cfg;
+      res.kernel_ms = hit.ms;
+      res.from_cache = 1;
+      if (result) *result = res;
+      *out = ix;
+      return CARVE_OK;
+    }
+  }
+  // Stage 1: every (layout, filter) candidate at one launch shape, each walk,
+  // the first candidate of the space (the default, bucketed with the
+  // automatic filter, when the space holds it) first; a later candidate
+  // replaces the best only when it is more than 1% faster: on a sample,
+  // differences below that are noise and do not carry over to the images.
+  // Stage 2: the picked candidate's full launch-shape sweep.
+  constexpr float kClearGain = 0.99f;
+  carve_index* best = nullptr;
+  carve_index_params best_p{};
+  float best_ms = 1e30f;
+  carve_scan* sc = nullptr;
+  int rc = CARVE_OK;
+  for (uint32_t layout = 0; layout < 3 && rc == CARVE_OK; ++layout) {
+    if (!((sp.layouts >> layout) & 1u)) continue;
+    for (uint32_t i = 0; i < sp.n_bloom && rc == CARVE_OK; ++i) {
+      carve_index_params p = b;
+      p.layout = layout;
+      p.bloom_bits_per_key = sp.bloom_bits[i];
+      carve_index* ix = nullptr;
+      if ((rc = build_master_index(master_sectors, file_sector_offsets, n_files, &p, stream, &ix)) != CARVE_OK) break;
+      ++res.candidates;
+      float cand_ms = 1e30f;
+      for (uint32_t w : split_modes(ix, contiguous)) {
+        ix->cfg = carve_scan_config{2, 1, w, 0};
+        float ms = 0.f;
+        if ((rc = time_walk(ix, sample_image, n_bytes, stream, contiguous, &sc, &ms)) != CARVE_OK) break;
+        if (ms < cand_ms) cand_ms = ms;
+      }
+      free_scan(sc);   // a scan object belongs to one index
+      sc = nullptr;
+      if (rc == CARVE_OK && (!best || cand_ms < best_ms * kClearGain)) {
+        free_index(best);
+        best = ix;
+        best_p = p;
+        best_ms = cand_ms;
+      } else {
+        free_index(ix);
+      }
+    }
+  }
+  if (rc == CARVE_OK && !best) rc = fail(CARVE_EINVAL, "autotune_index: no candidate");
+  carve_scan_config cfg{};
+  if (rc == CARVE_OK) rc = tune_shapes(best, sample_image, n_bytes, stream, contiguous, &cfg, &best_ms);
+  if (rc != CARVE_OK) {
+    free_index(best);
+    return rc;
+  }
+  res.params = best_p;
+  res.config = cfg;
+  res.kernel_ms = best_ms;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    bool replaced = false;
+    for (auto& e : g_tune_cache)
+      if (e.first == key) {
+        e.second = TunePick{best_p, cfg, best_ms};
+        replaced = true;
+      }
+    if (!replaced) g_tune_cache.emplace_back(key, TunePick{best_p, cfg, best_ms});
+  }
+  if (result) *result = res;
+  *out = best;
+  return CARVE_OK;
 }
 
 CARVE_HIDDEN uint32_t carve_index_unit_bytes(const carve_index* idx) { return idx ? idx->unit_bytes : 0; }

@@ -327,6 +327,9 @@ enum : int { kLayoutBucketed = 0, kLayoutLinear = 1, kLayoutSorted = 2 };
 // Register-blocked Bloom filter: a key owns one 64-bit word and sets 4 of
 // its bits. Word and bit positions come from the high half of a second
 // multiplicative hash (djb2's low bits are weak: 33 = 1 mod 32).
+// log2_words must be in 1..40: the word index is a shift by 64 - log2_words,
+// and a shift by 64 is not a shift by 64 on this chip (its amount is taken
+// mod 64), so a one-word filter would index far past its end.
 constexpr uint64_t kBloomMul = 0xD6E8FEB86659FD93ull;
 __device__ __forceinline__ void bloom_place(uint64_t h, uint32_t log2_words, uint32_t* word, uint64_t* bits) {
   const uint64_t p = h * kBloomMul;

@@ -1,6 +1,7 @@
 """The batched workload at its full size, in the launch configuration bench.py
 times: the 256 images of log-uniform sizes 1 MiB-1 GiB (about 47 GiB) against
-the mid master set, the launch shape the autotuner picks on a tuning sample,
+the mid master set, the index and launch shape autotune_index picks (for
+contiguous scans) on a tuning sample,
 one persistent scan_batch launch replayed from a HIP graph, then the per-image
 counts, ids and confirmation. Every image's flags and records are compared
 with the CPU oracle run on that image (Section 3.1: flag by the signature sets
@@ -25,12 +26,13 @@ def test_batched_full_size_exact():
     cfg = synth.CONFIGS["mid"]
     _log("[batched] generating 256 images on the GPU")
     ms = synth.master_set(cfg, device="cuda")
-    idx = carve.build_master_index(ms.sectors, ms.file_offsets)
     images = synth.batch_images(cfg, ms, device="cuda")
     total = sum(t.numel() for t in images)
     assert len(images) == 256 and total > 40 << 30
-    shape = idx.autotune(synth.tuning_sample(cfg, ms, device="cuda"))
-    _log(f"[batched] {total / 2**30:.1f} GiB, launch shape {shape}")
+    idx, pick = carve.autotune_index(ms.sectors, ms.file_offsets,
+                                     synth.tuning_sample(cfg, ms, device="cuda", max_sectors=1 << 24),
+                                     contiguous_only=True)
+    _log(f"[batched] {total / 2**30:.1f} GiB, pick {pick}")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         b = carve.scan_batch(idx, images)

@@ -1,7 +1,7 @@
 """Parity at the full workload sizes, through the C ABI, in the launch
-configuration bench.py times: default index parameters, the launch shape the
-autotuner picks on a tuning sample (an image of the same recipe that is not
-the scanned one), one scan of the whole image. Every flag and every confirmed
+configuration bench.py times: the index layout, prefilter size and launch
+shape that autotune_index picks on a tuning sample (an image of the same
+recipe that is not the scanned one, up to 8 GiB), one scan of the whole image. Every flag and every confirmed
 record is compared with the CPU oracle over the whole image.
 
 mid: 8 GiB image, 1,048,576 master sectors, one oracle pass.
@@ -57,9 +57,9 @@ def _full_size(name: str):
     _log(f"[{name}] generating on the GPU")
     ms = synth.master_set(cfg, device="cuda")
     img = synth.disk_image(cfg, ms, device="cuda")
-    idx = carve.build_master_index(ms.sectors, ms.file_offsets)
-    shape = idx.autotune(synth.tuning_sample(cfg, ms, device="cuda"))
-    _log(f"[{name}] index {idx.stats()}, launch shape {shape}")
+    idx, pick = carve.autotune_index(ms.sectors, ms.file_offsets,
+                                     synth.tuning_sample(cfg, ms, device="cuda", max_sectors=1 << 24))
+    _log(f"[{name}] index {idx.stats()}, pick {pick}")
     sc = carve.scan_image(idx, img.data)
     flags = carve.flagged_sectors(sc).numpy().astype(np.uint64)
     matches = carve.confirm_matches(idx, sc)

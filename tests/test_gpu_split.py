@@ -64,3 +64,29 @@ def test_split_ragged_slices(mid, n_sectors, extra):
             want = ox.flag_image(host, tau0, any_tau, threads=th)
             assert np.array_equal(flags, want), (n_sectors, tau0, mode)
             assert_same_matches(carve.confirm_matches(idx, sc), ox.confirm_image(host, want, tau0, any_tau))
+
+
+@pytest.mark.parametrize("split", [carve.CARVE_SPLIT_OFF, carve.CARVE_SPLIT_ON])
+@pytest.mark.parametrize("n_masters", [3, 20, 40, 70, 150, 1000, 5000])
+def test_small_indexes_either_walk(n_masters, split):
+    """Indexes of a few master sectors and up: no filter (under 5 distinct
+    signatures), filters too small to split (fewer than 16 words), and the
+    smallest split filters (2 words per position and up). Either walk,
+    forced, agrees with the oracle at several tau0 and both rules."""
+    cfg = synth.scaled(synth.CONFIGS["tiny"], n_master_sectors=n_masters, n_disk_sectors=4096 + 13,
+                       n_files=max(1, n_masters // 8), equal_files=False, tail_bytes=100)
+    ms = synth.master_set(cfg, device="cuda")
+    img = synth.disk_image(cfg, ms, device="cuda").data
+    idx = carve.build_master_index(ms.sectors, ms.file_offsets)
+    idx.set_scan_config(0, 0, split)
+    th = oracle.default_threads()
+    ox = oracle.Index(ms.sectors.cpu().numpy(), ms.file_offsets, threads=th)
+    host = img.cpu().numpy()
+    for tau0 in (0, 3):
+        for mode in (carve.CARVE_TAU_PER_CLUSTER, carve.CARVE_TAU_ANY):
+            any_tau = mode == carve.CARVE_TAU_ANY
+            sc = carve.scan_image(idx, img, tau0=tau0, tau_mode=mode)
+            flags = carve.flagged_sectors(sc).numpy().astype(np.uint64)
+            want = ox.flag_image(host, tau0, any_tau, threads=th)
+            assert np.array_equal(flags, want), (n_masters, split, tau0, mode)
+            assert_same_matches(carve.confirm_matches(idx, sc), ox.confirm_image(host, want, tau0, any_tau))
