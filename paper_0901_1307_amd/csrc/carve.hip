@@ -441,21 +441,31 @@ __global__ void k_bloom_tau_build(const uint64_t* __restrict__ keys, const uint8
 }
 
 // The fragment scan's two filters (placed by frag_lds_place and
-// frag_bloom_place; 32-bit words).
+// frag_bloom_place from a signature's low half; 32-bit words), from the
+// table's keys; with_zero: signature 0 is a master's too (it has no slot), so
+// the bits of low half 0 are set as well.
 __global__ void k_lds_filter_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t n_words,
-                                   uint32_t* filter) {
+                                   uint32_t with_zero, uint32_t* filter) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_slots || keys[i] == kEmptyKey) return;
   uint32_t w, bits;
-  frag_lds_place(keys[i], n_words, &w, &bits);
+  if (i == 0 && with_zero) {
+    frag_lds_place(0u, n_words, &w, &bits);
+    atomicOr(&filter[w], bits);
+  }
+  if (i >= n_slots || keys[i] == kEmptyKey) return;
+  frag_lds_place((uint32_t)keys[i], n_words, &w, &bits);
   atomicOr(&filter[w], bits);
 }
 __global__ void k_frag_bloom_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t log2_words,
-                                   uint32_t* bloom) {
+                                   uint32_t with_zero, uint32_t* bloom) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_slots || keys[i] == kEmptyKey) return;
   uint32_t w, bits;
-  frag_bloom_place(keys[i], log2_words, &w, &bits);
+  if (i == 0 && with_zero) {
+    frag_bloom_place(0u, log2_words, &w, &bits);
+    atomicOr(&bloom[w], bits);
+  }
+  if (i >= n_slots || keys[i] == kEmptyKey) return;
+  frag_bloom_place((uint32_t)keys[i], log2_words, &w, &bits);
   atomicOr(&bloom[w], bits);
 }
 
@@ -1127,9 +1137,16 @@ int launch_scan(carve_scan* sc, const Src& src) {
   if (sc->timing) HIP_TRY(hipEventRecord(sc->ev[slot], s));
   if constexpr (std::is_same<Src, FragmentWindows>::value) {
     const uint64_t n_tasks = cdiv(src.d.n_sectors, kWaveWindows);
-    const int grid = resident_grid(k_frag_scan, kFragThreads, cdiv(n_tasks, kFragWaves), per_cu);
-    k_frag_scan<<<grid, kFragThreads, 0, s>>>((const uint32_t*)src.d.base, src.d.n_sectors, sc->n_dwords,
-                                              idx->view(), sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>());
+    const IndexView ix = idx->view();
+    if (ix.bloom) {
+      const int grid = resident_grid(k_frag_scan<true>, kFragThreads, cdiv(n_tasks, kFragWaves), per_cu);
+      k_frag_scan<true><<<grid, kFragThreads, 0, s>>>((const uint32_t*)src.d.base, src.d.n_sectors, sc->n_dwords,
+                                                      ix, sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>());
+    } else {
+      const int grid = resident_grid(k_frag_scan<false>, kFragThreads, cdiv(n_tasks, kFragWaves), per_cu);
+      k_frag_scan<false><<<grid, kFragThreads, 0, s>>>((const uint32_t*)src.d.base, src.d.n_sectors, sc->n_dwords,
+                                                       ix, sc->bitmap.as<uint64_t>(), sc->hit_slot.as<uint32_t>());
+    }
     HIP_TRY(hipGetLastError());
   } else if (split) {
     const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
@@ -1620,15 +1637,15 @@ int build_index(const void* master_sectors, const uint64_t* file_sector_offsets,
     } else if (p.bloom_bits_per_key != CARVE_BLOOM_OFF) {
       while ((64ull << lw) < (uint64_t)p.bloom_bits_per_key * keys_n) ++lw;
     }
-    if (unit == kFragBytes && lw > 31) lw = 31;   // fragment filters count 32-bit words: at most 2^32
+    if (unit == kFragBytes && lw > 29) lw = 29;   // fragment filters: at most 2^30 words of 32 bits
     if (lw > 0 && lw <= 32) {
       if ((rc = ix->bloom.reserve(8ull << lw))) return bail2(rc);
       ix->log2_bloom_words = lw;
       if (hipMemsetAsync(ix->bloom.p, 0, 8ull << lw, s) != hipSuccess)
         return bail2(fail(CARVE_EDEVICE, "build_master_index: bloom memset failed"));
-      if (unit == kFragBytes)   // the same bytes as 2^(lw+1) words of 32 bits, 4 bits per signature
+      if (unit == kFragBytes)   // the same bytes as 2^(lw+1) words of 32 bits, 3 bits per signature
         k_frag_bloom_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw + 1,
-                                                                   ix->bloom.as<uint32_t>());
+                                                                   zmask ? 1u : 0u, ix->bloom.as<uint32_t>());
       else
         k_bloom_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw,
                                                             ix->bloom.as<uint64_t>());
@@ -1672,7 +1689,7 @@ int build_index(const void* master_sectors, const uint64_t* file_sector_offsets,
     if (hipMemsetAsync(ix->lds_filter.p, 0, 4ull * lw, s) != hipSuccess)
       return bail2(fail(CARVE_EDEVICE, "build_fragment_index: filter memset failed"));
     k_lds_filter_build<<<cdiv(ix->n_slots, 256), 256, 0, s>>>(ix->keys.as<uint64_t>(), ix->n_slots, lw,
-                                                             ix->lds_filter.as<uint32_t>());
+                                                             zmask ? 1u : 0u, ix->lds_filter.as<uint32_t>());
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
       return bail2(fail(CARVE_EDEVICE, "build_fragment_index: filter build failed"));
   }

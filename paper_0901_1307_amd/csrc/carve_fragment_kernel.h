@@ -20,29 +20,39 @@ constexpr uint32_t kWaveWindows = kWave * kLaneWindows;      // 1024 windows = 4
 constexpr uint32_t kFragRowDw = kLaneWindows;                // a lane's own 64 bytes, in dwords
 constexpr uint32_t kLdsFilterMaxWords = 40960;               // 160 KiB, all of a CU's LDS: the first filter
 
-// The two filters of a fragment index, both of 32-bit words. Their positions
-// come from two 32 x 32 -> 64-bit products of the signature's halves,
-// a = hi * kFragMulA and b = lo * kFragMulB (one multiply-add instruction
-// each); a word index comes from the top bits of a product's low half
-// (multiplicative hashing), bit positions are 5-bit fields of its high half:
+// The two filters of a fragment index, both of 32-bit words, are placed from
+// the low 32 bits of the signature, s = sig mod 2^32: Eq. (1) reduced modulo
+// 2^32 is the same recurrence (reduction modulo 2^32 respects sums and
+// products), so the scan rolls s with 32-bit arithmetic alone and forms the
+// full 64-bit signature only for the rare windows that pass both filters.
+// Positions come from two 32 x 32 -> 64-bit products a = s * kFragMulA and
+// b = s * kFragMulB (one multiply-add instruction each); a word index comes
+// from the top bits of a product's low half (multiplicative hashing), bit
+// positions are 5-bit fields of its high half:
 // * first level, in LDS: word from a (the low half scaled to the word count,
 //   which need not be a power of two), 2 bits from a's high half;
-// * second level, the Bloom filter in L2: word from b, 4 bits from b's high half.
-// Only windows that pass the first level read the second.
+// * second level, the Bloom filter in L2: word from b, 3 bits from b's high half
+//   (a simulation of the logos set's filters on random low halves: both
+//   levels pass 0.086% of windows with 2 bits, 0.034% with 3, 0.021% with 4;
+//   3 bits keep the exact path rare for two instructions fewer than 4).
+// Only windows that pass the first level read the second. A signature whose
+// low half is 0 is placed like any other; when a master's whole signature is
+// 0 (it lives beside the table, not in it) the build sets the bits of low half
+// 0 in both filters, so no value needs special handling in the scan.
 constexpr uint32_t kFragMulA = 0x9E3779B1u;
 constexpr uint32_t kFragMulB = 0x85EBCA77u;
-__device__ __forceinline__ void frag_lds_place(uint64_t h, uint32_t n_words, uint32_t* word, uint32_t* bits) {
-  const uint64_t a = (uint64_t)(uint32_t)(h >> 32) * kFragMulA;
+__device__ __forceinline__ void frag_lds_place(uint32_t s, uint32_t n_words, uint32_t* word, uint32_t* bits) {
+  const uint64_t a = (uint64_t)s * kFragMulA;
   const uint32_t a_hi = (uint32_t)(a >> 32);
   *word = (uint32_t)(((uint64_t)(uint32_t)a * n_words) >> 32);   // < n_words
   *bits = (1u << (a_hi & 31u)) | (1u << ((a_hi >> 5) & 31u));
 }
-__device__ __forceinline__ void frag_bloom_place(uint64_t h, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
-  const uint64_t b = (uint64_t)(uint32_t)h * kFragMulB;
+// log2_words in 1..30 (the filter has 2 to 2^30 words).
+__device__ __forceinline__ void frag_bloom_place(uint32_t s, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
+  const uint64_t b = (uint64_t)s * kFragMulB;
   const uint32_t b_hi = (uint32_t)(b >> 32);
-  *word = log2_words ? (uint32_t)b >> (32 - log2_words) : 0u;   // log2_words in 0..32
-  *bits = (1u << (b_hi & 31u)) | (1u << ((b_hi >> 5) & 31u)) | (1u << ((b_hi >> 10) & 31u)) |
-          (1u << ((b_hi >> 15) & 31u));
+  *word = (uint32_t)b >> (32 - log2_words);
+  *bits = (1u << (b_hi & 31u)) | (1u << ((b_hi >> 5) & 31u)) | (1u << ((b_hi >> 10) & 31u));
 }
 
 // Rolling Eq. (1) over a 64-byte window by 4 bytes. With the window's data
@@ -59,6 +69,11 @@ constexpr uint64_t kPow64 = pow33(kFragBytes);
 constexpr uint64_t kFragInit = 5381ull * pow33(kFragBytes);
 constexpr uint64_t kRollAdd = kFragInit - kFragInit * kPow4;   // mod 2^64
 constexpr uint64_t kNegPow64 = 0ull - kPow64;                  // mod 2^64
+// the same constants modulo 2^32, for the low half of the signature
+constexpr uint32_t kPow4Lo = (uint32_t)kPow4;
+constexpr uint32_t kFragInitLo = (uint32_t)kFragInit;
+constexpr uint32_t kRollAddLo = (uint32_t)kRollAdd;
+constexpr uint32_t kNegPow64Lo = (uint32_t)kNegPow64;
 
 // The byte weights of D in dot4 form: D = dot(word, low bytes of 33^(3-i))
 // + 256 dot(word, second bytes of 33^(3-i)) (33^3 < 2^16).
@@ -94,12 +109,153 @@ struct FragmentWindows {
   __device__ __forceinline__ uint32_t image_of_tile(uint64_t) const { return 0; }
 };
 
+// A task's image words for lane l: its 16 own dwords (dwords 16l..16l+15 of
+// the task) and, in lanes 0-15, dword 1024 + (l mod 16) (the next task's first
+// words, which lane 63's windows reach). Every task but the image's last lies
+// wholly inside the image (n_dwords >= n_windows + 15) and uses 16-byte loads;
+// the last task clamps every dword to the image's last one (only windows past
+// the end read the repeated words).
+struct TaskWords {
+  u32x4 v[kFragRowDw / 4];
+  uint32_t x;
+};
+__device__ __forceinline__ void load_task_inside(const uint32_t* __restrict__ image, uint64_t t, uint32_t l,
+                                                 TaskWords& T) {
+  const uint64_t dw0 = t * kWaveWindows;
+  const uint32_t* src = image + dw0 + (uint64_t)l * kFragRowDw;
+#pragma unroll
+  for (uint32_t q = 0; q < kFragRowDw / 4; ++q) T.v[q] = __builtin_nontemporal_load((const u32x4*)(src + 4 * q));
+  T.x = __builtin_nontemporal_load(image + dw0 + kWaveWindows + (l % kFragRowDw));
+}
+__device__ __forceinline__ void load_task_clamped(const uint32_t* __restrict__ image, uint64_t n_dwords, uint64_t t,
+                                                  uint32_t l, TaskWords& T) {
+  const uint64_t dw0 = t * kWaveWindows;
+#pragma unroll
+  for (uint32_t k = 0; k < kFragRowDw; ++k) {
+    const uint64_t g = dw0 + (uint64_t)l * kFragRowDw + k;
+    T.v[k / 4][k % 4] = image[g < n_dwords ? g : n_dwords - 1];
+  }
+  const uint64_t g = dw0 + kWaveWindows + (l % kFragRowDw);
+  T.x = image[g < n_dwords ? g : n_dwords - 1];
+}
+
+// One task of a wave (see k_frag_scan). kBloom: the index has the second
+// filter (a compile-time choice: no branch around the filter's loads).
+template <bool kBloom>
+__device__ __forceinline__ void frag_task(uint64_t n_windows, uint64_t n_words, const IndexView& ix,
+                                          const uint32_t* lfilter, uint32_t lw, uint64_t t, uint32_t l,
+                                          const TaskWords& cur, uint64_t* __restrict__ out,
+                                          uint32_t* __restrict__ hit_slot) {
+  const char* bloom = (const char*)ix.bloom;   // fragment indexes: 32-bit words
+  const uint32_t lwb = ix.log2_bloom_words + 1;
+  // d[k] = D(dword 16l + k) of the task; dx = D of dword 1024 + (l % 16)
+  uint32_t d[kFragRowDw];
+#pragma unroll
+  for (uint32_t k = 0; k < kFragRowDw; ++k) d[k] = word_djb2(cur.v[k / 4][k % 4]);
+  const uint32_t dx = word_djb2(cur.x);
+  // nx[k] = D(dword 16l + 16 + k): the next lane's d[k]; for lane 63, lane
+  // k's dx (the whole wave runs this code, so every source lane is active)
+  uint32_t nx[kFragRowDw];
+#pragma unroll
+  for (uint32_t k = 0; k < kFragRowDw; ++k) {
+    const uint32_t next_lane = (uint32_t)__shfl_down((int)d[k], 1, kWave);
+    const uint32_t from_ext = (uint32_t)__builtin_amdgcn_readlane((int)dx, (int)k);
+    nx[k] = l == kWave - 1 ? from_ext : next_lane;
+  }
+  const uint64_t j0 = t * kWaveWindows + (uint64_t)l * kLaneWindows;
+  const uint32_t valid = j0 >= n_windows ? 0u : (n_windows - j0 >= kLaneWindows ? kLaneWindows
+                                                                                 : (uint32_t)(n_windows - j0));
+  // low halves of the signatures of the lane's 16 windows: Horner over the
+  // first window's words, then the rolling update modulo 2^32
+  uint32_t s = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kFragRowDw; ++k) s = s * kPow4Lo + d[k];
+  s += kFragInitLo;
+  uint32_t h[kLaneWindows];
+#pragma unroll
+  for (uint32_t w = 0; w < kLaneWindows; ++w) {
+    h[w] = s;
+    s = s * kPow4Lo + (kRollAddLo + kNegPow64Lo * d[w]) + nx[w];   // unused after the last window
+  }
+  // windows still candidates after both filters
+  uint32_t pend = valid >= 16 ? 0xFFFFu : (1u << valid) - 1u;
+  uint32_t fail = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kLaneWindows; ++w) {
+    uint32_t wi, bits;
+    frag_lds_place(h[w], lw, &wi, &bits);
+    fail |= (uint32_t)((~lfilter[wi] & bits) != 0u) << w;
+  }
+  pend &= ~fail;
+  // the Bloom words, all in flight together: a window that failed the LDS
+  // filter reads the filter's first word, the same address in every such
+  // lane, and its bits are dropped (no branches)
+  uint32_t fw[kLaneWindows];
+  if constexpr (kBloom) {
+#pragma unroll
+    for (uint32_t w = 0; w < kLaneWindows; ++w) {
+      uint32_t wi, bits;
+      frag_bloom_place(h[w], lwb, &wi, &bits);
+      const uint32_t off = ((pend >> w) & 1u) ? wi << 2 : 0u;   // wi < 2^30
+      fw[w] = *(const uint32_t*)(bloom + off);
+    }
+  }
+  if constexpr (kBloom) {
+    fail = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kLaneWindows; ++w) {
+      uint32_t wi, bits;
+      frag_bloom_place(h[w], lwb, &wi, &bits);
+      fail |= (uint32_t)((~fw[w] & bits) != 0u) << w;
+    }
+    pend &= ~fail;
+  }
+  // The candidates (rare: about one window in 3000 of random data, besides
+  // the true hits) take the exact test with the full 64-bit signature,
+  // rolled across the lane's 16 windows in the lanes that have one.
+  uint32_t mask = 0;
+  if (pend) {
+    uint64_t H = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kFragRowDw; ++k) H = H * kPow4 + d[k];
+    uint64_t sig = kFragInit + H;
+#pragma unroll
+    for (uint32_t w = 0; w < kLaneWindows; ++w) {
+      if ((pend >> w) == 0u) break;   // no candidate left in this lane
+      if ((pend >> w) & 1u) {
+        int64_t slot = -1;
+        if (sig == kEmptyKey) {
+          if (ix.zero_sig_mask) slot = ix.zero_slot;
+        } else {
+          slot = find_slot(ix, sig);   // any position: every occupied slot has masters
+        }
+        if (slot >= 0) {
+          mask |= 1u << w;
+          hit_slot[j0 + w] = (uint32_t)slot;
+        }
+      }
+      sig = sig * kPow4 + (kRollAdd + kNegPow64 * d[w]) + nx[w];
+    }
+  }
+  // four lanes' 16-bit masks make one 64-bit hit word
+  const uint32_t m1 = (uint32_t)__shfl_down((int)mask, 1, kWave);
+  const uint32_t m2 = (uint32_t)__shfl_down((int)mask, 2, kWave);
+  const uint32_t m3 = (uint32_t)__shfl_down((int)mask, 3, kWave);
+  const uint64_t wi = t * (kWaveWindows / kTileSectors) + l / 4;
+  if ((l & 3u) == 0 && wi < n_words)
+    out[wi] = (uint64_t)(mask | (m1 << 16)) | ((uint64_t)(m2 | (m3 << 16)) << 32);
+}
+
 // Persistent grid of one block per CU; wave q takes tasks q, q + W, ...
 // (W = waves in the grid). Task t: windows [1024t, 1024t + 1024); lane l
 // rolls over windows 16l..16l+15 of it, and lanes 4m..4m+3 make hit word
 // 16t + m (bit b = window 64(16t+m)+b). For each hit the matched table slot
 // goes to hit_slot[window]. The block's LDS holds only the first filter; the
-// image goes straight to registers.
+// image goes straight to registers. Requesting the next task's words ahead,
+// behind the current task's Bloom words, was measured slower (1.34 vs
+// 1.23 ms on the 2 GiB logos workload, and 0.47 GB more fetched): the extra
+// image data in flight displaced Bloom words from L2.
+template <bool kBloom>
 __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_frag_scan(
     const uint32_t* __restrict__ image, uint64_t n_windows, uint64_t n_dwords, IndexView ix,
     uint64_t* __restrict__ out, uint32_t* __restrict__ hit_slot) {
@@ -107,115 +263,17 @@ __global__ __launch_bounds__(kFragThreads) __attribute__((amdgpu_waves_per_eu(4)
   const uint32_t lw = ix.lds_words;   // at most kLdsFilterMaxWords
   for (uint32_t i = threadIdx.x; i < lw; i += kFragThreads) lfilter[i] = ix.lds_filter[i];
   __syncthreads();   // before any wave of the block can leave
-  const uint32_t wv = threadIdx.x / kWave;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const uint32_t l = lane_id();
   const uint64_t n_tasks = (n_windows + kWaveWindows - 1) / kWaveWindows;
   const uint64_t n_words = (n_windows + kTileSectors - 1) / kTileSectors;
   const uint64_t n_waves = (uint64_t)gridDim.x * kFragWaves;
+  const uint64_t last = n_tasks - 1;   // n_windows >= 1 (the host launches nothing otherwise)
   for (uint64_t t = (uint64_t)blockIdx.x * kFragWaves + wv; t < n_tasks; t += n_waves) {
-    // Lane l's windows read dwords [16l, 16l + 32) of the task (dword dw0 =
-    // window 1024t): its own 16 and the next lane's. Lane 63's second 16 are
-    // the next task's first words, which lanes 0-15 load. Only the words' D
-    // values are kept. Inside the image these are 16-byte loads; the last
-    // task clamps every dword to the image's last one (only windows past the
-    // end read the repeated words).
-    const uint64_t dw0 = t * kWaveWindows;
-    // d[k] = D(dword 16l + k), dx = D of dword 1024 + (l % 16) of the task
-    uint32_t d[kFragRowDw], dx;
-    if (dw0 + kWaveWindows + kFragRowDw <= n_dwords) {
-      const uint32_t* src = image + dw0 + (uint64_t)l * kFragRowDw;
-#pragma unroll
-      for (uint32_t q = 0; q < kFragRowDw / 4; ++q) {
-        const u32x4 v = __builtin_nontemporal_load((const u32x4*)(src + 4 * q));
-        d[4 * q] = word_djb2(v.x), d[4 * q + 1] = word_djb2(v.y);
-        d[4 * q + 2] = word_djb2(v.z), d[4 * q + 3] = word_djb2(v.w);
-      }
-      dx = word_djb2(__builtin_nontemporal_load(image + dw0 + kWaveWindows + (l % kFragRowDw)));
-    } else {
-#pragma unroll
-      for (uint32_t k = 0; k < kFragRowDw; ++k) {
-        const uint64_t g = dw0 + (uint64_t)l * kFragRowDw + k;
-        d[k] = word_djb2(image[g < n_dwords ? g : n_dwords - 1]);
-      }
-      const uint64_t g = dw0 + kWaveWindows + (l % kFragRowDw);
-      dx = word_djb2(image[g < n_dwords ? g : n_dwords - 1]);
-    }
-    // D of word 16 + k of lane l's stream: the next lane's d[k]; for lane 63,
-    // lane k's dx (the whole wave runs this code, so every source lane is active)
-    auto d_second = [&](uint32_t k) {
-      const uint32_t next_lane = (uint32_t)__shfl_down((int)d[k], 1, kWave);
-      const uint32_t from_ext = (uint32_t)__builtin_amdgcn_readlane((int)dx, (int)k);
-      return l == kWave - 1 ? from_ext : next_lane;
-    };
-    const uint64_t j0 = dw0 + (uint64_t)l * kLaneWindows;
-    const uint32_t valid = j0 >= n_windows ? 0u : (n_windows - j0 >= kLaneWindows ? kLaneWindows
-                                                                                   : (uint32_t)(n_windows - j0));
-    uint64_t H = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < kFragRowDw; ++k) H = H * kPow4 + d[k];
-    uint64_t sig = kFragInit + H;   // window 16l of the task
-    const uint32_t* bloom = (const uint32_t*)ix.bloom;   // fragment indexes: 32-bit words
-    const uint32_t lwb = ix.log2_bloom_words + 1;
-    uint32_t mask = 0;
-    // batches of 8 windows: 8 signatures; the LDS filter; Bloom words only for
-    // the windows that pass it, in flight together; then the (rare) windows
-    // that pass both go through the table probe
-#pragma unroll
-    for (uint32_t b = 0; b < kLaneWindows; b += 8) {
-      uint64_t h[8];
-#pragma unroll
-      for (uint32_t i = 0; i < 8; ++i) {
-        const uint32_t w = b + i;
-        h[i] = sig;
-        // roll to window w + 1 (after the last window the result is unused)
-        sig = sig * kPow4 + (kRollAdd + kNegPow64 * d[w]) + d_second(w);
-      }
-      uint32_t pend = valid <= b ? 0u : (valid - b >= 8 ? 0xFFu : (1u << (valid - b)) - 1u);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {   // no branches: every window reads its LDS word
-        uint32_t wi, bits;
-        frag_lds_place(h[i], lw, &wi, &bits);
-        const bool out = (lfilter[wi] & bits) != bits && h[i] != kEmptyKey;
-        pend &= ~((uint32_t)out << i);
-      }
-      if (bloom) {
-        uint32_t bits[8], fw[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          uint32_t wi;
-          frag_bloom_place(h[i], lwb, &wi, &bits[i]);
-          fw[i] = ((pend >> i) & 1u) ? bloom[wi] : ~0u;
-        }
-        uint32_t pass = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) pass |= (uint32_t)(h[i] == kEmptyKey || (fw[i] & bits[i]) == bits[i]) << i;
-        pend &= pass;
-      }
-      while (pend) {
-        const int i = __builtin_ctz(pend);
-        pend &= pend - 1u;
-        uint64_t hv = h[0];
-#pragma unroll
-        for (int k = 1; k < 8; ++k) hv = i == k ? h[k] : hv;
-        int64_t slot = -1;
-        if (hv == kEmptyKey) {
-          if (ix.zero_sig_mask) slot = ix.zero_slot;
-        } else {
-          slot = find_slot(ix, hv);   // any position: every occupied slot has masters
-        }
-        if (slot >= 0) {
-          mask |= 1u << (b + i);
-          hit_slot[j0 + b + i] = (uint32_t)slot;
-        }
-      }
-    }
-    // four lanes' 16-bit masks make one 64-bit hit word
-    const uint32_t m1 = (uint32_t)__shfl_down((int)mask, 1, kWave);
-    const uint32_t m2 = (uint32_t)__shfl_down((int)mask, 2, kWave);
-    const uint32_t m3 = (uint32_t)__shfl_down((int)mask, 3, kWave);
-    const uint64_t wi = t * (kWaveWindows / kTileSectors) + l / 4;
-    if ((l & 3u) == 0 && wi < n_words)
-      out[wi] = (uint64_t)(mask | (m1 << 16)) | ((uint64_t)(m2 | (m3 << 16)) << 32);
+    TaskWords cur;
+    if (t < last) load_task_inside(image, t, l, cur);   // uniform branch
+    else load_task_clamped(image, n_dwords, t, l, cur);
+    frag_task<kBloom>(n_windows, n_words, ix, lfilter, lw, t, l, cur, out, hit_slot);
   }
 }
 

@@ -214,3 +214,48 @@ def test_fragment_workload_full():
     assert len(wf) > 3_000_000
     assert np.array_equal(f, wf)
     assert_same_matches(m, wm)
+
+
+@pytest.mark.parametrize("bloom", [0, carve.CARVE_BLOOM_OFF])
+@pytest.mark.parametrize("zero_master", [True, False])
+def test_fragment_signature_low_halves(bloom, zero_master):
+    """The scan filters windows on the low 32 bits of their signature and takes
+    the exact 64-bit test only for those that pass: master fragments whose
+    signature is 0 (it lives beside the table) or whose low half is 0, 1 or
+    2^32 - 1 with other high halves; windows equal to them, windows crafted
+    to their signatures with other bytes (flagged, not confirmed), and windows
+    that share only a low half (not flagged); against the oracle."""
+    from oracle import spec
+    rng = random.Random(77 + zero_master)
+    targets = [(1 << 32) * 5, (1 << 32) * 12345 + 1, (1 << 64) - 1, ((1 << 31) + 7) << 32 | 0xFFFFFFFF]
+    if zero_master:
+        targets.append(0)
+    crafted = [spec.craft_sector(bytes([65 + i]) * 8, t, n=64) for i, t in enumerate(targets)]
+    assert [spec.djb2_closed(c) for c in crafted] == targets
+    files = _files(rng, 5, 128, 1024)
+    files.append(b"".join(crafted) + bytes(rng.getrandbits(8) for _ in range(64)))
+    frag_data, offsets = oracle.pack_fragment_files(files)
+    # same low half, another high half: never flagged
+    others = [spec.craft_sector(b"other" + bytes([i]), (t ^ (0xDEAD << 40)) & ((1 << 64) - 1), n=64)
+              for i, t in enumerate(targets)]
+    collisions = [spec.craft_sector(b"collide" + bytes([i]), t, n=64) for i, t in enumerate(targets)]
+    img = bytearray(rng.getrandbits(8) for _ in range(64 * 1024))
+    pieces = crafted + others + collisions
+    for k, p in enumerate(pieces):
+        o = 4096 + 1024 * k + 4 * (k % 7)
+        img[o:o + 64] = p
+    image = bytes(img)
+    idx = carve.build_fragment_index(dev_bytes(frag_data.tobytes()), offsets, bloom_bits_per_key=bloom)
+    f, m, _ = _gpu(idx, dev_bytes(image))
+    wf, wm = _oracle(frag_data, offsets, image)
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
+    flagged = set(f.tolist())
+    for k in range(len(pieces)):
+        j = (4096 + 1024 * k + 4 * (k % 7)) // 4
+        if k < len(crafted):
+            assert j in flagged and j in set(m["disk_sector"].tolist())
+        elif k < 2 * len(crafted):
+            assert j not in flagged
+        else:
+            assert j in flagged and j not in set(m["disk_sector"].tolist())
