@@ -1,11 +1,13 @@
 #!/usr/bin/env python3
 """Disk-scan throughput of the carving path on one MI355X.
 
-A step is one pass of the whole hot path over a device-resident disk image:
-scan_image (sector loads, djb2-64 signatures, cluster positions, index probe,
-ordered compaction of the flagged ids), flagged_sectors (ids into a device
-buffer) and confirm_matches (byte comparison of every flagged sector with its
-candidate master sectors, ordered records into a device buffer). The master
+A step is one pass of the whole hot path over a device-resident disk image,
+enqueued whole and then waited for once: scan_image (sector loads, djb2-64
+signatures, cluster positions, index probe, ordered compaction of the flagged
+ids), confirm_enqueue_to (byte comparison of every flagged sector with its
+candidate master sectors, ordered records into a device buffer),
+flagged_sectors_enqueue (ids into a device buffer) and scan_counts (the one
+readback: both counts). The master
 index is built once, before timing, and the launch shape is picked by the
 library's autotuner on a tuning sample (an image of the same recipe that is
 not the timed one).
@@ -226,11 +228,11 @@ def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
     match_out = torch.empty(16 * max(1, 2 * n_match + 1024), dtype=torch.uint8, device="cuda")
     log(f"[bench] {n_flag} flagged, {n_match} confirmed")
 
-    def step():
+    def step():   # the whole path enqueued, then one wait for both counts
         carve.scan_image(idx, img.data, scan=sc)
-        nf = carve.flagged_sectors(sc, flag_out).numel()
-        nm = carve.confirm_matches(idx, sc, match_out)
-        return nf, nm
+        carve.confirm_enqueue(idx, sc, match_out)
+        carve.flagged_sectors_enqueue(sc, flag_out)
+        return carve.scan_counts(sc)
 
     for _ in range(args.warmup):
         step()
@@ -370,8 +372,9 @@ def run_batched(args) -> dict:
                                                                   dtype=torch.uint8, device="cuda"))
         match_out = torch.empty(24 * (2 * n_match + 1024), dtype=torch.uint8, device="cuda")
         graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=stream):
+        with torch.cuda.graph(graph, stream=stream):   # scan, compaction and confirmation
             carve.scan_batch(idx, images, batch=b)
+            carve.confirm_enqueue(idx, b)
     n_flag = int(counts.sum())
     log(f"[bench] {n_flag} flagged, {n_match} confirmed")
 
@@ -717,11 +720,11 @@ def run_fragments(args):
     match_out = torch.empty(16 * (n_match + 1024), dtype=torch.uint8, device="cuda")
     log(f"[bench] {n_flag} windows flagged, {n_match} confirmed")
 
-    def step():
+    def step():   # the whole path enqueued, then one wait for both counts
         carve.scan_fragments(idx, img, scan=sc)
-        nf = carve.flagged_sectors(sc, flag_out).numel()
-        nm = carve.confirm_matches(idx, sc, match_out)
-        return nf, nm
+        carve.confirm_enqueue(idx, sc, match_out)
+        carve.flagged_sectors_enqueue(sc, flag_out)
+        return carve.scan_counts(sc)
 
     for _ in range(args.warmup):
         step()

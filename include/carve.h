@@ -209,6 +209,43 @@ int confirm_matches(const carve_index* idx, carve_scan* sc, carve_match* out, ui
 int confirm_enqueue(const carve_index* idx, carve_scan* sc);
 
 /*
+ * confirm_enqueue_to -- confirm_enqueue with the records written straight into
+ * the caller's device memory (Section 3.1 confirmation; the host reads the
+ * results once, Section 3.2): no copy afterwards. Asynchronous on the scan's
+ * stream, nothing is read back, so a whole step (scan_image,
+ * confirm_enqueue_to, flagged_sectors_enqueue, then scan_counts) waits once.
+ *   out    device, room for cap records (may be NULL when cap == 0); receives
+ *          the first min(matches, cap) records in confirm_matches' order.
+ *          BORROWED until the stream has run the confirmation.
+ * A later confirm_matches with the same out and cap reads the count only.
+ * Errors: EINVAL (null idx/sc, a batch object, another index, null out with
+ * cap > 0, out not device memory), ENOMEM, EDEVICE.
+ */
+int confirm_enqueue_to(const carve_index* idx, carve_scan* sc, carve_match* out, uint64_t cap);
+
+/*
+ * flagged_sectors_enqueue -- flagged_sectors into the caller's device memory
+ * without waiting: enqueues the copy of the first min(count, cap) ids on the
+ * scan's stream (Section 3.2's match buffer). The count comes from
+ * scan_counts (or flagged_sectors) afterwards.
+ *   out    device, room for cap ids (may be NULL when cap == 0).
+ * Errors: EINVAL (null sc, a batch object, null out with cap > 0, out not
+ * device memory), EDEVICE.
+ */
+int flagged_sectors_enqueue(carve_scan* sc, uint64_t* out, uint64_t cap);
+
+/*
+ * scan_counts -- synchronizes the scan's stream and reads its counts in one
+ * readback: the flagged units of the latest scan (a batch: of all its images)
+ * and the records of a confirmation that ran after it, or
+ * CARVE_NOT_CONFIRMED when none did.
+ * Errors: EINVAL (null argument), EDEVICE (also when a single-pass kernel of
+ * the scan could not complete its counts).
+ */
+int scan_counts(carve_scan* sc, uint64_t* n_flagged, uint64_t* n_confirmed);
+#define CARVE_NOT_CONFIRMED UINT64_MAX
+
+/*
  * sector_signatures -- djb2-64 signature (Eq. (1), Section 4) of each of
  * n_sectors packed sectors. sectors: device, 16-B aligned; sigs: device,
  * n_sectors values. Asynchronous on `stream`.
@@ -307,7 +344,9 @@ void ingest_free(carve_ingest* in);   /* NULL is a no-op; waits for transfers an
  *   ids    device, room for cap ids (may be NULL when cap == 0): receives the
  *          first min(count, cap) flagged sector ids, ascending.
  *   count  device, one uint64_t: receives the number of flagged sectors (the
- *          full count, also when it exceeds cap).
+ *          full count, also when it exceeds cap), or UINT64_MAX when the
+ *          compaction could not complete it (a device error: the ids are
+ *          not valid).
  * Asynchronous on `stream`: nothing is read back. Every call on one GPU uses
  * that GPU's one array, so calls that overlap on a GPU (on any streams) race:
  * the caller orders them (e.g. one stream).

@@ -39,7 +39,8 @@ EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_match
            "server_release", "server_release_many", "server_stats", "server_free", "free_index", "free_scan",
            "free_batch", "carve_last_error", "build_fragment_index", "scan_fragments", "ingest_create",
            "ingest_scan", "ingest_flagged_sectors", "ingest_matches", "ingest_stats", "ingest_free",
-           "scan_image_noalloc", "read_ceiling_probe", "autotune_index")
+           "scan_image_noalloc", "read_ceiling_probe", "autotune_index", "confirm_enqueue_to",
+           "flagged_sectors_enqueue", "scan_counts")
 
 
 class CarveError(RuntimeError):
@@ -50,6 +51,7 @@ class CarveError(RuntimeError):
 
 CARVE_BLOOM_OFF = 0xFFFFFFFF
 CARVE_ALL_IMAGES = 0xFFFFFFFF
+CARVE_NOT_CONFIRMED = 0xFFFFFFFFFFFFFFFF   # scan_counts: no confirmation ran after the latest scan
 
 
 class _IndexParams(ctypes.Structure):
@@ -203,6 +205,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.confirm_enqueue.argtypes = [P, P]
     lib.batch_confirm_enqueue.restype = I32
     lib.batch_confirm_enqueue.argtypes = [P, P]
+    lib.confirm_enqueue_to.restype = I32
+    lib.confirm_enqueue_to.argtypes = [P, P, P, U64]
+    lib.flagged_sectors_enqueue.restype = I32
+    lib.flagged_sectors_enqueue.argtypes = [P, P, U64]
+    lib.scan_counts.restype = I32
+    lib.scan_counts.argtypes = [P, PU64, PU64]
     lib.free_batch.restype = None
     lib.free_batch.argtypes = [P]
     lib.scan_set_timing.restype = I32
@@ -300,6 +308,7 @@ class Scan:
     def __init__(self):
         self.handle = None
         self.image = None
+        self.pending = []   # device outputs of enqueued work, kept alive until a synchronization
 
     def set_timing(self, enable: bool = True):
         _check(load_library().scan_set_timing(self.handle, int(enable)))
@@ -821,10 +830,39 @@ class Ingest:
             pass
 
 
-def confirm_enqueue(index: Index, scan) -> None:
-    """Enqueue the confirmation of the last scan (or batch) without waiting."""
+def confirm_enqueue(index: Index, scan, out: Optional[torch.Tensor] = None) -> None:
+    """Enqueue the confirmation of the last scan (or batch) without waiting.
+    With `out` (a contiguous device uint8 tensor of 16*cap bytes; not for
+    batches) the records go straight there (confirm_enqueue_to)."""
     lib = load_library()
     if isinstance(scan, Batch):
+        if out is not None:
+            raise TypeError("a batch confirms into its own buffer")
         _check(lib.batch_confirm_enqueue(index.handle, scan.handle))
-    else:
+    elif out is None:
         _check(lib.confirm_enqueue(index.handle, scan.handle))
+    else:
+        if out.dtype != torch.uint8 or not out.is_contiguous() or out.numel() % 16:
+            raise TypeError("out must be a contiguous uint8 tensor of 16-byte records")
+        cap = out.numel() // 16
+        _check(lib.confirm_enqueue_to(index.handle, scan.handle, out.data_ptr() if cap else None, cap))
+        scan.pending = [t for t in scan.pending if t is not out] + [out]   # alive until the stream has run
+
+
+def flagged_sectors_enqueue(scan: Scan, out: torch.Tensor) -> None:
+    """Enqueue the copy of the first min(count, out.numel()) flagged ids into
+    `out` (a contiguous device int64 tensor) without waiting."""
+    if out.dtype != torch.int64 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous int64 tensor")
+    _check(load_library().flagged_sectors_enqueue(scan.handle, out.data_ptr() if out.numel() else None,
+                                                  out.numel()))
+    scan.pending = [t for t in scan.pending if t is not out] + [out]
+
+
+def scan_counts(scan) -> tuple:
+    """(flagged units, confirmed records or None when no confirmation ran after
+    the latest scan), read in one synchronization of the scan's stream."""
+    nf, nm = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load_library().scan_counts(scan.handle, ctypes.byref(nf), ctypes.byref(nm)))
+    scan.pending = []
+    return int(nf.value), (None if nm.value == CARVE_NOT_CONFIRMED else int(nm.value))

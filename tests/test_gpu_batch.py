@@ -175,6 +175,49 @@ def test_graph_of_scan_image_confirms_each_replay(setup):
         assert len(m) >= 16
 
 
+def test_graph_of_one_wait_step(setup):
+    """scan_image, the confirmation into a device buffer and the ids copy
+    captured in one graph: every replay over new bytes gives the oracle's ids
+    and records (read with one scan_counts). The single-pass kernels leave
+    their state clean on every replay; eager scans of other sizes run between
+    the replays."""
+    ms, idx, images = setup
+    t, tau0, mode = images[7]
+    img = t.clone()
+    any_tau = mode == carve.CARVE_TAU_ANY
+    n_units = img.numel() // SECTOR
+    ids = torch.empty(n_units, dtype=torch.int64, device="cuda")
+    rec = torch.empty(16 * (4 * n_units + 1024), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sc = carve.scan_image(idx, img, tau0=tau0, tau_mode=mode)
+        carve.confirm_enqueue(idx, sc, rec)
+        carve.flagged_sectors_enqueue(sc, ids)
+        carve.scan_counts(sc)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            carve.scan_image(idx, img, tau0=tau0, tau_mode=mode, scan=sc)
+            carve.confirm_enqueue(idx, sc, rec)
+            carve.flagged_sectors_enqueue(sc, ids)
+    ox = oracle.Index(ms.sectors.cpu().numpy(), ms.file_offsets)
+    for rep in range(4):
+        _plant(ms, img, rep, tau0)
+        other, o_tau0, o_mode = images[(5, 8, 6, 4)[rep]]
+        gpu_flags_and_matches(idx, other, o_tau0, o_mode == carve.CARVE_TAU_ANY)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        nf, nm = carve.scan_counts(sc)
+        host = img.cpu().numpy()
+        wf = ox.flag_image(host, tau0, any_tau)
+        wm = ox.confirm_image(host, wf, tau0, any_tau)
+        assert (nf, nm) == (len(wf), len(wm)) and nm >= 16
+        assert np.array_equal(ids[:nf].cpu().numpy().astype(np.uint64), wf)
+        got = np.frombuffer(rec[: 16 * nm].cpu().numpy().tobytes(), dtype=carve.MATCH_DTYPE)
+        assert_same_matches(got, wm)
+
+
 def test_batch_rejects_bad_descriptor(setup):
     ms, idx, images = setup
     bad = list(images)

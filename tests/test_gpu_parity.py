@@ -415,6 +415,47 @@ def test_confirm_into_device_memory(tiny_gpu):
     assert_same_matches(first, m[:7])
 
 
+def test_one_wait_step(tiny_gpu):
+    """The step that waits once: scan_image, the confirmation enqueued into a
+    device buffer, the ids copy enqueued, then scan_counts. Ids and records
+    equal the oracle's on every repetition; confirm_matches with the same
+    buffer only reads the count; a short id buffer gets the first ids; a host
+    copy-out afterwards produces the records again; host buffers are refused."""
+    cfg, ms, img, idx = tiny_gpu
+    wf, wm = oracle_flags_and_matches(ms.sectors.cpu().numpy(), ms.file_offsets, img.data.cpu().numpy())
+    assert len(wf) > 5000 and len(wm) > 5000
+    ids = torch.full((len(wf) + 9,), -1, dtype=torch.int64, device="cuda")
+    rec = torch.zeros(16 * (len(wm) + 3), dtype=torch.uint8, device="cuda")
+    sc = None
+    for rep in range(3):
+        sc = carve.scan_image(idx, img.data, scan=sc)
+        if rep == 0:
+            assert carve.scan_counts(sc) == (len(wf), None)
+        carve.confirm_enqueue(idx, sc, rec)
+        carve.flagged_sectors_enqueue(sc, ids)
+        assert carve.scan_counts(sc) == (len(wf), len(wm))
+        assert np.array_equal(ids[: len(wf)].cpu().numpy().astype(np.uint64), wf)
+        assert bool((ids[len(wf):] == -1).all())
+        got = np.frombuffer(rec.cpu().numpy().tobytes(), dtype=carve.MATCH_DTYPE)[: len(wm)]
+        assert_same_matches(got, wm)
+        assert carve.confirm_matches(idx, sc, rec) == len(wm)
+    short = torch.zeros(5, dtype=torch.int64, device="cuda")
+    carve.flagged_sectors_enqueue(sc, short)
+    assert carve.scan_counts(sc)[0] == len(wf)
+    assert np.array_equal(short.cpu().numpy().astype(np.uint64), wf[:5])
+    assert_same_matches(carve.confirm_matches(idx, sc), wm)
+    with pytest.raises(carve.CarveError) as e:
+        carve.flagged_sectors_enqueue(sc, torch.zeros(4, dtype=torch.int64))
+    assert e.value.code == carve.CARVE_EINVAL
+    with pytest.raises(carve.CarveError) as e:
+        carve.confirm_enqueue(idx, sc, torch.zeros(64, dtype=torch.uint8))
+    assert e.value.code == carve.CARVE_EINVAL
+    empty = carve.scan_image(idx, img.data[:100])
+    assert carve.scan_counts(empty) == (0, None)
+    carve.confirm_enqueue(idx, empty, rec)
+    assert carve.scan_counts(empty) == (0, 0)
+
+
 def test_host_memory_image_rejected(tiny_gpu):
     """scan_image takes device memory: a pinned or pageable host image is refused
     on the host (EINVAL), before any kernel runs."""
