@@ -239,8 +239,7 @@ int flagged_sectors_enqueue(carve_scan* sc, uint64_t* out, uint64_t cap);
  * readback: the flagged units of the latest scan (a batch: of all its images)
  * and the records of a confirmation that ran after it, or
  * CARVE_NOT_CONFIRMED when none did.
- * Errors: EINVAL (null argument), EDEVICE (also when a single-pass kernel of
- * the scan could not complete its counts).
+ * Errors: EINVAL (null argument), EDEVICE.
  */
 int scan_counts(carve_scan* sc, uint64_t* n_flagged, uint64_t* n_confirmed);
 #define CARVE_NOT_CONFIRMED UINT64_MAX
@@ -344,9 +343,7 @@ void ingest_free(carve_ingest* in);   /* NULL is a no-op; waits for transfers an
  *   ids    device, room for cap ids (may be NULL when cap == 0): receives the
  *          first min(count, cap) flagged sector ids, ascending.
  *   count  device, one uint64_t: receives the number of flagged sectors (the
- *          full count, also when it exceeds cap), or UINT64_MAX when the
- *          compaction could not complete it (a device error: the ids are
- *          not valid).
+ *          full count, also when it exceeds cap).
  * Asynchronous on `stream`: nothing is read back. Every call on one GPU uses
  * that GPU's one array, so calls that overlap on a GPU (on any streams) race:
  * the caller orders them (e.g. one stream).

@@ -47,15 +47,14 @@ using namespace carve;
 
 // Work buffers of scan_image_noalloc, for callers that cannot allocate: hit
 // words (and the position-split scan's per-position words) of images up to
-// 2^27 sectors, and the compaction's look-back state. Every GPU that runs the
+// 2^27 sectors, and the compaction's chunk sums. Every GPU that runs the
 // library holds its own copy until the process ends. In host code this name
 // is a host-side stand-in, never a device address: kernels get the address
 // that noalloc_scratch() looks up per device.
 constexpr uint64_t kNoAllocMaxSectors = 1ull << 27;                        // 64 GiB of image
 constexpr uint64_t kNoAllocMaxWords = kNoAllocMaxSectors / kTileSectors;    // 2^21 hit words
-constexpr uint64_t kNoAllocMaxChunks = kNoAllocMaxWords / 1024;             // compaction chunks of 1024 words
-constexpr uint64_t kNoAllocLbWords = 3 + kNoAllocMaxChunks;                 // look-back header + a status per chunk
-constexpr uint64_t kScratchWords = 2 * kNoAllocMaxWords + kNoAllocLbWords;  // 32 MiB + 16 KiB + 24 B
+constexpr uint64_t kNoAllocMaxChunks = kNoAllocMaxWords / 2048;             // compaction chunks of 2048 words
+constexpr uint64_t kScratchWords = 2 * kNoAllocMaxWords + 2 * kNoAllocMaxChunks;   // 32 MiB + 16 KiB
 static __device__ __align__(256) uint64_t scratch[kScratchWords];
 
 namespace {
@@ -63,6 +62,7 @@ namespace {
 constexpr int kBlockThreads = 256;
 constexpr int kItemsPerThread = 8;
 constexpr int kItemsPerBlock = kBlockThreads * kItemsPerThread;   // 2048
+static_assert(kNoAllocMaxChunks * kItemsPerBlock == kNoAllocMaxWords, "scratch holds every chunk sum");
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be placed
 
@@ -79,15 +79,12 @@ constexpr uint64_t kTimedRing = 256;
 // -------------------------------------------------------- prefix sums
 // An item count known on the host (dev == null) or read on the device, so work
 // sized by a count the host has not seen can be enqueued without waiting.
-// A count a single-pass kernel could not complete (kCarveCountError) counts
-// no items.
 struct Count {
   uint64_t v;            // the count, or with dev: the most the buffers have room for
   const uint64_t* dev;
   __device__ __forceinline__ uint64_t get() const {
     if (!dev) return v;
     const uint64_t n = *dev;
-    if (n == kCarveCountError) return 0;
     return n < v ? n : v;
   }
 };
@@ -96,19 +93,19 @@ struct U32Items {
   const uint32_t* v;
   __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return v[i]; }
 };
-// The hit words a compaction reads: the scan's bitmap as it is, or after a
-// position-split scan hit word w of the image (sectors 64w..64w+63) gathered
-// from the per-position words. Sector 64w + 8m + r sits at position
-// (r + tau0) mod 8, in that position's tile w/8, bit 8(w mod 8) + m: byte
-// w mod 8 of the 8 positions' words, an 8 x 8 bit matrix, transposed (the
-// last word cut at the image's end).
-struct BitmapWords {
+struct PopcountItems {
   const uint64_t* words;
-  __device__ __forceinline__ uint64_t operator()(uint64_t w) const { return words[w]; }
+  __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return (uint64_t)__popcll(words[i]); }
 };
-struct TauMergeWords {
+// After a position-split scan: hit word w of the image (sectors 64w..64w+63)
+// gathered from the per-position words. Sector 64w + 8m + r sits at position
+// (r + tau0) mod 8, in that position's tile w/8, bit 8(w mod 8) + m: byte
+// w mod 8 of the 8 positions' words, an 8 x 8 bit matrix, transposed. Writes
+// the word to the bitmap (the last one cut at the image's end) and counts it.
+struct TauMergeItems {
   const uint64_t* tau_words;
   uint64_t words_per_pos;
+  uint64_t* bitmap;
   uint64_t n_words;
   uint32_t tau0;
   uint32_t last_bits;   // valid bits of the last word, 0 = all 64
@@ -128,7 +125,8 @@ struct TauMergeWords {
     t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
     x ^= t ^ (t << 28);
     if (w == n_words - 1 && last_bits) x &= (1ull << last_bits) - 1ull;
-    return x;
+    bitmap[w] = x;
+    return (uint64_t)__popcll(x);
   }
 };
 
@@ -290,259 +288,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_apply(Emit e, Count count, co
   }
 }
 
-// -------------------------------------------- single-pass prefix sums
-// A compaction or a confirmation in one launch (decoupled look-back): a
-// block claims the next chunk through one counter, adds up the chunk, and
-// publishes that sum; it then learns the sum of every chunk before it from
-// their published words, a window of chunks per round trip from the
-// nearest back (a block's worth of loads: with a couple of thousand chunks in
-// flight, the nearest inclusive prefix is often hundreds of chunks back),
-// until one of them carries its inclusive prefix, and publishes its own. A
-// chunk is only waited for once claimed, i.e. by a block that is running, so
-// every wait ends. Each launch has an epoch, and a status counts only when written
-// in the current one; the block that makes the grid's last claim (every
-// other block has then left its loop) clears the statuses it used, moves the
-// epoch on and resets the counter for the next launch.
-// Layout: [0] claims, [1] a wait ran past its bound or a value its width,
-// [2] the epoch, [3 + c] chunk c's status: bits 63-62 the state, 61-40 the
-// epoch that wrote it, 39-0 the value.
-constexpr uint32_t kLbHeader = 3;
-constexpr uint64_t kLbAggregate = 1ull << 62;   // state: the chunk's own sum
-constexpr uint64_t kLbInclusive = 2ull << 62;   // state: the sum of the chunks up to and including it
-constexpr uint32_t kLbValueBits = 40;
-constexpr uint64_t kLbValue = (1ull << kLbValueBits) - 1;
-constexpr uint64_t kLbEpochMask = (1ull << 22) - 1;
-constexpr uint32_t kLbSpinLimit = 1u << 20;     // polls of one window (about a second) before a wait fails
-// A count written when a wait ran past its bound: the host reports a device error.
-constexpr uint64_t kCountError = kCarveCountError;
-
-// Status words are read and written at device scope, so that blocks on other
-// XCDs (each with its own L2) see them.
-__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t lb_status(uint64_t state, uint64_t epoch, uint64_t v) {
-  return state | (epoch << kLbValueBits) | (v & kLbValue);
-}
-// The state of a status word in epoch e (0: not published in this launch).
-__device__ __forceinline__ uint32_t lb_state(uint64_t w, uint64_t e) {
-  return ((w >> kLbValueBits) & kLbEpochMask) == e ? (uint32_t)(w >> 62) : 0u;
-}
-
-__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
-  const uint32_t l = lane_id();
-#pragma unroll
-  for (uint32_t o = kWave / 2; o; o >>= 1) x += shfl_u64(x, l ^ o);
-  return x;
-}
-__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
-#pragma unroll
-  for (uint32_t o = kWave / 2; o; o >>= 1) {
-    const uint32_t y = (uint32_t)__shfl_xor((int)x, (int)o);
-    x = y < x ? y : x;
-  }
-  return x;
-}
-// Block-wide sum / minimum (uniform result); red holds one word per wave.
-__device__ __forceinline__ uint64_t block_sum(uint64_t v, uint64_t* red) {
-  v = wave_sum(v);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = v;
-  __syncthreads();
-  uint64_t t = 0;
-#pragma unroll
-  for (uint32_t w = 0; w < kBlockThreads / kWave; ++w) t += red[w];
-  __syncthreads();
-  return t;
-}
-__device__ __forceinline__ uint32_t block_min(uint32_t v, uint64_t* red) {
-  v = wave_min(v);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = v;
-  __syncthreads();
-  uint32_t t = ~0u;
-#pragma unroll
-  for (uint32_t w = 0; w < kBlockThreads / kWave; ++w) t = (uint32_t)red[w] < t ? (uint32_t)red[w] : t;
-  __syncthreads();
-  return t;
-}
-
-// Before a block's first claim: thread 0 reads the launch's epoch (its value
-// reaches LDS, so the load is complete before the claim that follows) and
-// claims the block's first chunk; the block waits for it at lb_next.
-__device__ __forceinline__ void lb_begin(uint64_t* lb, uint64_t* s_epoch, uint64_t& claim) {
-  if (threadIdx.x == 0) {
-    *s_epoch = lb_load(lb + 2) & kLbEpochMask;
-    __builtin_amdgcn_s_waitcnt(0);
-    claim = __hip_atomic_fetch_add(lb, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// Thread 0, once it has published the inclusive prefix of the block's current
-// chunk: claims the next one, so that the claim's round trip overlaps the
-// rest of the chunk's work. It first waits for its own memory operations, so
-// its status stores have landed before the claim that may let the last block
-// clear them. No fence: a device-scope release would write back, and its
-// acquire invalidate, this XCD's whole L2 on every claim.
-__device__ __forceinline__ void lb_claim_ahead(uint64_t* lb, uint64_t& claim) {
-  if (threadIdx.x == 0) {
-    __builtin_amdgcn_s_waitcnt(0);
-    claim = __hip_atomic_fetch_add(lb, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// The block's next chunk, claimed earlier by thread 0 (every thread gets it,
-// once the block is done with the previous chunk).
-__device__ __forceinline__ uint64_t lb_next(uint64_t claim, uint64_t* s_chunk) {
-  __syncthreads();
-  if (threadIdx.x == 0) *s_chunk = claim;
-  __syncthreads();
-  return *s_chunk;
-}
-
-// Every thread of the block holding chunk c (uniform), whose items add up to
-// `agg`: the sum of every chunk before c (uniform), c's inclusive prefix
-// published. A window of kPer statuses per thread (the nearest first,
-// consecutive threads on consecutive words) is read at once; the block waits
-// until all of them are published, then adds up to the nearest inclusive one.
-// Each status a thread holds costs registers: a kernel whose other work needs
-// them (the confirmation) takes one per thread.
-template <uint32_t kPer>
-__device__ uint64_t lb_exclusive(uint64_t* lb, uint64_t c, uint64_t agg, uint64_t e, uint64_t* red) {
-  constexpr uint64_t kLbWindow = (uint64_t)kBlockThreads * kPer;
-  uint64_t* st = lb + kLbHeader;
-  if (threadIdx.x == 0) {
-    if (agg > kLbValue) lb_store(lb + 1, 1);
-    lb_store(st + c, lb_status(c ? kLbAggregate : kLbInclusive, e, agg));
-  }
-  if (c == 0) return 0;
-  uint64_t prefix = 0;
-  for (int64_t top = (int64_t)c - 1;; top -= (int64_t)kLbWindow) {
-    uint64_t w[kPer];
-#pragma unroll
-    for (uint32_t k = 0; k < kPer; ++k) {
-      const int64_t j = top - (int64_t)(k * kBlockThreads + threadIdx.x);
-      w[k] = j >= 0 ? lb_load(st + j) : lb_status(kLbInclusive, e, 0);   // before chunk 0: a prefix of 0
-    }
-    for (uint32_t spins = 0;; ++spins) {
-      bool missing = false;
-#pragma unroll
-      for (uint32_t k = 0; k < kPer; ++k) missing |= lb_state(w[k], e) == 0;
-      if (!__syncthreads_or(missing)) break;
-      if (spins == kLbSpinLimit) {   // not published: the state was not clean; count the chunks as empty
-        if (threadIdx.x == 0) lb_store(lb + 1, 1);
-#pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k)
-          if (lb_state(w[k], e) == 0) w[k] = lb_status(kLbAggregate, e, 0);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-      for (uint32_t k = 0; k < kPer; ++k)
-        if (lb_state(w[k], e) == 0) w[k] = lb_load(st + (top - (int64_t)(k * kBlockThreads + threadIdx.x)));
-    }
-    uint32_t near = ~0u;   // distance of the nearest inclusive prefix in this window
-#pragma unroll
-    for (uint32_t k = 0; k < kPer; ++k) {
-      const uint32_t i = k * kBlockThreads + threadIdx.x;
-      if (lb_state(w[k], e) == 2 && i < near) near = i;
-    }
-    const uint32_t first = block_min(near, red);
-    uint64_t v = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < kPer; ++k)
-      if (k * kBlockThreads + threadIdx.x <= first) v += w[k] & kLbValue;
-    prefix += block_sum(v, red);
-    if (first != ~0u) break;
-  }
-  if (threadIdx.x == 0) {
-    if (prefix + agg > kLbValue) lb_store(lb + 1, 1);
-    lb_store(st + c, lb_status(kLbInclusive, e, prefix + agg));
-  }
-  return prefix;
-}
-
-// Called by every block after its failed claim `c` (uniform in the block):
-// the block that made the grid's last claim writes the total (*total; the
-// error count if a wait failed) and readies the state for the next launch.
-__device__ __forceinline__ void lb_finish(uint64_t* lb, uint64_t c, uint64_t n_chunks, uint64_t e,
-                                          uint64_t* total, uint64_t* s_word) {
-  if (c != n_chunks + gridDim.x - 1) return;
-  uint64_t* st = lb + kLbHeader;
-  if (threadIdx.x == 0) {
-    const uint64_t t = n_chunks ? (lb_load(st + n_chunks - 1) & kLbValue) : 0;
-    *s_word = lb_load(lb + 1) ? kCountError : t;
-  }
-  __syncthreads();
-  for (uint64_t i = threadIdx.x; i < n_chunks; i += blockDim.x) lb_store(st + i, 0);
-  if (threadIdx.x == 0) {
-    *total = *s_word;
-    lb_store(lb + 1, 0);
-    lb_store(lb + 2, (e + 1) & kLbEpochMask);
-    lb_store(lb, 0);
-  }
-}
-
-// Compaction in one pass: hit words -> ascending ids of the flagged units
-// (EmitIds), the total into *total; chunk_off (batches; may be null) gets
-// each chunk's first id position. A scan's compaction also clears its
-// confirmation marker (*clear, see kConfirmedWord; may be null). A chunk is kCompactWords words: staged
-// through LDS as in k_apply, kCompactPerThread consecutive words per thread.
-constexpr uint32_t kCompactPerThread = 4;
-constexpr uint64_t kCompactWords = (uint64_t)kBlockThreads * kCompactPerThread;
-constexpr uint32_t kCompactStage = kCompactWords + kCompactWords / 32;
-
-template <class Words, class Src>
-__global__ __launch_bounds__(kBlockThreads) void k_compact(Words words, uint64_t n_words, EmitIds<Src> e,
-                                                           uint64_t* lb, uint64_t* __restrict__ chunk_off,
-                                                           uint64_t* total, uint64_t* clear) {
-  if (clear && blockIdx.x == 0 && threadIdx.x == 0) *clear = 0;
-  __shared__ uint64_t stage[kCompactStage];
-  __shared__ uint64_t lds_w[kBlockThreads / kWave];
-  __shared__ uint64_t s_chunk, s_word, s_epoch;
-  const uint64_t n_chunks = (n_words + kCompactWords - 1) / kCompactWords;
-  uint64_t claim = 0;   // thread 0: the block's next chunk
-  lb_begin(lb, &s_epoch, claim);
-  uint64_t c;
-  while ((c = lb_next(claim, &s_chunk)) < n_chunks) {
-    const uint64_t c0 = c * kCompactWords;
-#pragma unroll
-    for (uint32_t k = 0; k < kCompactPerThread; ++k) {
-      const uint32_t j = k * kBlockThreads + threadIdx.x;
-      stage[stage_index(j)] = c0 + j < n_words ? words(c0 + j) : 0;
-    }
-    __syncthreads();
-    const uint32_t j0 = threadIdx.x * kCompactPerThread;
-    uint64_t x[kCompactPerThread];
-    uint64_t s = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < kCompactPerThread; ++k) {
-      x[k] = stage[stage_index(j0 + k)];
-      s += (uint64_t)__popcll(x[k]);
-    }
-    uint64_t agg;
-    uint64_t pos = block_exclusive_scan<kBlockThreads>(s, lds_w, &agg);
-    const uint64_t p = lb_exclusive<4>(lb, c, agg, s_epoch, lds_w);
-    lb_claim_ahead(lb, claim);
-    if (threadIdx.x == 0 && chunk_off) chunk_off[c] = p;
-    pos += p;
-#pragma unroll
-    for (uint32_t k = 0; k < kCompactPerThread; ++k) {
-      const uint64_t i = c0 + j0 + k;
-      if (i < n_words) e.emit(i, x[k], pos);
-      pos += (uint64_t)__popcll(x[k]);
-    }
-  }
-  lb_finish(lb, c, n_chunks, s_epoch, total, &s_word);
-}
-
 // Batches: first flagged-id position of each image (img_off[n] = total), from
-// the chunk offsets of the compaction and the words of the image's chunk that
+// the block offsets of the compaction and the words of the image's block that
 // precede its first tile. One wave per image: its lanes popcount those words
-// (at most kCompactWords - 1) in strides of the wave, then add up.
+// (at most kItemsPerBlock - 1) in strides of the wave, then add up.
 __global__ void k_image_offsets(ManyImages src, const uint64_t* __restrict__ words,
-                                const uint64_t* __restrict__ chunk_off, const uint64_t* __restrict__ total,
+                                const uint64_t* __restrict__ blk_off, const uint64_t* __restrict__ total,
                                 uint64_t* __restrict__ img_off) {
   const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;   // uniform in the wave
   const uint32_t lane = threadIdx.x % kWave;
@@ -552,11 +303,11 @@ __global__ void k_image_offsets(ManyImages src, const uint64_t* __restrict__ wor
     if (lane == 0) img_off[i] = *total;
     return;
   }
-  const uint64_t b = w / kCompactWords;
+  const uint64_t b = w / kItemsPerBlock;
   uint32_t c = 0;
-  for (uint64_t k = b * kCompactWords + lane; k < w; k += kWave) c += (uint32_t)__popcll(words[k]);
+  for (uint64_t k = b * kItemsPerBlock + lane; k < w; k += kWave) c += (uint32_t)__popcll(words[k]);
   for (int o = kWave / 2; o; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
-  if (lane == 0) img_off[i] = chunk_off[b] + c;
+  if (lane == 0) img_off[i] = blk_off[b] + c;
 }
 
 // Batches, for callers that cannot wait: totals, per-image offsets, ids and
@@ -570,14 +321,12 @@ __global__ void k_stage_out(const uint64_t* __restrict__ counts, int with_matche
   static_assert(sizeof(carve_batch_match) == 24, "a batch record is three 64-bit words");
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  uint64_t nf = counts[0];
-  uint64_t nm = with_matches ? counts[1] : 0;
-  if (t == 0) {   // an incomplete count (kCarveCountError) reaches the host as it is, and stages nothing
+  const uint64_t nf = counts[0];
+  const uint64_t nm = with_matches ? counts[1] : 0;
+  if (t == 0) {
     totals[0] = nf;
     totals[1] = nm;
   }
-  if (nf == kCarveCountError) nf = 0;
-  if (nm == kCarveCountError) nm = 0;
   for (uint64_t i = t; i <= n_images; i += stride) h_off[i] = img_off[i];
   const uint64_t kf = nf < ids_cap ? nf : ids_cap;
   for (uint64_t i = t; i < kf; i += stride) h_ids[i] = ids[i];
@@ -1113,9 +862,6 @@ int device_cus() {
   return cus;
 }
 
-// Blocks of a persistent grid: as many as stay resident at once (capped by
-// `per_cu_cap` when non-zero) so no block waits for a second round, and no
-// more than the work needs.
 // Resident blocks per CU of a kernel at a block size, queried once per
 // (kernel, block size, device): the query costs more host time than a launch.
 struct OccupancyEntry {
@@ -1142,6 +888,9 @@ int blocks_per_cu(Kernel kernel, int threads) {
   return per_cu;
 }
 
+// Blocks of a persistent grid: as many as stay resident at once (capped by
+// `per_cu_cap` when non-zero) so no block waits for a second round, and no
+// more than the work needs.
 template <class Kernel>
 int resident_grid(Kernel kernel, int threads, uint64_t want, uint32_t per_cu_cap = 0) {
   int per_cu = blocks_per_cu(kernel, threads);
@@ -1304,9 +1053,8 @@ struct carve_scan {
   DevBuf d_desc;                 // batches: the descriptors on the device
   HostBuf h_desc;                // pinned staging for their upload
   std::vector<ImageDesc> uploaded;
-  DevBuf bitmap, ids, img_of, count, hit_slot, img_off;   // hit_slot: matched slot of each flagged sector
+  DevBuf bitmap, ws, ids, img_of, count, hit_slot, img_off;   // hit_slot: matched slot of each flagged sector
   DevBuf tau_words;   // one image, per-cluster rule: the hit words of the position-split scan
-  DevBuf lb_scan, chunk_off;   // the compaction's look-back state; batches: each chunk's first id
   HostBuf h_small, h_img_off;                                 // pinned readbacks
   // confirmation: records go to `matches` (rec_cap of them) or to a caller's
   // device buffer (conf_dest, conf_dest_cap records)
@@ -1443,37 +1191,26 @@ int launch_scan(carve_scan* sc, const Src& src) {
     ++sc->n_timed;
     sc->timed = true;
   }
-  const uint64_t n_chunks = cdiv(n_words, kCompactWords);
-  const EmitIds<Src> emit{src, nullptr, sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr, ~0ull};
-  uint64_t* chunk_off = sc->batch ? sc->chunk_off.as<uint64_t>() : nullptr;
-  if (split) {   // the position-split scan's words, merged while compacting
-    const TauMergeWords w{sc->tau_words.as<uint64_t>(), cdiv(n_words, kPositions), n_words, one.tau0,
-                          (uint32_t)(one.n_sectors % kTileSectors)};
-    k_compact<<<resident_grid(k_compact<TauMergeWords, Src>, kBlockThreads, n_chunks), kBlockThreads, 0, s>>>(
-        w, n_words, emit, sc->lb_scan.as<uint64_t>(), chunk_off, d_count, d_count + kConfirmedWord);
-  } else {
-    k_compact<<<resident_grid(k_compact<BitmapWords, Src>, kBlockThreads, n_chunks), kBlockThreads, 0, s>>>(
-        BitmapWords{sc->bitmap.as<uint64_t>()}, n_words, emit, sc->lb_scan.as<uint64_t>(), chunk_off, d_count,
-        d_count + kConfirmedWord);
-  }
+  const uint64_t nb = cdiv(n_words, kItemsPerBlock);
+  uint64_t* sums = sc->ws.as<uint64_t>();
+  uint64_t* offs = sums + nb;
+  if (split)   // the position-split scan's words, merged into the bitmap while counting
+    k_reduce<<<nb, kBlockThreads, 0, s>>>(
+        TauMergeItems{sc->tau_words.as<uint64_t>(), cdiv(n_words, kPositions), sc->bitmap.as<uint64_t>(), n_words,
+                      one.tau0, (uint32_t)(one.n_sectors % kTileSectors)},
+        Count{n_words, nullptr}, sums);
+  else
+    k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{sc->bitmap.as<uint64_t>()}, Count{n_words, nullptr}, sums);
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n_words, nullptr}, offs, d_count, d_count + kConfirmedWord);
+  k_apply<<<nb, kBlockThreads, 0, s>>>(
+      EmitIds<Src>{src, sc->bitmap.as<uint64_t>(), sc->ids.as<uint64_t>(), sc->batch ? sc->img_of.as<uint32_t>() : nullptr,
+                   ~0ull},
+      Count{n_words, nullptr}, offs);
   if constexpr (std::is_same<Src, ManyImages>::value) {
     const uint64_t per_block = kBlockThreads / kWave;
     k_image_offsets<<<cdiv(sc->n_images + 1, per_block), kBlockThreads, 0, s>>>(
-        src, sc->bitmap.as<uint64_t>(), chunk_off, d_count, sc->img_off.as<uint64_t>());
+        src, sc->bitmap.as<uint64_t>(), offs, d_count, sc->img_off.as<uint64_t>());
   }
-  HIP_TRY(hipGetLastError());
-  return CARVE_OK;
-}
-
-// Look-back state for n_chunks chunks (kLbHeader + n_chunks words): zeroed
-// on the stream when allocated; every single-pass launch leaves it zero.
-int reserve_lookback(DevBuf& b, uint64_t n_chunks, hipStream_t s) {
-  const size_t need = (kLbHeader + n_chunks) * sizeof(uint64_t);
-  if (need <= b.bytes) return CARVE_OK;
-  CARVE_TRY(b.reserve(need));
-  const uint64_t words = b.bytes / sizeof(uint64_t);
-  const uint64_t blocks = cdiv(words, 256);
-  k_fill_u64<<<(unsigned)(blocks < 1024 ? blocks : 1024), 256, 0, s>>>(b.as<uint64_t>(), words, 0);
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
@@ -1481,9 +1218,9 @@ int reserve_lookback(DevBuf& b, uint64_t n_chunks, hipStream_t s) {
 // Buffers for a tile space of n_tiles tiles.
 int reserve_scan(carve_scan* sc) {
   const uint64_t n_words = sc->n_tiles ? sc->n_tiles : 1;
-  const uint64_t n_chunks = cdiv(n_words, kCompactWords);
+  const uint64_t nb = cdiv(n_words, kItemsPerBlock);
   CARVE_TRY(sc->bitmap.reserve(n_words * 8));
-  CARVE_TRY(reserve_lookback(sc->lb_scan, n_chunks, sc->stream));
+  CARVE_TRY(sc->ws.reserve(2 * nb * 8));
   CARVE_TRY(sc->ids.reserve(n_words * kTileSectors * 8));
   // a single image of sectors may be scanned split by position (k_scan_tau):
   // its tiles of 64 clusters reach slot 512 * ceil(n_words / 8)
@@ -1495,7 +1232,6 @@ int reserve_scan(carve_scan* sc) {
   if (sc->batch) {
     CARVE_TRY(sc->img_of.reserve(n_words * kTileSectors * 4));
     CARVE_TRY(sc->img_off.reserve((sc->n_images + 1) * 8));
-    CARVE_TRY(sc->chunk_off.reserve(n_chunks * 8));
   }
   if (sc->timing && sc->ev.empty()) {
     sc->ev.assign(2 * kTimedRing, nullptr);
@@ -1508,10 +1244,7 @@ int reserve_scan(carve_scan* sc) {
 // the marker (1: a confirmation ran after the latest scan).
 int read_counts(carve_scan* sc, uint64_t c[3]) {
   static_assert(kConfirmedWord == 2, "the counts and the marker are read in one copy");
-  CARVE_TRY(read_words(sc, sc->count.as<uint64_t>(), 3, c));
-  if (c[0] == kCountError || (c[kConfirmedWord] && c[1] == kCountError))
-    return fail(CARVE_EDEVICE, "a single-pass kernel gave up waiting for an earlier chunk (its state was not clean)");
-  return CARVE_OK;
+  return read_words(sc, sc->count.as<uint64_t>(), 3, c);
 }
 
 // Confirmation buffers for up to cap_f flagged units. Records: room for
@@ -2032,7 +1765,7 @@ extern "C" void free_scan(carve_scan* sc) {
   if (!sc) return;
   (void)hipStreamSynchronize(sc->stream);
   for (DevBuf* b : {&sc->d_desc, &sc->bitmap, &sc->ids, &sc->img_of, &sc->count, &sc->hit_slot, &sc->img_off,
-                    &sc->tau_words, &sc->lb_scan, &sc->chunk_off, &sc->n_match, &sc->match_mask, &sc->out_off,
+                    &sc->tau_words, &sc->ws, &sc->n_match, &sc->match_mask, &sc->out_off,
                     &sc->matches, &sc->cws})
     b->release();
   sc->h_desc.release();
@@ -2129,29 +1862,29 @@ extern "C" int scan_image_noalloc(const carve_index* idx, const void* image, uin
     HIP_TRY(hipGetLastError());
     return CARVE_OK;
   }
-  static_assert(kNoAllocMaxChunks * kCompactWords == kNoAllocMaxWords && kNoAllocLbWords == kLbHeader + kNoAllocMaxChunks,
-                "scratch holds the look-back header and every chunk's status");
-  uint64_t* bitmap = sw;                           // written by the scan kernel before it is read
-  uint64_t* tau_words = sw + kNoAllocMaxWords;     // likewise
-  uint64_t* lb = sw + 2 * kNoAllocMaxWords;        // the compaction's look-back state: must start at zero
-  const uint64_t n_chunks = cdiv(n_words, kCompactWords);
-  k_fill_u64<<<1, 256, 0, s>>>(lb, kLbHeader + n_chunks, 0);
+  // every word read below is written first by this call's own kernels
+  uint64_t* bitmap = sw;
+  uint64_t* tau_words = sw + kNoAllocMaxWords;
+  uint64_t* sums = sw + 2 * kNoAllocMaxWords;
+  uint64_t* offs = sums + kNoAllocMaxChunks;
   const OneImage src{ImageDesc{(const uint8_t*)image, n_sectors, 0, tau0, tau_mode == CARVE_TAU_ANY ? 1u : 0u}};
-  const EmitIds<OneImage> emit{src, nullptr, ids, nullptr, cap};
   const uint32_t per_cu = idx->cfg.blocks_per_cu;
   const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
+  const uint64_t nb = cdiv(n_words, kItemsPerBlock);
   if (use_split(idx, src.d.any_tau)) {   // as scan_image: the position-split scan
     CARVE_TRY(launch_k_scan_tau(idx->sig_kind, idx->layout, src.d, cdiv(n_words, kPositions), chunk, per_cu,
                                 idx->view(), idx->weights, tau_words, nullptr, s));
-    const TauMergeWords w{tau_words, cdiv(n_words, kPositions), n_words, tau0, (uint32_t)(n_sectors % kTileSectors)};
-    k_compact<<<resident_grid(k_compact<TauMergeWords, OneImage>, kBlockThreads, n_chunks), kBlockThreads, 0, s>>>(
-        w, n_words, emit, lb, nullptr, count, nullptr);
+    k_reduce<<<nb, kBlockThreads, 0, s>>>(TauMergeItems{tau_words, cdiv(n_words, kPositions), bitmap, n_words,
+                                                        tau0, (uint32_t)(n_sectors % kTileSectors)},
+                                          Count{n_words, nullptr}, sums);
   } else {
     CARVE_TRY(launch_k_scan<kFlagBits>(idx->sig_kind, src, n_words, chunk, per_cu, idx->view(), idx->weights, bitmap,
                                         nullptr, s, idx->layout));
-    k_compact<<<resident_grid(k_compact<BitmapWords, OneImage>, kBlockThreads, n_chunks), kBlockThreads, 0, s>>>(
-        BitmapWords{bitmap}, n_words, emit, lb, nullptr, count, nullptr);
+    k_reduce<<<nb, kBlockThreads, 0, s>>>(PopcountItems{bitmap}, Count{n_words, nullptr}, sums);
   }
+  k_scan_blocks<<<1, kBlockThreads, 0, s>>>(sums, Count{n_words, nullptr}, offs, count);
+  k_apply<<<nb, kBlockThreads, 0, s>>>(EmitIds<OneImage>{src, bitmap, ids, nullptr, cap}, Count{n_words, nullptr},
+                                       offs);
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
@@ -2307,13 +2040,6 @@ int enqueue_id_copy(carve_scan* sc, uint64_t* out, uint64_t cap) {
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
 }
-
-int read_flag_count(carve_scan* sc, uint64_t* n) {
-  CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>(), n));
-  if (*n == kCountError)
-    return fail(CARVE_EDEVICE, "the compaction gave up waiting for an earlier chunk (its state was not clean)");
-  return CARVE_OK;
-}
 }  // namespace
 
 extern "C" int flagged_sectors(carve_scan* sc, uint64_t* out, uint64_t cap, uint64_t* n_out) {
@@ -2323,9 +2049,9 @@ extern "C" int flagged_sectors(carve_scan* sc, uint64_t* out, uint64_t cap, uint
   uint64_t n = 0;
   if (cap && sc->n_tiles && is_device_memory(out)) {   // copy on the device, then one synchronization
     CARVE_TRY(enqueue_id_copy(sc, out, cap));
-    CARVE_TRY(read_flag_count(sc, &n));
+    CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>(), &n));
   } else {
-    CARVE_TRY(read_flag_count(sc, &n));
+    CARVE_TRY(read_u64(sc, sc->count.as<uint64_t>(), &n));
     CARVE_TRY(copy_ids(sc, 0, n, out, cap));
   }
   *n_out = n;
@@ -2398,8 +2124,6 @@ int read_img_off(carve_batch* b) {
   CARVE_TRY(b->h_img_off.reserve((b->n_images + 1) * 8));
   HIP_TRY(hipMemcpyAsync(b->h_img_off.p, b->img_off.p, (b->n_images + 1) * 8, hipMemcpyDeviceToHost, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
-  if (b->h_img_off.as<uint64_t>()[b->n_images] == kCountError)
-    return fail(CARVE_EDEVICE, "the compaction gave up waiting for an earlier chunk (its state was not clean)");
   return CARVE_OK;
 }
 }  // namespace
@@ -2422,7 +2146,7 @@ extern "C" int batch_flagged_sectors(carve_batch* b, uint32_t image, uint64_t* o
   if (cap && !out) return fail(CARVE_EINVAL, "batch_flagged_sectors: null out with cap > 0");
   uint64_t first = 0, n = 0;
   if (all) {
-    if (b->n_tiles) CARVE_TRY(read_flag_count(b, &n));
+    if (b->n_tiles) CARVE_TRY(read_u64(b, b->count.as<uint64_t>(), &n));
   } else {
     CARVE_TRY(read_img_off(b));
     const uint64_t* off = b->h_img_off.as<uint64_t>();

@@ -7,11 +7,6 @@
 
 #define CARVE_HIDDEN extern "C" __attribute__((visibility("hidden")))
 
-// The count a single-pass kernel (compaction, confirmation) writes when one of
-// its waits for an earlier chunk ran past its bound: its look-back state was
-// not clean, and the counts and offsets of that launch are not to be used.
-constexpr uint64_t kCarveCountError = ~0ull;
-
 // Records a message for carve_last_error() and returns `code`.
 CARVE_HIDDEN int carve_fail_msg(int code, const char* msg);
 

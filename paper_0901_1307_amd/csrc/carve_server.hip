@@ -173,9 +173,7 @@ int retire(carve_server* s, Lane& ln) {
   const uint64_t total = st[0];
   const uint64_t* off = st + 2;
   uint64_t nm = s->p.confirm ? st[1] : 0;
-  if (total == kCarveCountError || nm == kCarveCountError)
-    rc = carve_fail_msg(CARVE_EDEVICE, "server: a single-pass kernel gave up waiting (its state was not clean)");
-  else if (total > res->ids.cap) {
+  if (total > res->ids.cap) {
     uint64_t got = 0;
     if (!res->ids.reserve(total)) rc = carve_fail_msg(CARVE_ENOMEM, "server: pinned allocation failed");
     else rc = batch_flagged_sectors(ln.batch, CARVE_ALL_IMAGES, res->ids.p, res->ids.cap, &got);
