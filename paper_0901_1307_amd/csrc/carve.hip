@@ -53,15 +53,15 @@ using namespace carve;
 // that noalloc_scratch() looks up per device.
 constexpr uint64_t kNoAllocMaxSectors = 1ull << 27;                        // 64 GiB of image
 constexpr uint64_t kNoAllocMaxWords = kNoAllocMaxSectors / kTileSectors;    // 2^21 hit words
-constexpr uint64_t kNoAllocMaxChunks = kNoAllocMaxWords / 2048;             // compaction chunks of 2048 words
-constexpr uint64_t kScratchWords = 2 * kNoAllocMaxWords + 2 * kNoAllocMaxChunks;   // 32 MiB + 16 KiB
+constexpr uint64_t kNoAllocMaxChunks = kNoAllocMaxWords / 1024;             // compaction chunks of 1024 words
+constexpr uint64_t kScratchWords = 2 * kNoAllocMaxWords + 2 * kNoAllocMaxChunks;   // 32 MiB + 32 KiB
 static __device__ __align__(256) uint64_t scratch[kScratchWords];
 
 namespace {
 
 constexpr int kBlockThreads = 256;
-constexpr int kItemsPerThread = 8;
-constexpr int kItemsPerBlock = kBlockThreads * kItemsPerThread;   // 2048
+constexpr int kItemsPerThread = 4;
+constexpr int kItemsPerBlock = kBlockThreads * kItemsPerThread;   // 1024
 static_assert(kNoAllocMaxChunks * kItemsPerBlock == kNoAllocMaxWords, "scratch holds every chunk sum");
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be placed

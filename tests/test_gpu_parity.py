@@ -290,17 +290,18 @@ def test_many_duplicates_of_one_sector():
     assert len(m) == 4 * 300
 
 
-@pytest.mark.parametrize("n_planted", [2047, 2048, 2049, 4097])
+@pytest.mark.parametrize("n_planted", [1023, 1024, 1025, 2047, 2048, 2049, 4097])
 def test_compaction_chunk_edges(n_planted):
-    """The compaction works in chunks of 2048 items: hit words (64 sectors
+    """The compaction works in chunks of 1024 items: hit words (64 sectors
     each) for the flagged ids, then one count per flagged sector for the
-    record offsets. Flags on both sides of a word chunk's edge and flagged
-    counts around multiples of 2048 give the oracle's lists exactly."""
+    record offsets. Flags on both sides of word-chunk edges and flagged counts
+    around multiples of 1024 give the oracle's lists exactly."""
     gen = torch.Generator().manual_seed(n_planted)
     masters = torch.randint(0, 256, (4096 * SECTOR,), dtype=torch.uint8, generator=gen)
     n_sec = 2048 * 64 * 2 + 37                         # 4096 hit words and a ragged one
     image = torch.randint(0, 256, (n_sec * SECTOR,), dtype=torch.uint8, generator=gen)
-    edges = [0, 2048 * 64 - 1, 2048 * 64, 2048 * 64 + 1, 4096 * 64 - 1, 4096 * 64, n_sec - 1]
+    edges = [0, 1024 * 64 - 1, 1024 * 64, 2048 * 64 - 1, 2048 * 64, 2048 * 64 + 1, 4096 * 64 - 1, 4096 * 64,
+             n_sec - 1]
     rng = random.Random(n_planted)
     rest = rng.sample(sorted(set(range(n_sec)) - set(edges)), n_planted - len(edges))
     img2 = image.view(n_sec, SECTOR)
