@@ -441,19 +441,19 @@ __global__ void k_bloom_tau_build(const uint64_t* __restrict__ keys, const uint8
 }
 
 // The fragment scan's two filters (placed by frag_lds_place and
-// frag_bloom_place from a signature's low half; 32-bit words), from the
+// frag_bloom_place from a signature's filter key; 32-bit words), from the
 // table's keys; with_zero: signature 0 is a master's too (it has no slot), so
-// the bits of low half 0 are set as well.
+// the bits of its key are set as well.
 __global__ void k_lds_filter_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t n_words,
                                    uint32_t with_zero, uint32_t* filter) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t w, bits;
   if (i == 0 && with_zero) {
-    frag_lds_place(0u, n_words, &w, &bits);
+    frag_lds_place(frag_filter_key(0), n_words, &w, &bits);
     atomicOr(&filter[w], bits);
   }
   if (i >= n_slots || keys[i] == kEmptyKey) return;
-  frag_lds_place((uint32_t)keys[i], n_words, &w, &bits);
+  frag_lds_place(frag_filter_key(keys[i]), n_words, &w, &bits);
   atomicOr(&filter[w], bits);
 }
 __global__ void k_frag_bloom_build(const uint64_t* __restrict__ keys, uint64_t n_slots, uint32_t log2_words,
@@ -461,11 +461,11 @@ __global__ void k_frag_bloom_build(const uint64_t* __restrict__ keys, uint64_t n
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t w, bits;
   if (i == 0 && with_zero) {
-    frag_bloom_place(0u, log2_words, &w, &bits);
+    frag_bloom_place(frag_filter_key(0), log2_words, &w, &bits);
     atomicOr(&bloom[w], bits);
   }
   if (i >= n_slots || keys[i] == kEmptyKey) return;
-  frag_bloom_place((uint32_t)keys[i], log2_words, &w, &bits);
+  frag_bloom_place(frag_filter_key(keys[i]), log2_words, &w, &bits);
   atomicOr(&bloom[w], bits);
 }
 
@@ -1659,7 +1659,7 @@ int build_index(const void* master_sectors, const uint64_t* file_sector_offsets,
     // per signature, then as large as 4 MiB and 16 bits per signature allow.
     // A filter word per sector costs less traffic than a bucket line even
     // where the filter no longer fits in L2.
-    // Fragment indexes (32-bit words of 4 bits, which fill less evenly) aim
+    // Fragment indexes (32-bit words of 3 bits, which fill less evenly) aim
     // at twice the bits.
     constexpr uint64_t kAutoBytes = 4ull << 20;
     const uint64_t keys_n = h_unique ? h_unique : 1;

@@ -19,40 +19,83 @@ constexpr uint32_t kLaneWindows = 16;                        // consecutive wind
 constexpr uint32_t kWaveWindows = kWave * kLaneWindows;      // 1024 windows = 4 KiB of image per wave task
 constexpr uint32_t kFragRowDw = kLaneWindows;                // a lane's own 64 bytes, in dwords
 constexpr uint32_t kLdsFilterMaxWords = 40960;               // 160 KiB, all of a CU's LDS: the first filter
+constexpr int kDppWaveShl1 = 0x130;                          // DPP control: lane i takes lane i + 1's value
 
 // The two filters of a fragment index, both of 32-bit words, are placed from
-// the low 32 bits of the signature, s = sig mod 2^32: Eq. (1) reduced modulo
-// 2^32 is the same recurrence (reduction modulo 2^32 respects sums and
-// products), so the scan rolls s with 32-bit arithmetic alone and forms the
-// full 64-bit signature only for the rare windows that pass both filters.
-// Positions come from two 32 x 32 -> 64-bit products a = s * kFragMulA and
-// b = s * kFragMulB (one multiply-add instruction each); a word index comes
-// from the top bits of a product's low half (multiplicative hashing), bit
-// positions are 5-bit fields of its high half:
-// * first level, in LDS: word from a (the low half scaled to the word count,
-//   which need not be a power of two), 2 bits from a's high half;
-// * second level, the Bloom filter in L2: word from b, 3 bits from b's high half
-//   (a simulation of the logos set's filters on random low halves: both
-//   levels pass 0.086% of windows with 2 bits, 0.034% with 3, 0.021% with 4;
-//   3 bits keep the exact path rare for two instructions fewer than 4).
-// Only windows that pass the first level read the second. A signature whose
-// low half is 0 is placed like any other; when a master's whole signature is
-// 0 (it lives beside the table, not in it) the build sets the bits of low half
-// 0 in both filters, so no value needs special handling in the scan.
+// a 32-bit key: k = H mod 2^32, the low half of the window's data part H (its
+// signature minus the constant 5381*33^64, below). Eq. (1) reduced modulo 2^32
+// is the same recurrence (reduction modulo 2^32 respects sums and products),
+// so the scan rolls k with 32-bit arithmetic alone, and equal signatures give
+// equal keys; the full 64-bit signature is formed only for the rare windows
+// that pass both filters. Rolling H rather than the signature drops the
+// constant term from every step.
+// Each level takes one 32 x 32 -> 64-bit product of the key (a = k * kFragMulA,
+// b = k * kFragMulB; one multiply-add instruction each, the only full 32-bit
+// multiplies of a lookup):
+// * first level, in LDS: the word from the low 24 bits of a's high half scaled
+//   to the word count (a 24-bit multiply, which need not be a power of two),
+//   2 bit positions from bits 24-28 of a's high and of a's low half;
+// * second level, the Bloom filter in L2: the word from the top bits of b's
+//   low half, 3 bit positions from bits 0-4, 16-20 and 24-28 of b's high half.
+// Bit positions sit at byte and half-word boundaries so that the scan's shifts
+// take them straight from the product's register (sub-dword operand selects).
+// A simulation of the logos set's filters on random keys: both levels pass
+// 0.033% of windows; 3 Bloom bits keep the exact path rare for two
+// instructions fewer than 4. Only windows that pass the first level read the
+// second. Key 0 is placed like any other; when a master's whole signature is
+// 0 (it lives beside the table, not in it) the build sets the bits of its key
+// in both filters, so no value needs special handling in the scan.
 constexpr uint32_t kFragMulA = 0x9E3779B1u;
 constexpr uint32_t kFragMulB = 0x85EBCA77u;
-__device__ __forceinline__ void frag_lds_place(uint32_t s, uint32_t n_words, uint32_t* word, uint32_t* bits) {
-  const uint64_t a = (uint64_t)s * kFragMulA;
-  const uint32_t a_hi = (uint32_t)(a >> 32);
-  *word = (uint32_t)(((uint64_t)(uint32_t)a * n_words) >> 32);   // < n_words
-  *bits = (1u << (a_hi & 31u)) | (1u << ((a_hi >> 5) & 31u));
+// A first-level lookup: the word and the 2 bit positions (each < 32).
+struct FragLdsProbe {
+  uint32_t word, p0, p1;
+};
+// n_words in 1..kLdsFilterMaxWords (so n_words * 256 < 2^24).
+__device__ __forceinline__ FragLdsProbe frag_lds_probe(uint32_t key, uint32_t n_words) {
+  const uint64_t a = (uint64_t)key * kFragMulA;
+  const uint32_t hi = (uint32_t)(a >> 32), lo = (uint32_t)a;
+  FragLdsProbe r;
+  const uint32_t n8 = (n_words << 8) & 0xFFFFFFu;   // both factors 24-bit: a 24-bit multiply
+  r.word = (uint32_t)(((uint64_t)(hi & 0xFFFFFFu) * n8) >> 32);   // < n_words
+  r.p0 = (hi >> 24) & 31u;
+  r.p1 = (lo >> 24) & 31u;
+  return r;
 }
+// A second-level lookup: the word's byte offset and the 3 bit positions.
+struct FragBloomProbe {
+  uint32_t byte_off, p0, p1, p2;
+};
 // log2_words in 1..30 (the filter has 2 to 2^30 words).
-__device__ __forceinline__ void frag_bloom_place(uint32_t s, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
-  const uint64_t b = (uint64_t)s * kFragMulB;
-  const uint32_t b_hi = (uint32_t)(b >> 32);
-  *word = (uint32_t)b >> (32 - log2_words);
-  *bits = (1u << (b_hi & 31u)) | (1u << ((b_hi >> 5) & 31u)) | (1u << ((b_hi >> 10) & 31u));
+__device__ __forceinline__ FragBloomProbe frag_bloom_probe(uint32_t key, uint32_t log2_words) {
+  const uint64_t b = (uint64_t)key * kFragMulB;
+  const uint32_t hi = (uint32_t)(b >> 32), lo = (uint32_t)b;
+  FragBloomProbe r;
+  r.byte_off = (lo >> (30 - log2_words)) & ~3u;   // the word (top log2_words bits of lo) times 4
+  r.p0 = hi & 31u;
+  r.p1 = (hi >> 16) & 31u;
+  r.p2 = (hi >> 24) & 31u;
+  return r;
+}
+// The build's view: the word and its bits.
+__device__ __forceinline__ void frag_lds_place(uint32_t key, uint32_t n_words, uint32_t* word, uint32_t* bits) {
+  const FragLdsProbe r = frag_lds_probe(key, n_words);
+  *word = r.word;
+  *bits = (1u << r.p0) | (1u << r.p1);
+}
+__device__ __forceinline__ void frag_bloom_place(uint32_t key, uint32_t log2_words, uint32_t* word, uint32_t* bits) {
+  const FragBloomProbe r = frag_bloom_probe(key, log2_words);
+  *word = r.byte_off >> 2;
+  *bits = (1u << r.p0) | (1u << r.p1) | (1u << r.p2);
+}
+// The scan's view: 1 when all of a probe's bits are set in the filter word x
+// (the word shifted by each position and the low bits combined: fewer
+// instructions than a mask built and compared).
+__device__ __forceinline__ uint32_t frag_lds_has(uint32_t x, const FragLdsProbe& r) {
+  return (x >> r.p0) & (x >> r.p1) & 1u;
+}
+__device__ __forceinline__ uint32_t frag_bloom_has(uint32_t x, const FragBloomProbe& r) {
+  return (x >> r.p0) & (x >> r.p1) & (x >> r.p2) & 1u;
 }
 
 // Rolling Eq. (1) over a 64-byte window by 4 bytes. With the window's data
@@ -69,11 +112,12 @@ constexpr uint64_t kPow64 = pow33(kFragBytes);
 constexpr uint64_t kFragInit = 5381ull * pow33(kFragBytes);
 constexpr uint64_t kRollAdd = kFragInit - kFragInit * kPow4;   // mod 2^64
 constexpr uint64_t kNegPow64 = 0ull - kPow64;                  // mod 2^64
-// the same constants modulo 2^32, for the low half of the signature
+// the constants modulo 2^32 that roll the filter key H mod 2^32
 constexpr uint32_t kPow4Lo = (uint32_t)kPow4;
 constexpr uint32_t kFragInitLo = (uint32_t)kFragInit;
-constexpr uint32_t kRollAddLo = (uint32_t)kRollAdd;
 constexpr uint32_t kNegPow64Lo = (uint32_t)kNegPow64;
+// The filter key of a signature: its data part modulo 2^32.
+__device__ __forceinline__ uint32_t frag_filter_key(uint64_t sig) { return (uint32_t)sig - kFragInitLo; }
 
 // The byte weights of D in dot4 form: D = dot(word, low bytes of 33^(3-i))
 // + 256 dot(word, second bytes of 33^(3-i)) (33^3 < 2^16).
@@ -154,61 +198,57 @@ __device__ __forceinline__ void frag_task(uint64_t n_windows, uint64_t n_words, 
   for (uint32_t k = 0; k < kFragRowDw; ++k) d[k] = word_djb2(cur.v[k / 4][k % 4]);
   const uint32_t dx = word_djb2(cur.x);
   // nx[k] = D(dword 16l + 16 + k): the next lane's d[k]; for lane 63, lane
-  // k's dx (the whole wave runs this code, so every source lane is active)
+  // k's dx (the whole wave runs this code, so every source lane is active).
+  // Lane 63's value arrives first by a permute (lane 63 reads lane k; the
+  // other lanes read lanes below 31 and are overwritten), then a wave-wide
+  // shift by one lane moves d[k] down into lanes 0-62 and leaves lane 63,
+  // which has no source, as it was: one vector instruction per word.
+  const uint32_t ext_from = l == kWave - 1 ? 0u : 4u * (l % kFragRowDw);   // byte address of a lane
   uint32_t nx[kFragRowDw];
 #pragma unroll
   for (uint32_t k = 0; k < kFragRowDw; ++k) {
-    const uint32_t next_lane = (uint32_t)__shfl_down((int)d[k], 1, kWave);
-    const uint32_t from_ext = (uint32_t)__builtin_amdgcn_readlane((int)dx, (int)k);
-    nx[k] = l == kWave - 1 ? from_ext : next_lane;
+    const int ext = __builtin_amdgcn_ds_bpermute((int)(ext_from + 4u * k), (int)dx);
+    nx[k] = (uint32_t)__builtin_amdgcn_update_dpp(ext, (int)d[k], kDppWaveShl1, 0xF, 0xF, false);
   }
   const uint64_t j0 = t * kWaveWindows + (uint64_t)l * kLaneWindows;
   const uint32_t valid = j0 >= n_windows ? 0u : (n_windows - j0 >= kLaneWindows ? kLaneWindows
                                                                                  : (uint32_t)(n_windows - j0));
-  // low halves of the signatures of the lane's 16 windows: Horner over the
-  // first window's words, then the rolling update modulo 2^32
+  // filter keys (H mod 2^32) of the lane's 16 windows: Horner over the first
+  // window's words, then the rolling update modulo 2^32
   uint32_t s = 0;
 #pragma unroll
   for (uint32_t k = 0; k < kFragRowDw; ++k) s = s * kPow4Lo + d[k];
-  s += kFragInitLo;
   uint32_t h[kLaneWindows];
 #pragma unroll
   for (uint32_t w = 0; w < kLaneWindows; ++w) {
     h[w] = s;
-    s = s * kPow4Lo + (kRollAddLo + kNegPow64Lo * d[w]) + nx[w];   // unused after the last window
+    s = s * kPow4Lo + kNegPow64Lo * d[w] + nx[w];   // unused after the last window
   }
   // windows still candidates after both filters
   uint32_t pend = valid >= 16 ? 0xFFFFu : (1u << valid) - 1u;
-  uint32_t fail = 0;
+  uint32_t pass = 0;
 #pragma unroll
   for (uint32_t w = 0; w < kLaneWindows; ++w) {
-    uint32_t wi, bits;
-    frag_lds_place(h[w], lw, &wi, &bits);
-    fail |= (uint32_t)((~lfilter[wi] & bits) != 0u) << w;
+    const FragLdsProbe r = frag_lds_probe(h[w], lw);
+    pass |= frag_lds_has(lfilter[r.word], r) << w;
   }
-  pend &= ~fail;
+  pend &= pass;
   // the Bloom words, all in flight together: a window that failed the LDS
   // filter reads the filter's first word, the same address in every such
   // lane, and its bits are dropped (no branches)
-  uint32_t fw[kLaneWindows];
   if constexpr (kBloom) {
+    FragBloomProbe r[kLaneWindows];
+    uint32_t fw[kLaneWindows];
 #pragma unroll
     for (uint32_t w = 0; w < kLaneWindows; ++w) {
-      uint32_t wi, bits;
-      frag_bloom_place(h[w], lwb, &wi, &bits);
-      const uint32_t off = ((pend >> w) & 1u) ? wi << 2 : 0u;   // wi < 2^30
-      fw[w] = *(const uint32_t*)(bloom + off);
+      r[w] = frag_bloom_probe(h[w], lwb);
+      const uint32_t keep = 0u - ((pend >> w) & 1u);   // all ones or zero
+      fw[w] = *(const uint32_t*)(bloom + (r[w].byte_off & keep));
     }
-  }
-  if constexpr (kBloom) {
-    fail = 0;
+    pass = 0;
 #pragma unroll
-    for (uint32_t w = 0; w < kLaneWindows; ++w) {
-      uint32_t wi, bits;
-      frag_bloom_place(h[w], lwb, &wi, &bits);
-      fail |= (uint32_t)((~fw[w] & bits) != 0u) << w;
-    }
-    pend &= ~fail;
+    for (uint32_t w = 0; w < kLaneWindows; ++w) pass |= frag_bloom_has(fw[w], r[w]) << w;
+    pend &= pass;
   }
   // The candidates (rare: about one window in 3000 of random data, besides
   // the true hits) take the exact test with the full 64-bit signature,

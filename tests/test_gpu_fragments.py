@@ -219,15 +219,19 @@ def test_fragment_workload_full():
 @pytest.mark.parametrize("bloom", [0, carve.CARVE_BLOOM_OFF])
 @pytest.mark.parametrize("zero_master", [True, False])
 def test_fragment_signature_low_halves(bloom, zero_master):
-    """The scan filters windows on the low 32 bits of their signature and takes
-    the exact 64-bit test only for those that pass: master fragments whose
-    signature is 0 (it lives beside the table) or whose low half is 0, 1 or
-    2^32 - 1 with other high halves; windows equal to them, windows crafted
+    """The scan filters windows on a 32-bit key taken from their signature
+    (the low half of the signature's data part: the signature minus
+    5381 * 33^64, modulo 2^32) and takes the exact 64-bit test only for those
+    that pass: master fragments whose signature is 0 (it lives beside the
+    table), whose low half is 0, 1 or 2^32 - 1, or whose key is 0, 1 or
+    2^32 - 1, with other high halves; windows equal to them, windows crafted
     to their signatures with other bytes (flagged, not confirmed), and windows
     that share only a low half (not flagged); against the oracle."""
     from oracle import spec
     rng = random.Random(77 + zero_master)
-    targets = [(1 << 32) * 5, (1 << 32) * 12345 + 1, (1 << 64) - 1, ((1 << 31) + 7) << 32 | 0xFFFFFFFF]
+    key0 = (5381 * pow(33, 64, 1 << 64)) & 0xFFFFFFFF   # the low half whose key is 0
+    targets = [(1 << 32) * 5, (1 << 32) * 12345 + 1, (1 << 64) - 1, ((1 << 31) + 7) << 32 | 0xFFFFFFFF,
+               (1 << 32) * 777 + key0, (1 << 32) * 31 + key0 + 1, (1 << 32) * 90001 + key0 - 1]
     if zero_master:
         targets.append(0)
     crafted = [spec.craft_sector(bytes([65 + i]) * 8, t, n=64) for i, t in enumerate(targets)]
