@@ -7,10 +7,15 @@ signatures, cluster positions, index probe, ordered compaction of the flagged
 ids), confirm_enqueue_to (byte comparison of every flagged sector with its
 candidate master sectors, ordered records into a device buffer),
 flagged_sectors_enqueue (ids into a device buffer) and scan_counts (the one
-readback: both counts). The master
-index is built once, before timing, and the launch shape is picked by the
-library's autotuner on a tuning sample (an image of the same recipe that is
-not the timed one).
+readback: both counts). The fragment workload keeps two steps in flight by
+default (--inflight), on two streams with a scan object and output buffers
+each: the scan kernels run in step order, and each step's confirmation, ids
+copy and readback run beside the next step's scan; its line also reports the
+same steps one at a time (`ms_per_step_one_in_flight`). The plain workloads
+run one step at a time by default (two in flight measured no faster). The
+master index is built once, before timing, and the launch shape is picked by
+the library's autotuner on a tuning sample (an image of the same recipe that
+is not the timed one).
 
 With no --workload, prints one JSON line for the whole metric: the headline
 is the large workload (64 GiB image, 16M master sectors), with `roofline`
@@ -182,6 +187,97 @@ def scan_kernel_name(idx) -> str:
     return "k_scan_tau" if on and idx.stats()["bloom_bytes"] else "k_scan"
 
 
+class StepLanes:
+    """Steps of one workload kept in flight on `depth` streams. Step i runs
+    wholly on stream i % depth with that stream's scan object and output
+    buffers: the scan, the confirmation into the records buffer, the ids copy
+    and the one count readback. The host waits for step i - depth + 1's counts
+    after enqueuing step i, so the GPU never waits for the host. Step i's scan
+    waits on the other stream for step i-1's whole step, or with `overlap`
+    for step i-1's scan only (then step i-1's confirmation, ids copy and
+    readback run beside step i's scan). depth 1 is the plain loop: enqueue a
+    step, wait for its counts."""
+
+    def __init__(self, depth, first_scan, scan_again, ids_len, rec_bytes, overlap=False):
+        import torch
+        from paper_0901_1307_amd import carve
+        self.carve, self.depth, self.scan_again, self.overlap = carve, depth, scan_again, overlap
+        self.lanes = []
+        for k in range(depth):
+            s = torch.cuda.current_stream() if k == 0 else torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                sc = first_scan()
+            self.lanes.append({"stream": s, "scan": sc, "event": torch.cuda.Event(),
+                               "ids": torch.empty(ids_len, dtype=torch.int64, device="cuda"),
+                               "rec": torch.empty(rec_bytes, dtype=torch.uint8, device="cuda")})
+        torch.cuda.synchronize()
+
+    def _enqueue(self, i):
+        import torch
+        lane, prev = self.lanes[i % self.depth], self.lanes[(i - 1) % self.depth]
+        with torch.cuda.stream(lane["stream"]):
+            if self.depth > 1 and i > 0:
+                lane["stream"].wait_event(prev["event"])   # in step order
+            self.scan_again(lane["scan"])
+            if self.overlap:
+                lane["event"].record(lane["stream"])
+            self.carve.confirm_enqueue(self.scan_index, lane["scan"], lane["rec"])
+            self.carve.flagged_sectors_enqueue(lane["scan"], lane["ids"])
+            if not self.overlap:
+                lane["event"].record(lane["stream"])
+
+    def run(self, index, n, check):
+        """n steps; check(counts) on each step's (n_flagged, n_confirmed)."""
+        self.scan_index = index
+        for i in range(n):
+            self._enqueue(i)
+            if i >= self.depth - 1:
+                check(self.carve.scan_counts(self.lanes[(i - self.depth + 1) % self.depth]["scan"]))
+        for i in range(max(0, n - self.depth + 1), n):
+            check(self.carve.scan_counts(self.lanes[i % self.depth]["scan"]))
+
+    def set_timing(self, on):
+        for lane in self.lanes:
+            lane["scan"].set_timing(on)
+
+    def kernel_ms(self, n):
+        """The kernel durations of the last n steps (each lane's share)."""
+        out = []
+        for k, lane in enumerate(self.lanes):
+            mine = sum(1 for i in range(n) if i % self.depth == k)
+            out += lane["scan"].kernel_ms_recent(mine) if mine else []
+        return out
+
+    def release(self):
+        self.lanes = []
+
+
+def timed_lanes(lanes, index, steps, warmup, expect):
+    """warmup, then `steps` timed steps between HIP events on the default
+    stream (the host has waited for every step's counts before the closing
+    event); returns (ms_per_step, wall ms per step, kernel ms of every timed
+    launch)."""
+    import torch
+
+    def check(c):
+        assert c == expect, (c, expect)
+
+    lanes.run(index, warmup, check)
+    lanes.set_timing(True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record()
+    lanes.run(index, steps, check)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - wall0) * 1e3 / steps
+    kms = lanes.kernel_ms(steps)
+    assert len(kms) == steps
+    lanes.set_timing(False)
+    return ev0.elapsed_time(ev1) / steps, wall, kms
+
+
 def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
     """One image: K timed steps of scan + ids + confirmation."""
     import torch
@@ -225,34 +321,29 @@ def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
     sc = carve.scan_image(idx, img.data)
     n_flag = carve.flagged_sectors(sc, flag_out).numel()
     n_match = carve.confirm_matches(idx, sc, torch.empty(16 * max(1, 4 * n_flag), dtype=torch.uint8, device="cuda"))
-    match_out = torch.empty(16 * max(1, 2 * n_match + 1024), dtype=torch.uint8, device="cuda")
+    del flag_out
     log(f"[bench] {n_flag} flagged, {n_match} confirmed")
 
-    def step():   # the whole path enqueued, then one wait for both counts
-        carve.scan_image(idx, img.data, scan=sc)
-        carve.confirm_enqueue(idx, sc, match_out)
-        carve.flagged_sectors_enqueue(sc, flag_out)
-        return carve.scan_counts(sc)
+    # the whole path enqueued per step (scan, records into a device buffer, ids
+    # copy), one wait for both counts; steps in flight on `inflight` streams
+    inflight = args.inflight or 1
 
-    for _ in range(args.warmup):
-        step()
-    sc.set_timing(True)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        nf, nm = step()
-        assert (nf, nm) == (n_flag, n_match)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    kernel_ms = sc.kernel_ms_recent(args.steps)   # every timed launch, read after the timed region
-    assert len(kernel_ms) == args.steps
-    sc.set_timing(False)
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (event), wall {wall * 1e3 / args.steps:.3f} ms/step")
+    def lanes_of(depth):
+        return StepLanes(depth, lambda: carve.scan_image(idx, img.data),
+                         lambda s: carve.scan_image(idx, img.data, scan=s), n_sectors, 16 * max(1, 2 * n_match + 1024),
+                         overlap=args.overlap == "on")
+
+    serial = None
+    if inflight > 1:   # the same steps one at a time, for comparison
+        lanes = lanes_of(1)
+        ms1, _, _ = timed_lanes(lanes, idx, args.steps, args.warmup, (n_flag, n_match))
+        lanes.release()
+        serial = round(ms1, 4)
+    lanes = lanes_of(inflight)
+    ms_per_step, wall, kernel_ms = timed_lanes(lanes, idx, args.steps, args.warmup, (n_flag, n_match))
+    lanes.release()
+    log(f"[bench] {args.steps} steps, {inflight} in flight: {ms_per_step:.3f} ms/step (event), "
+        f"wall {wall:.3f} ms/step; one at a time {serial} ms/step")
     # apart from the timed steps: the same step with ids and records copied to
     # pinned host memory (end to end including device-to-host)
     flag_h = torch.empty(n_flag + 1024, dtype=torch.int64, pin_memory=True)
@@ -270,7 +361,7 @@ def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
     for _ in range(5):
         assert step_host() == (n_flag, n_match)
     ms_host = (time.perf_counter() - t_h) * 1e3 / 5
-    del sc, flag_out, match_out, flag_h, match_h
+    del sc, flag_h, match_h
 
     value = image_bytes / (ms_per_step * 1e-3) / 1e9
     k_avg = sum(kernel_ms) / len(kernel_ms)
@@ -304,6 +395,8 @@ def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
             "prefilter_bytes": idx.stats()["bloom_bytes"],
         },
         "sectors_per_s": round(n_sectors / (ms_per_step * 1e-3)),
+        "steps_in_flight": inflight,
+        "ms_per_step_one_in_flight": serial,
         "ms_per_step_host_outputs": round(ms_host, 4),
         "hbm_frac_of_value": round(value / HBM_PEAK_GBS, 4),
         "flagged": n_flag,
@@ -716,37 +809,35 @@ def run_fragments(args):
     sc = carve.scan_fragments(idx, img)
     n_flag = carve.flagged_sectors(sc).numel()
     n_match = carve.confirm_matches(idx, sc, torch.empty(16 * (2 * n_flag + 1024), dtype=torch.uint8, device="cuda"))
-    flag_out = torch.empty(n_flag + 1024, dtype=torch.int64, device="cuda")
-    match_out = torch.empty(16 * (n_match + 1024), dtype=torch.uint8, device="cuda")
+    del sc
     log(f"[bench] {n_flag} windows flagged, {n_match} confirmed")
 
-    def step():   # the whole path enqueued, then one wait for both counts
-        carve.scan_fragments(idx, img, scan=sc)
-        carve.confirm_enqueue(idx, sc, match_out)
-        carve.flagged_sectors_enqueue(sc, flag_out)
-        return carve.scan_counts(sc)
+    # the whole path enqueued per step (scan, records into a device buffer, ids
+    # copy), one wait for both counts; steps in flight on `inflight` streams
+    inflight = args.inflight or 2
 
-    for _ in range(args.warmup):
-        step()
-    sc.set_timing(True)
-    kms = []
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        assert step() == (n_flag, n_match)
-    ev1.record()
-    torch.cuda.synchronize()
-    kms = sc.kernel_ms_recent(args.steps)   # every timed launch, read after the timed region
-    assert len(kms) == args.steps
-    sc.set_timing(False)
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    def lanes_of(depth):
+        return StepLanes(depth, lambda: carve.scan_fragments(idx, img),
+                         lambda s: carve.scan_fragments(idx, img, scan=s), n_flag + 1024, 16 * (n_match + 1024),
+                         overlap=args.overlap != "off")
+
+    serial, serial_kms = None, None
+    if inflight > 1:   # the same steps one at a time, for comparison
+        lanes = lanes_of(1)
+        ms1, _, serial_kms = timed_lanes(lanes, idx, args.steps, args.warmup, (n_flag, n_match))
+        lanes.release()
+        serial = round(ms1, 4)
+    lanes = lanes_of(inflight)
+    ms, _, kms = timed_lanes(lanes, idx, args.steps, args.warmup, (n_flag, n_match))
+    lanes.release()
+    ms_per_step = ms
     k_avg = sum(kms) / len(kms)
     alg = n_bytes + n_windows / 8            # the image read once, one flag bit per window
     achieved = alg / (k_avg * 1e-3) / 1e9
     value = n_bytes / (ms_per_step * 1e-3) / 1e9
     traffic, traffic_src = measured_traffic("logos", k_avg, FRAG_TRAFFIC_FILE, FRAG_KERNEL_SOURCES)
-    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, kernel {k_avg:.3f} ms")
+    log(f"[bench] {args.steps} steps, {inflight} in flight: {ms_per_step:.3f} ms/step, kernel {k_avg:.3f} ms; "
+        f"one at a time {serial} ms/step")
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -757,10 +848,17 @@ def run_fragments(args):
                                 f"({cfg.p_aligned:.0%} 4-byte aligned), djb2-64"),
                    "image_bytes": n_bytes, "n_windows": n_windows, "n_fragments": len(frags) // 64},
         "windows_per_s": round(n_windows / (ms_per_step * 1e-3)),
+        "steps_in_flight": inflight, "ms_per_step_one_in_flight": serial,
         "flagged": n_flag, "confirmed": n_match,
         "roofline": {"bound": "hbm", "kernel": "k_frag_scan (rolling signatures + filter/table probe)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel_ms": round(k_avg, 4),
+                     # the kernel alone: the same kernel in the steps run one at a time
+                     "kernel_ms_one_in_flight": (None if not serial_kms else
+                                                 round(sum(serial_kms) / len(serial_kms), 4)),
+                     "frac_one_in_flight": (None if not serial_kms else
+                                            round(alg / (sum(serial_kms) / len(serial_kms) * 1e-3) / 1e9
+                                                  / HBM_PEAK_GBS, 4)),
                      "traffic_bytes_per_launch": (None if traffic_src is None else
                                                   round(traffic_src["fetch_bytes_per_launch"] +
                                                         traffic_src["write_bytes_per_launch"])),
@@ -864,7 +962,9 @@ def run_report(args):
     served = run_served(args)
     mid_rate = mid["value"]
     head["mid"] = {"workload": mid["config"]["workload"], "value": mid["value"], "unit": "GB/s",
-                   "ms_per_step": mid["ms_per_step"], "hbm_frac_of_value": mid["hbm_frac_of_value"],
+                   "ms_per_step": mid["ms_per_step"], "steps_in_flight": mid["steps_in_flight"],
+                   "ms_per_step_one_in_flight": mid["ms_per_step_one_in_flight"],
+                   "hbm_frac_of_value": mid["hbm_frac_of_value"],
                    "kernel": mid["roofline"]["kernel"], "kernel_ms": mid["roofline"]["kernel_ms"],
                    "achieved": mid["roofline"]["achieved"], "frac": mid["roofline"]["frac"],
                    "traffic": mid["roofline"]["traffic"], "launch_shape": mid["config"]["launch_shape"],
@@ -933,6 +1033,12 @@ def main():
                          "(0: as many as fit)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--seed", type=int, default=None, help="plain: workload seed (default: the configuration's)")
+    ap.add_argument("--inflight", type=int, default=None,
+                    help="plain, fragments: steps in flight on as many streams (1: enqueue a step, wait for it; "
+                         "default 1 for plain, 2 for fragments)")
+    ap.add_argument("--overlap", choices=["auto", "on", "off"], default="auto",
+                    help="with --inflight 2 or more: whether a step's confirmation runs beside the next step's scan "
+                         "(auto: for fragments only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true", help="plain: skip the streaming-read ceiling")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 4 GiB device copy (counter scaling)")
