@@ -553,11 +553,15 @@ int server_submit_many(carve_server* s, const carve_image_desc* jobs, uint32_t n
 /* server_poll -- non-blocking progress: retire finished batches, admit queued
  * jobs into free lanes and launch them. Completed jobs are reported once,
  * in `done` (host, cap entries); *n_done receives how many were written (the
- * rest are reported by later calls). */
+ * rest are reported by later calls). A batch that fails to launch or to
+ * retire reports each of its jobs with the error as its `status` (the call
+ * returns CARVE_OK); the call's own error is EINVAL for a bad argument and
+ * EDEVICE when a lane's completion cannot be queried (its jobs stay running). */
 int server_poll(carve_server* s, carve_job_done* done, uint32_t cap, uint32_t* n_done);
 
 /* server_job_flags / server_job_matches -- results of a completed job
- * (host buffers; ETRUNC + full count when short, EINVAL if not completed). */
+ * (host buffers; ETRUNC + full count when short, EINVAL if not completed, the
+ * job's own error status if it failed: a failed job has no results). */
 int server_job_flags(carve_server* s, uint64_t job_id, uint64_t* out, uint64_t cap, uint64_t* n_out);
 int server_job_matches(carve_server* s, uint64_t job_id, carve_match* out, uint64_t cap, uint64_t* n_out);
 
@@ -568,6 +572,15 @@ int server_release(carve_server* s, uint64_t job_id);
  * order; stops at the first id that is not a reported job (EINVAL), the ids
  * before it released. */
 int server_release_many(carve_server* s, const uint64_t* job_ids, uint32_t n);
+
+/* server_fail_next_launches -- for tests of the failure path: the next n
+ * batch launches fail with CARVE_EDEVICE after all of their work (host-job
+ * copies, scan, confirmation, stage-out) has been enqueued. The server then
+ * does what it does for any launch error: it waits for the lane's stream,
+ * reports each of the batch's jobs with that status (server_poll) and frees
+ * their budget. Jobs that fail this way have no results; submit them again.
+ * EINVAL for a NULL server. */
+int server_fail_next_launches(carve_server* s, uint32_t n);
 
 int server_stats(const carve_server* s, carve_server_stats* out);
 void server_free(carve_server* s);  /* NULL is a no-op; waits for running batches */

@@ -40,7 +40,7 @@ EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_match
            "free_batch", "carve_last_error", "build_fragment_index", "scan_fragments", "ingest_create",
            "ingest_scan", "ingest_flagged_sectors", "ingest_matches", "ingest_stats", "ingest_free",
            "scan_image_noalloc", "read_ceiling_probe", "autotune_index", "confirm_enqueue_to",
-           "flagged_sectors_enqueue", "scan_counts")
+           "flagged_sectors_enqueue", "scan_counts", "server_fail_next_launches")
 
 
 class CarveError(RuntimeError):
@@ -199,6 +199,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.server_release_many.argtypes = [P, P, U32]
     lib.server_stats.restype = I32
     lib.server_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
+    lib.server_fail_next_launches.restype = I32
+    lib.server_fail_next_launches.argtypes = [P, U32]
     lib.server_free.restype = None
     lib.server_free.argtypes = [P]
     lib.confirm_enqueue.restype = I32
@@ -748,6 +750,11 @@ class Server:
         if self._keep:
             for j in ids.tolist():
                 self._keep.pop(j, None)
+
+    def fail_next_launches(self, n: int) -> None:
+        """Tests of the failure path: the next n batch launches fail after
+        enqueuing their work (their jobs are reported with CARVE_EDEVICE)."""
+        _check(load_library().server_fail_next_launches(self.handle, int(n)))
 
     def stats(self) -> dict:
         st = _ServerStats()

@@ -125,6 +125,7 @@ struct carve_server {
   std::vector<carve_image_desc> descs;
   std::vector<uint64_t> counts;
   uint32_t scan_per_cu = 1;   // scan blocks per CU that stay resident (the batch scan kernel's occupancy)
+  uint32_t fail_launches = 0;  // server_fail_next_launches: launches still to fail after enqueuing their work
   std::vector<std::unique_ptr<Results>> spare;   // recycled result buffers
 
   // Recycled buffers with room for `n` ids and records: the smallest spare
@@ -279,6 +280,10 @@ int launch(carve_server* s, Lane& ln) {
                              ln.res->matches.cap};
     rc = carve_batch_stage_out(ln.batch, s->p.confirm ? 1 : 0, &st, &ln.match_room);
   }
+  if (rc == CARVE_OK && s->fail_launches > 0) {   // a failure after every step above was enqueued
+    --s->fail_launches;
+    rc = carve_fail_msg(CARVE_EDEVICE, "server: injected launch failure (server_fail_next_launches)");
+  }
   if (rc == CARVE_OK && hipEventRecord(ln.done, ln.stream) != hipSuccess)
     rc = carve_fail_msg(CARVE_EDEVICE, "server: event record failed");
   if (rc != CARVE_OK) {   // the jobs fail with the batch's error
@@ -423,19 +428,20 @@ extern "C" int server_submit_many(carve_server* s, const carve_image_desc* jobs,
 
 extern "C" int server_poll(carve_server* s, carve_job_done* done, uint32_t cap, uint32_t* n_done) {
   if (!s || !n_done || (cap && !done)) return carve_fail_msg(CARVE_EINVAL, "server_poll: null argument");
+  // A batch that fails in retire() or launch() reports each of its jobs with
+  // the error as its status; only a failure that leaves jobs unreported (an
+  // event query that fails: the lane stays busy) is the call's own error.
   int rc = CARVE_OK;
   for (Lane& ln : s->lanes) {
     if (!ln.busy) continue;
     const hipError_t q = hipEventQuery(ln.done);
     if (q == hipErrorNotReady) continue;
-    const int r = q == hipSuccess ? retire(s, ln) : carve_fail_msg(CARVE_EDEVICE, "server_poll: event query failed");
-    if (r != CARVE_OK && rc == CARVE_OK) rc = r;
+    if (q == hipSuccess) (void)retire(s, ln);
+    else if (rc == CARVE_OK) rc = carve_fail_msg(CARVE_EDEVICE, "server_poll: event query failed");
   }
   for (Lane& ln : s->lanes) {
     if (s->queue.empty()) break;
-    if (ln.busy) continue;
-    const int r = launch(s, ln);
-    if (r != CARVE_OK && rc == CARVE_OK) rc = r;
+    if (!ln.busy) (void)launch(s, ln);
   }
   uint32_t k = 0;
   while (k < cap && !s->to_report.empty()) {
@@ -460,6 +466,7 @@ extern "C" int server_job_flags(carve_server* s, uint64_t job_id, uint64_t* out,
   if (!s || !n_out || (cap && !out)) return carve_fail_msg(CARVE_EINVAL, "server_job_flags: null argument");
   Job* j = finished(s, job_id);
   if (!j) return carve_fail_msg(CARVE_EINVAL, "server_job_flags: no such completed job");
+  if (j->status != CARVE_OK) return carve_fail_msg(j->status, "server_job_flags: the job failed (see its status)");
   *n_out = j->n_flags;
   const uint64_t k = j->n_flags < cap ? j->n_flags : cap;
   if (k) memcpy(out, j->res->ids.p + j->flag_at, k * 8);
@@ -470,6 +477,7 @@ extern "C" int server_job_matches(carve_server* s, uint64_t job_id, carve_match*
   if (!s || !n_out || (cap && !out)) return carve_fail_msg(CARVE_EINVAL, "server_job_matches: null argument");
   Job* j = finished(s, job_id);
   if (!j) return carve_fail_msg(CARVE_EINVAL, "server_job_matches: no such completed job");
+  if (j->status != CARVE_OK) return carve_fail_msg(j->status, "server_job_matches: the job failed (see its status)");
   *n_out = j->n_matches;
   const uint64_t k = j->n_matches < cap ? j->n_matches : cap;
   for (uint64_t i = 0; i < k; ++i) {
@@ -494,6 +502,12 @@ extern "C" int server_release_many(carve_server* s, const uint64_t* job_ids, uin
     const int rc = server_release(s, job_ids[i]);
     if (rc != CARVE_OK) return rc;
   }
+  return CARVE_OK;
+}
+
+extern "C" int server_fail_next_launches(carve_server* s, uint32_t n) {
+  if (!s) return carve_fail_msg(CARVE_EINVAL, "server_fail_next_launches: null server");
+  s->fail_launches = n;
   return CARVE_OK;
 }
 

@@ -209,3 +209,39 @@ def test_host_memory_jobs(pool):
         _check_job(srv, jid, done[jid], ox, idx, t, tau0, mode, given=src if w else None)
     assert sum(done[j][0] for j, w in zip(ids, where) if w) > 0     # host jobs found something
     srv.close()
+
+
+@pytest.mark.parametrize("n_streams", [1, 2])
+def test_failed_launch_reports_and_recovers(pool, n_streams):
+    """A batch launch that fails after its work was enqueued (forced from the
+    host with server_fail_next_launches; every kernel runs normally): the
+    server waits for the lane, reports the batch's jobs with the error, frees
+    their budget and keeps serving. The failed jobs have no results; submitted
+    again they complete, and every completed job equals the oracle."""
+    ms, idx, img, ox = pool
+    jobs = _jobs(img, 12, seed=40 + n_streams, max_bytes=4 << 20)
+    srv = carve.Server(idx, n_streams=n_streams)
+    srv.fail_next_launches(1)
+    ids = {srv.submit(t, tau0, mode): k for k, (t, tau0, mode) in enumerate(jobs)}
+    status, counts = {}, {}
+    while len(status) < len(ids):
+        for jid, nf, nc, st in srv.poll():
+            status[jid], counts[jid] = st, (nf, nc)
+    failed = [j for j, st in status.items() if st != carve.CARVE_OK]
+    assert failed and all(status[j] == carve.CARVE_EDEVICE for j in failed)
+    assert srv.stats()["in_flight_bytes"] == 0
+    for j in failed:
+        with pytest.raises(carve.CarveError) as e:
+            srv.flags(j)
+        assert e.value.code == carve.CARVE_EDEVICE
+    for j, k in ids.items():
+        if status[j] == carve.CARVE_OK:
+            t, tau0, mode = jobs[k]
+            _check_job(srv, j, counts[j], ox, idx, t, tau0, mode)
+    again = {srv.submit(*jobs[ids[j]]): ids[j] for j in failed}
+    done = _drain(srv, list(again))
+    for j, k in again.items():
+        t, tau0, mode = jobs[k]
+        _check_job(srv, j, done[j], ox, idx, t, tau0, mode)
+    assert srv.stats()["in_flight_bytes"] == 0
+    srv.close()
