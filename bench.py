@@ -327,9 +327,10 @@ def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
     # the whole path enqueued per step (scan, records into a device buffer, ids
     # copy), one wait for both counts; steps in flight on `inflight` streams
     inflight = args.inflight or 1
+    reuse = [sc]   # the first lane takes the scan object above (no extra scan before the warm-up)
 
     def lanes_of(depth):
-        return StepLanes(depth, lambda: carve.scan_image(idx, img.data),
+        return StepLanes(depth, lambda: reuse.pop() if reuse else carve.scan_image(idx, img.data),
                          lambda s: carve.scan_image(idx, img.data, scan=s), n_sectors, 16 * max(1, 2 * n_match + 1024),
                          overlap=args.overlap == "on")
 
