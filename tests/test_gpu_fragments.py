@@ -263,3 +263,56 @@ def test_fragment_signature_low_halves(bloom, zero_master):
             assert j not in flagged
         else:
             assert j in flagged and j not in set(m["disk_sector"].tolist())
+
+
+def test_two_steps_in_flight():
+    """Two scan objects on two streams sharing one index, as bench.py runs the
+    fragment step: step i runs wholly on stream i % 2 (scan, records into a
+    device buffer, ids copy, count readback), its scan ordered after step
+    i-1's scan by an event, so step i-1's confirmation runs beside step i's
+    scan; the host reads step i-1's counts after enqueuing step i. Each step
+    scans other bytes; ids and records equal the oracle's for that step."""
+    rng = random.Random(21)
+    files = _files(rng, 200, 256, 8192)
+    frag_data, offsets = oracle.pack_fragment_files(files)
+    idx = carve.build_fragment_index(dev_bytes(frag_data.tobytes()), offsets)
+    images, expect = [], []
+    for k in range(6):
+        n = (2 << 20) + 4 * k + (k % 3)                      # ragged lengths
+        img = bytearray(np.random.default_rng(100 + k).integers(0, 256, size=n, dtype=np.uint8).tobytes())
+        o = 0
+        while o < n - 10000:
+            data = files[rng.randrange(len(files))]
+            o += rng.randrange(100, 9000)
+            o -= o % 4 if rng.random() < 0.7 else 0
+            img[o:o + len(data)] = data
+            o += len(data)
+        images.append(dev_bytes(bytes(img)))
+        expect.append(_oracle(frag_data, offsets, bytes(img)))
+    most_f = max(len(f) for f, _ in expect)
+    most_m = max(len(m) for _, m in expect)
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    scans, events = [None, None], [torch.cuda.Event(), torch.cuda.Event()]
+    ids = [torch.full((most_f + 7,), -1, dtype=torch.int64, device="cuda") for _ in range(2)]
+    rec = [torch.zeros(16 * (most_m + 7), dtype=torch.uint8, device="cuda") for _ in range(2)]
+
+    def check(i):
+        k = i % 2
+        wf, wm = expect[i]
+        assert carve.scan_counts(scans[k]) == (len(wf), len(wm))
+        assert np.array_equal(ids[k][: len(wf)].cpu().numpy().astype(np.uint64), wf)
+        got = np.frombuffer(rec[k].cpu().numpy().tobytes(), dtype=carve.MATCH_DTYPE)[: len(wm)]
+        assert_same_matches(got, wm)
+
+    for i in range(len(images)):
+        k = i % 2
+        with torch.cuda.stream(streams[k]):
+            if i > 0:
+                streams[k].wait_event(events[1 - k])
+            scans[k] = carve.scan_fragments(idx, images[i], scan=scans[k])
+            events[k].record(streams[k])
+            carve.confirm_enqueue(idx, scans[k], rec[k])
+            carve.flagged_sectors_enqueue(scans[k], ids[k])
+        if i > 0:
+            check(i - 1)
+    check(len(images) - 1)
