@@ -198,10 +198,11 @@ class StepLanes:
     readback run beside step i's scan). depth 1 is the plain loop: enqueue a
     step, wait for its counts."""
 
-    def __init__(self, depth, first_scan, scan_again, ids_len, rec_bytes, overlap=False):
+    def __init__(self, index, depth, first_scan, scan_again, ids_len, rec_bytes, overlap=False):
         import torch
         from paper_0901_1307_amd import carve
-        self.carve, self.depth, self.scan_again, self.overlap = carve, depth, scan_again, overlap
+        self.carve, self.index, self.depth = carve, index, depth
+        self.scan_again, self.overlap = scan_again, overlap
         self.lanes = []
         for k in range(depth):
             s = torch.cuda.current_stream() if k == 0 else torch.cuda.Stream()
@@ -221,14 +222,13 @@ class StepLanes:
             self.scan_again(lane["scan"])
             if self.overlap:
                 lane["event"].record(lane["stream"])
-            self.carve.confirm_enqueue(self.scan_index, lane["scan"], lane["rec"])
+            self.carve.confirm_enqueue(self.index, lane["scan"], lane["rec"])
             self.carve.flagged_sectors_enqueue(lane["scan"], lane["ids"])
             if not self.overlap:
                 lane["event"].record(lane["stream"])
 
-    def run(self, index, n, check):
+    def run(self, n, check):
         """n steps; check(counts) on each step's (n_flagged, n_confirmed)."""
-        self.scan_index = index
         for i in range(n):
             self._enqueue(i)
             if i >= self.depth - 1:
@@ -252,7 +252,7 @@ class StepLanes:
         self.lanes = []
 
 
-def timed_lanes(lanes, index, steps, warmup, expect):
+def timed_lanes(lanes, steps, warmup, expect):
     """warmup, then `steps` timed steps between HIP events on the default
     stream (the host has waited for every step's counts before the closing
     event); returns (ms_per_step, wall ms per step, kernel ms of every timed
@@ -262,13 +262,13 @@ def timed_lanes(lanes, index, steps, warmup, expect):
     def check(c):
         assert c == expect, (c, expect)
 
-    lanes.run(index, warmup, check)
+    lanes.run(warmup, check)
     lanes.set_timing(True)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     ev0.record()
-    lanes.run(index, steps, check)
+    lanes.run(steps, check)
     ev1.record()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - wall0) * 1e3 / steps
@@ -330,18 +330,18 @@ def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
     reuse = [sc]   # the first lane takes the scan object above (no extra scan before the warm-up)
 
     def lanes_of(depth):
-        return StepLanes(depth, lambda: reuse.pop() if reuse else carve.scan_image(idx, img.data),
+        return StepLanes(idx, depth, lambda: reuse.pop() if reuse else carve.scan_image(idx, img.data),
                          lambda s: carve.scan_image(idx, img.data, scan=s), n_sectors, 16 * max(1, 2 * n_match + 1024),
                          overlap=args.overlap == "on")
 
     serial = None
     if inflight > 1:   # the same steps one at a time, for comparison
         lanes = lanes_of(1)
-        ms1, _, _ = timed_lanes(lanes, idx, args.steps, args.warmup, (n_flag, n_match))
+        ms1, _, _ = timed_lanes(lanes, args.steps, args.warmup, (n_flag, n_match))
         lanes.release()
         serial = round(ms1, 4)
     lanes = lanes_of(inflight)
-    ms_per_step, wall, kernel_ms = timed_lanes(lanes, idx, args.steps, args.warmup, (n_flag, n_match))
+    ms_per_step, wall, kernel_ms = timed_lanes(lanes, args.steps, args.warmup, (n_flag, n_match))
     lanes.release()
     log(f"[bench] {args.steps} steps, {inflight} in flight: {ms_per_step:.3f} ms/step (event), "
         f"wall {wall:.3f} ms/step; one at a time {serial} ms/step")
@@ -818,18 +818,18 @@ def run_fragments(args):
     inflight = args.inflight or 2
 
     def lanes_of(depth):
-        return StepLanes(depth, lambda: carve.scan_fragments(idx, img),
+        return StepLanes(idx, depth, lambda: carve.scan_fragments(idx, img),
                          lambda s: carve.scan_fragments(idx, img, scan=s), n_flag + 1024, 16 * (n_match + 1024),
                          overlap=args.overlap != "off")
 
     serial, serial_kms = None, None
     if inflight > 1:   # the same steps one at a time, for comparison
         lanes = lanes_of(1)
-        ms1, _, serial_kms = timed_lanes(lanes, idx, args.steps, args.warmup, (n_flag, n_match))
+        ms1, _, serial_kms = timed_lanes(lanes, args.steps, args.warmup, (n_flag, n_match))
         lanes.release()
         serial = round(ms1, 4)
     lanes = lanes_of(inflight)
-    ms, _, kms = timed_lanes(lanes, idx, args.steps, args.warmup, (n_flag, n_match))
+    ms, _, kms = timed_lanes(lanes, args.steps, args.warmup, (n_flag, n_match))
     lanes.release()
     ms_per_step = ms
     k_avg = sum(kms) / len(kms)
