@@ -20,6 +20,9 @@ constexpr uint32_t kWaveWindows = kWave * kLaneWindows;      // 1024 windows = 4
 constexpr uint32_t kFragRowDw = kLaneWindows;                // a lane's own 64 bytes, in dwords
 constexpr uint32_t kLdsFilterMaxWords = 40960;               // 160 KiB, all of a CU's LDS: the first filter
 constexpr int kDppWaveShl1 = 0x130;                          // DPP control: lane i takes lane i + 1's value
+// Buffer descriptor word 3 for raw (unformatted, unswizzled) dword access on
+// gfx9-family chips: data format 32 in bits 15-18 (value 4), the rest 0.
+constexpr int kRawBufferFlags = 0x00020000;
 
 // The two filters of a fragment index, both of 32-bit words, are placed from
 // a 32-bit key: k = H mod 2^32, the low half of the window's data part H (its
@@ -196,13 +199,23 @@ struct TaskWords {
   u32x4 v[kFragRowDw / 4];
   uint32_t x;
 };
+// The inside task's words come by buffer loads from a descriptor based at
+// the task (scalar base, 32-bit lane offsets: less address arithmetic than
+// 64-bit global addresses), streaming and system-scoped (cache policy nt, sc1):
+// on the 2 GiB logos workload 1.187 vs 1.211 ms for non-temporal global loads,
+// and 74 MB less fetched per launch. The image is only read, so the policy
+// affects speed alone.
+constexpr int kImagePolicy = 2 | 16;   // nt | sc1
 __device__ __forceinline__ void load_task_inside(const uint32_t* __restrict__ image, uint64_t t, uint32_t l,
                                                  TaskWords& T) {
-  const uint64_t dw0 = t * kWaveWindows;
-  const uint32_t* src = image + dw0 + (uint64_t)l * kFragRowDw;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(image + t * kWaveWindows), (short)0, 0x7FFFFFFF, kRawBufferFlags);
 #pragma unroll
-  for (uint32_t q = 0; q < kFragRowDw / 4; ++q) T.v[q] = __builtin_nontemporal_load((const u32x4*)(src + 4 * q));
-  T.x = __builtin_nontemporal_load(image + dw0 + kWaveWindows + (l % kFragRowDw));
+  for (uint32_t q = 0; q < kFragRowDw / 4; ++q) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((l * kFragRowDw + 4 * q) * 4), 0, kImagePolicy);
+    T.v[q] = u32x4{v[0], v[1], v[2], v[3]};
+  }
+  T.x = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)((kWaveWindows + (l % kFragRowDw)) * 4), 0, kImagePolicy);
 }
 __device__ __forceinline__ void load_task_clamped(const uint32_t* __restrict__ image, uint64_t n_dwords, uint64_t t,
                                                   uint32_t l, TaskWords& T) {
