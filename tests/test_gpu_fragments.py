@@ -44,11 +44,13 @@ def _files(rng, n, lo=64, hi=4096):
     return [bytes(rng.getrandbits(8) for _ in range(rng.randrange(lo, hi))) for _ in range(n)]
 
 
-@pytest.mark.parametrize("n_bytes", [0, 63, 64, 67, 68, 100, 4096, 8191, 8192 + 60, 8192 + 64, 8192 + 67,
-                                     3 * 8192 + 1000, 5 * 8192])
+@pytest.mark.parametrize("n_bytes", [0, 63, 64, 67, 68, 100, 124, 128, 4096, 4096 + 60, 4096 + 64, 8191,
+                                     8192 + 59, 8192 + 60, 8192 + 64, 8192 + 67, 3 * 8192 + 1000, 5 * 8192])
 def test_fragment_sizes(n_bytes):
     """Every window up to the last one (4j + 64 <= n), across whole and partial
-    wave tasks (8 KiB of windows each), with a fragment planted at the very end."""
+    lanes (16 windows each) and wave tasks (1024 windows, 4 KiB of image each:
+    4096 + 60 bytes is exactly one task, 4096 + 64 one window more), with a
+    fragment planted at the very end."""
     rng = random.Random(n_bytes)
     files = _files(rng, 6)
     frag_data, offsets = oracle.pack_fragment_files(files)
