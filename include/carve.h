@@ -242,6 +242,18 @@ int flagged_sectors_enqueue(carve_scan* sc, uint64_t* out, uint64_t cap);
  * Errors: EINVAL (null argument), EDEVICE.
  */
 int scan_counts(carve_scan* sc, uint64_t* n_flagged, uint64_t* n_confirmed);
+
+/*
+ * scan_wait_kernel -- makes `stream` (a hipStream_t, or NULL for the null
+ * stream) wait until the latest scan kernel of `sc` has finished, not the
+ * compaction and confirmation enqueued after it on the scan's stream: work
+ * enqueued on `stream` afterwards (another scan object's scan, say) may then
+ * run beside them. Nothing to wait for before the first scan. For keeping
+ * several steps in flight on several streams (Section 3.2's pipeline of
+ * scans, with the host never waiting between them).
+ * Errors: EINVAL (null sc), EDEVICE.
+ */
+int scan_wait_kernel(carve_scan* sc, void* stream);
 #define CARVE_NOT_CONFIRMED UINT64_MAX
 
 /*

@@ -40,7 +40,7 @@ EXPORTS = ("build_master_index", "scan_image", "flagged_sectors", "confirm_match
            "free_batch", "carve_last_error", "build_fragment_index", "scan_fragments", "ingest_create",
            "ingest_scan", "ingest_flagged_sectors", "ingest_matches", "ingest_stats", "ingest_free",
            "scan_image_noalloc", "read_ceiling_probe", "autotune_index", "confirm_enqueue_to",
-           "flagged_sectors_enqueue", "scan_counts", "server_fail_next_launches")
+           "flagged_sectors_enqueue", "scan_counts", "server_fail_next_launches", "scan_wait_kernel")
 
 
 class CarveError(RuntimeError):
@@ -201,6 +201,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.server_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
     lib.server_fail_next_launches.restype = I32
     lib.server_fail_next_launches.argtypes = [P, U32]
+    lib.scan_wait_kernel.restype = I32
+    lib.scan_wait_kernel.argtypes = [P, P]
     lib.server_free.restype = None
     lib.server_free.argtypes = [P]
     lib.confirm_enqueue.restype = I32
@@ -864,6 +866,12 @@ def flagged_sectors_enqueue(scan: Scan, out: torch.Tensor) -> None:
     _check(load_library().flagged_sectors_enqueue(scan.handle, out.data_ptr() if out.numel() else None,
                                                   out.numel()))
     scan.pending = [t for t in scan.pending if t is not out] + [out]
+
+
+def scan_wait_kernel(scan, stream=None) -> None:
+    """Make `stream` (default: torch's current stream) wait for the scan
+    object's latest scan kernel only, not its compaction and confirmation."""
+    _check(load_library().scan_wait_kernel(scan.handle, _stream_ptr(stream)))
 
 
 def scan_counts(scan) -> tuple:

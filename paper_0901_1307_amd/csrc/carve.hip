@@ -1068,6 +1068,7 @@ struct carve_scan {
   // timing: launch k brackets its scan kernel with ev[2 (k mod kTimedRing)]
   // and ev[2 (k mod kTimedRing) + 1]; n_timed launches so far
   std::vector<hipEvent_t> ev;
+  hipEvent_t kernel_done = nullptr;   // recorded after each scan kernel, before the compaction (scan_wait_kernel)
   uint64_t n_timed = 0;
   bool timing = false, timed = false;
 };
@@ -1191,6 +1192,7 @@ int launch_scan(carve_scan* sc, const Src& src) {
     ++sc->n_timed;
     sc->timed = true;
   }
+  HIP_TRY(hipEventRecord(sc->kernel_done, s));
   const uint64_t nb = cdiv(n_words, kItemsPerBlock);
   uint64_t* sums = sc->ws.as<uint64_t>();
   uint64_t* offs = sums + nb;
@@ -1237,6 +1239,7 @@ int reserve_scan(carve_scan* sc) {
     sc->ev.assign(2 * kTimedRing, nullptr);
     for (hipEvent_t& e : sc->ev) HIP_TRY(hipEventCreate(&e));
   }
+  if (!sc->kernel_done) HIP_TRY(hipEventCreateWithFlags(&sc->kernel_done, hipEventDisableTiming));
   return CARVE_OK;
 }
 
@@ -1772,6 +1775,7 @@ extern "C" void free_scan(carve_scan* sc) {
   sc->h_small.release();
   sc->h_img_off.release();
   for (hipEvent_t e : sc->ev) (void)hipEventDestroy(e);
+  if (sc->kernel_done) (void)hipEventDestroy(sc->kernel_done);
   if (sc->batch) delete static_cast<carve_batch*>(sc);
   else delete sc;
 }
@@ -2067,6 +2071,13 @@ extern "C" int flagged_sectors_enqueue(carve_scan* sc, uint64_t* out, uint64_t c
   if (cap && !is_device_memory(out)) return fail(CARVE_EINVAL, "flagged_sectors_enqueue: out is not device memory");
   if (!cap || !sc->n_tiles) return CARVE_OK;
   return enqueue_id_copy(sc, out, cap);
+}
+
+extern "C" int scan_wait_kernel(carve_scan* sc, void* stream) {
+  if (!sc) return fail(CARVE_EINVAL, "scan_wait_kernel: null scan");
+  if (!sc->kernel_done) return CARVE_OK;   // no scan kernel enqueued yet
+  HIP_TRY(hipStreamWaitEvent((hipStream_t)stream, sc->kernel_done, 0));
+  return CARVE_OK;
 }
 
 extern "C" int scan_counts(carve_scan* sc, uint64_t* n_flagged, uint64_t* n_confirmed) {

@@ -267,13 +267,16 @@ def test_fragment_signature_low_halves(bloom, zero_master):
             assert j in flagged and j not in set(m["disk_sector"].tolist())
 
 
-def test_two_steps_in_flight():
+@pytest.mark.parametrize("after", ["scan", "kernel"])
+def test_two_steps_in_flight(after):
     """Two scan objects on two streams sharing one index, as bench.py runs the
     fragment step: step i runs wholly on stream i % 2 (scan, records into a
     device buffer, ids copy, count readback), its scan ordered after step
-    i-1's scan by an event, so step i-1's confirmation runs beside step i's
-    scan; the host reads step i-1's counts after enqueuing step i. Each step
-    scans other bytes; ids and records equal the oracle's for that step."""
+    i-1's scan, either by an event after scan_fragments (its kernel and
+    compaction) or by scan_wait_kernel (its kernel alone), so step i-1's
+    confirmation (and compaction) run beside step i's scan; the host reads
+    step i-1's counts after enqueuing step i. Each step scans other bytes;
+    ids and records equal the oracle's for that step."""
     rng = random.Random(21)
     files = _files(rng, 200, 256, 8192)
     frag_data, offsets = oracle.pack_fragment_files(files)
@@ -310,7 +313,10 @@ def test_two_steps_in_flight():
         k = i % 2
         with torch.cuda.stream(streams[k]):
             if i > 0:
-                streams[k].wait_event(events[1 - k])
+                if after == "kernel":
+                    carve.scan_wait_kernel(scans[1 - k], streams[k])
+                else:
+                    streams[k].wait_event(events[1 - k])
             scans[k] = carve.scan_fragments(idx, images[i], scan=scans[k])
             events[k].record(streams[k])
             carve.confirm_enqueue(idx, scans[k], rec[k])
