@@ -469,3 +469,43 @@ def test_host_memory_image_rejected(tiny_gpu):
         rc = lib.scan_image(idx.handle, t.data_ptr(), t.numel(), 0, 0, None, carve.ctypes.byref(h))
         assert rc == carve.CARVE_EINVAL and not h.value
         assert b"device memory" in lib.carve_last_error()
+
+
+def test_plain_steps_in_flight(tiny_gpu):
+    """Two scan objects on two streams over one index, each step's scan
+    waiting only for the previous step's scan kernel (scan_wait_kernel) while
+    that step's compaction, confirmation and ids copy run on its own stream;
+    steps alternate tau0 and the image prefix, so consecutive steps differ.
+    Every step's ids and records equal the oracle's."""
+    cfg, ms, img, idx = tiny_gpu
+    host = img.data.cpu().numpy()
+    masters = ms.sectors.cpu().numpy()
+    plan = [(0, img.data.numel()), (5, img.data.numel() - 512 * 77), (3, img.data.numel() // 1024 * 512 + 512 * 3),
+            (0, img.data.numel() - 512), (7, img.data.numel())]
+    expect = [oracle_flags_and_matches(masters, ms.file_offsets, host[:n], tau0) for tau0, n in plan]
+    most_f = max(len(f) for f, _ in expect)
+    most_m = max(len(m) for _, m in expect)
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    scans = [None, None]
+    ids = [torch.full((most_f + 5,), -1, dtype=torch.int64, device="cuda") for _ in range(2)]
+    rec = [torch.zeros(16 * (most_m + 5), dtype=torch.uint8, device="cuda") for _ in range(2)]
+
+    def check(i):
+        k = i % 2
+        wf, wm = expect[i]
+        assert carve.scan_counts(scans[k]) == (len(wf), len(wm))
+        assert np.array_equal(ids[k][: len(wf)].cpu().numpy().astype(np.uint64), wf)
+        got = np.frombuffer(rec[k].cpu().numpy().tobytes(), dtype=carve.MATCH_DTYPE)[: len(wm)]
+        assert_same_matches(got, wm)
+
+    for i, (tau0, n) in enumerate(plan):
+        k = i % 2
+        with torch.cuda.stream(streams[k]):
+            if i > 0:
+                carve.scan_wait_kernel(scans[1 - k], streams[k])
+            scans[k] = carve.scan_image(idx, img.data[:n], tau0=tau0, scan=scans[k])
+            carve.confirm_enqueue(idx, scans[k], rec[k])
+            carve.flagged_sectors_enqueue(scans[k], ids[k])
+        if i > 0:
+            check(i - 1)
+    check(len(plan) - 1)
