@@ -14,7 +14,9 @@ kernel, scan_wait_kernel), and each step's compaction, confirmation, ids copy
 and readback run beside the next step's scan; its line also reports the same
 steps one at a time (`ms_per_step_one_in_flight`). The plain workloads run
 one step at a time by default (--inflight 2 --overlap kernel is 0.4-2%
-faster, measured, but its kernel shares the chip with the confirmation). The
+faster, measured, but its kernel shares the chip with the confirmation); the
+report's `mid` object also times the same steps two in flight
+(`in_flight_comparison`). The
 master index is built once, before timing, and the launch shape is picked by
 the library's autotuner on a tuning sample (an image of the same recipe that
 is not the timed one).
@@ -284,8 +286,10 @@ def timed_lanes(lanes, steps, warmup, expect):
     return ev0.elapsed_time(ev1) / steps, wall, kms
 
 
-def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
-    """One image: K timed steps of scan + ids + confirmation."""
+def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool, also_in_flight: int = 0) -> dict:
+    """One image: K timed steps of scan + ids + confirmation. also_in_flight > 1:
+    the same steps timed again with that many in flight (each step's scan after
+    the previous scan kernel), reported beside the line's own figures."""
     import torch
 
     import synth
@@ -351,6 +355,17 @@ def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
     lanes.release()
     log(f"[bench] {args.steps} steps, {inflight} in flight: {ms_per_step:.3f} ms/step (event), "
         f"wall {wall:.3f} ms/step; one at a time {serial} ms/step")
+    extra = None
+    if also_in_flight > 1 and also_in_flight != inflight:
+        lanes = StepLanes(idx, also_in_flight, lambda: carve.scan_image(idx, img.data),
+                          lambda s: carve.scan_image(idx, img.data, scan=s), n_sectors,
+                          16 * max(1, 2 * n_match + 1024), overlap="kernel")
+        ms_x, _, kms_x = timed_lanes(lanes, args.steps, args.warmup, (n_flag, n_match))
+        lanes.release()
+        extra = {"steps_in_flight": also_in_flight, "ms_per_step": round(ms_x, 4),
+                 "value": round(image_bytes / (ms_x * 1e-3) / 1e9, 2),
+                 "kernel_ms": round(sum(kms_x) / len(kms_x), 4) if kms_x else None}
+        log(f"[bench] the same steps, {also_in_flight} in flight: {ms_x:.3f} ms/step")
     # apart from the timed steps: the same step with ids and records copied to
     # pinned host memory (end to end including device-to-host)
     flag_h = torch.empty(n_flag + 1024, dtype=torch.int64, pin_memory=True)
@@ -404,6 +419,7 @@ def run_plain(args, config: str, with_cpu: bool, with_ceiling: bool) -> dict:
         "sectors_per_s": round(n_sectors / (ms_per_step * 1e-3)),
         "steps_in_flight": inflight,
         "ms_per_step_one_in_flight": serial,
+        "in_flight_comparison": extra,
         "ms_per_step_host_outputs": round(ms_host, 4),
         "hbm_frac_of_value": round(value / HBM_PEAK_GBS, 4),
         "flagged": n_flag,
@@ -964,13 +980,14 @@ def run_report(args):
     mid, batched and served workloads as sub-objects."""
     t_start = time.perf_counter()
     head = run_plain(args, "large", with_cpu=not args.no_cpu_baseline, with_ceiling=True)
-    mid = run_plain(args, "mid", with_cpu=False, with_ceiling=False)
+    mid = run_plain(args, "mid", with_cpu=False, with_ceiling=False, also_in_flight=2)
     batched = run_batched(args)
     served = run_served(args)
     mid_rate = mid["value"]
     head["mid"] = {"workload": mid["config"]["workload"], "value": mid["value"], "unit": "GB/s",
                    "ms_per_step": mid["ms_per_step"], "steps_in_flight": mid["steps_in_flight"],
                    "ms_per_step_one_in_flight": mid["ms_per_step_one_in_flight"],
+                   "in_flight_comparison": mid["in_flight_comparison"],
                    "hbm_frac_of_value": mid["hbm_frac_of_value"],
                    "kernel": mid["roofline"]["kernel"], "kernel_ms": mid["roofline"]["kernel_ms"],
                    "achieved": mid["roofline"]["achieved"], "frac": mid["roofline"]["frac"],
@@ -1007,7 +1024,7 @@ def run_report(args):
     return head
 
 
-def main():
+def arg_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -1050,7 +1067,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true", help="plain: skip the streaming-read ceiling")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 4 GiB device copy (counter scaling)")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = arg_parser().parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the scan has no cross-GPU step, and only --gpus 1 is supported "
               "(sharding is described in DESIGN.md)", file=sys.stderr)

@@ -248,9 +248,12 @@ int scan_counts(carve_scan* sc, uint64_t* n_flagged, uint64_t* n_confirmed);
  * stream) wait until the latest scan kernel of `sc` has finished, not the
  * compaction and confirmation enqueued after it on the scan's stream: work
  * enqueued on `stream` afterwards (another scan object's scan, say) may then
- * run beside them. Nothing to wait for before the first scan. For keeping
- * several steps in flight on several streams (Section 3.2's pipeline of
- * scans, with the host never waiting between them).
+ * run beside them. Nothing to wait for before the first scan. An ordering
+ * point only: no results are handed over (the scan's outputs are read after
+ * its compaction, on its own stream), so the wait carries no system-scope
+ * cache fence. For keeping several steps in flight on several streams
+ * (Section 3.2's pipeline of scans, with the host never waiting between
+ * them).
  * Errors: EINVAL (null sc), EDEVICE.
  */
 int scan_wait_kernel(carve_scan* sc, void* stream);

@@ -1217,6 +1217,15 @@ int launch_scan(carve_scan* sc, const Src& src) {
   return CARVE_OK;
 }
 
+// The events around timed scan kernels. They carry timestamps only (read
+// after the host has waited for the stream), so they skip the system-scope
+// fence that writes back and invalidates the caches at every record.
+int create_timing_ring(carve_scan* sc) {
+  sc->ev.assign(2 * kTimedRing, nullptr);
+  for (hipEvent_t& e : sc->ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+  return CARVE_OK;
+}
+
 // Buffers for a tile space of n_tiles tiles.
 int reserve_scan(carve_scan* sc) {
   const uint64_t n_words = sc->n_tiles ? sc->n_tiles : 1;
@@ -1235,11 +1244,12 @@ int reserve_scan(carve_scan* sc) {
     CARVE_TRY(sc->img_of.reserve(n_words * kTileSectors * 4));
     CARVE_TRY(sc->img_off.reserve((sc->n_images + 1) * 8));
   }
-  if (sc->timing && sc->ev.empty()) {
-    sc->ev.assign(2 * kTimedRing, nullptr);
-    for (hipEvent_t& e : sc->ev) HIP_TRY(hipEventCreate(&e));
-  }
-  if (!sc->kernel_done) HIP_TRY(hipEventCreateWithFlags(&sc->kernel_done, hipEventDisableTiming));
+  if (sc->timing && sc->ev.empty()) CARVE_TRY(create_timing_ring(sc));
+  // an ordering point for other streams only (no host read, no data handed
+  // over), so without the system-scope fence that writes back and invalidates
+  // the caches at every record
+  if (!sc->kernel_done)
+    HIP_TRY(hipEventCreateWithFlags(&sc->kernel_done, hipEventDisableTiming | hipEventDisableSystemFence));
   return CARVE_OK;
 }
 
@@ -1998,10 +2008,7 @@ CARVE_HIDDEN uint32_t carve_batch_scan_blocks_per_cu(void) {
 
 extern "C" int scan_set_timing(carve_scan* sc, int enable) {
   if (!sc) return fail(CARVE_EINVAL, "scan_set_timing: null scan");
-  if (enable && sc->ev.empty()) {
-    sc->ev.assign(2 * kTimedRing, nullptr);
-    for (hipEvent_t& e : sc->ev) HIP_TRY(hipEventCreate(&e));
-  }
+  if (enable && sc->ev.empty()) CARVE_TRY(create_timing_ring(sc));
   if (enable && !sc->timing) {   // a new timed series
     sc->n_timed = 0;
     sc->timed = false;
