@@ -198,7 +198,7 @@ def test_fragment_workload_scaled():
 
 def test_fragment_workload_full():
     """The benchmark's workload at its full size (2 GiB image, 346,577
-    fragments of 2,000 files, the 128 KiB LDS filter and the 2 MiB Bloom
+    fragments of 2,000 files, the 160 KiB LDS filter and the 2 MiB Bloom
     filter), scanned as bench.py times it: every window's flag and every
     confirmed record equal the oracle's over the whole image."""
     import synth
@@ -214,6 +214,32 @@ def test_fragment_workload_full():
     wf = ox.flag_windows(host, threads=oracle.default_threads())
     wm = ox.confirm_windows(host, wf)
     assert len(wf) > 3_000_000
+    assert np.array_equal(f, wf)
+    assert_same_matches(m, wm)
+
+
+def test_fragment_workload_chunk_boundary():
+    """The benchmark's recipe on an image of 2^30 + 132 bytes: 268,435,474
+    windows, so the compaction's hit words make 4,097 chunks of 1,024 and the
+    one-block scan of their sums takes a second pass of a single sum (passes
+    of 4,096). Every flag and record against the oracle."""
+    import dataclasses
+
+    import synth
+    cfg = dataclasses.replace(synth.FRAGMENT_CONFIGS["logos"], image_bytes=(1 << 30) + 132, n_embedded=12500)
+    n_words = -(-((cfg.image_bytes - 64) // 4 + 1) // 64)   # hit words of 64 windows
+    assert -(-n_words // 1024) == 4097
+    files = synth.fragment_files(cfg, device="cuda")
+    frags, offsets = carve.pack_fragment_files(files)
+    img = synth.fragment_image(cfg, files, device="cuda")
+    idx = carve.build_fragment_index(frags, offsets)
+    f, m, _ = _gpu(idx, img)
+    host = img.cpu().numpy()
+    del img
+    ox = oracle.FragmentIndex(frags.cpu().numpy(), offsets, threads=oracle.default_threads())
+    wf = ox.flag_windows(host, threads=oracle.default_threads())
+    wm = ox.confirm_windows(host, wf)
+    assert len(wf) > 1_000_000
     assert np.array_equal(f, wf)
     assert_same_matches(m, wm)
 
