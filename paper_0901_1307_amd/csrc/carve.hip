@@ -54,7 +54,8 @@ using namespace carve;
 constexpr uint64_t kNoAllocMaxSectors = 1ull << 27;                        // 64 GiB of image
 constexpr uint64_t kNoAllocMaxWords = kNoAllocMaxSectors / kTileSectors;    // 2^21 hit words
 constexpr uint64_t kNoAllocMaxChunks = kNoAllocMaxWords / 1024;             // compaction chunks of 1024 words
-constexpr uint64_t kScratchWords = 2 * kNoAllocMaxWords + 2 * kNoAllocMaxChunks;   // 32 MiB + 32 KiB
+constexpr uint64_t kNoAllocCounters = 256;   // the position-split scan's work-sharing counters
+constexpr uint64_t kScratchWords = 2 * kNoAllocMaxWords + 2 * kNoAllocMaxChunks + kNoAllocCounters;   // 32 MiB + 34 KiB
 static __device__ __align__(256) uint64_t scratch[kScratchWords];
 
 namespace {
@@ -63,6 +64,8 @@ constexpr int kBlockThreads = 256;
 constexpr int kItemsPerThread = 4;
 constexpr int kItemsPerBlock = kBlockThreads * kItemsPerThread;   // 1024
 static_assert(kNoAllocMaxChunks * kItemsPerBlock == kNoAllocMaxWords, "scratch holds every chunk sum");
+static_assert(kNoAllocCounters == carve::kTauCounters, "scratch holds the split scan's counters");
+static_assert((2 * kNoAllocMaxWords + 2 * kNoAllocMaxChunks) % carve::kCtrStride == 0, "counters on 256-byte lines");
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;   // master whose key could not be placed
 
@@ -969,43 +972,56 @@ int launch_k_scan(uint32_t kind, const Src& src, uint64_t n_tiles, uint32_t chun
 // size is a multiple of 8, one eighth of it per cluster position.
 template <int kSig, int kLayout, bool kSlots>
 void launch_k_scan_tau_as(const ImageDesc& d, uint64_t words_per_pos, uint32_t chunk, uint32_t per_cu_cap,
-                          const IndexView& ix, uint64_t wt, uint64_t* tau_words, uint32_t* hit_slot, hipStream_t s) {
+                          const IndexView& ix, uint64_t wt, uint64_t* tau_words, uint32_t* hit_slot, uint64_t* ctr,
+                          hipStream_t s) {
   const uint64_t want = kPositions * cdiv(cdiv(words_per_pos, chunk), kScanWaves);
   int grid = resident_grid(k_scan_tau<kSig, kLayout, kSlots>, kScanThreads, want, per_cu_cap);
   grid = grid < (int)kPositions ? (int)kPositions : grid - grid % (int)kPositions;
+  k_fill_u64<<<1, 256, 0, s>>>(ctr, kTauCounters, 0);   // the work-sharing counters start at zero
   k_scan_tau<kSig, kLayout, kSlots><<<grid, kScanThreads, 0, s>>>(d.base, d.n_sectors, d.tau0, words_per_pos, chunk,
-                                                                   ix, wt, tau_words, hit_slot);
+                                                                   ix, wt, tau_words, hit_slot,
+                                                                   (unsigned int*)ctr);
 }
 
 template <int kSig, bool kSlots>
 void launch_k_scan_tau_sig(uint32_t layout, const ImageDesc& d, uint64_t words_per_pos, uint32_t chunk,
                            uint32_t per_cu_cap, const IndexView& ix, uint64_t wt, uint64_t* tau_words,
-                           uint32_t* hit_slot, hipStream_t s) {
+                           uint32_t* hit_slot, uint64_t* ctr, hipStream_t s) {
   if (layout == CARVE_LAYOUT_LINEAR)
     return launch_k_scan_tau_as<kSig, kLayoutLinear, kSlots>(d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
-                                                              hit_slot, s);
+                                                              hit_slot, ctr, s);
   if (layout == CARVE_LAYOUT_SORTED)
     return launch_k_scan_tau_as<kSig, kLayoutSorted, kSlots>(d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
-                                                              hit_slot, s);
+                                                              hit_slot, ctr, s);
   launch_k_scan_tau_as<kSig, kLayoutBucketed, kSlots>(d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
-                                                       hit_slot, s);
+                                                       hit_slot, ctr, s);
 }
 
-// hit_slot null: no slot records (the flags are not confirmed afterwards).
+// The position-split scan's work-sharing counters sit behind its hit words,
+// on a 256-byte boundary.
+uint64_t tau_counter_offset(uint64_t n_words) {
+  return cdiv(kPositions * cdiv(n_words, kPositions), kCtrStride) * kCtrStride;
+}
+uint64_t* tau_counters(uint64_t* tau_words, uint64_t n_words) {
+  return tau_words + tau_counter_offset(n_words);
+}
+
+// hit_slot null: no slot records (the flags are not confirmed afterwards). ctr: kTauCounters
+// words, 256-byte aligned, for the work-sharing counters (cleared here).
 int launch_k_scan_tau(uint32_t kind, uint32_t layout, const ImageDesc& d, uint64_t words_per_pos, uint32_t chunk,
                       uint32_t per_cu_cap, const IndexView& ix, uint64_t wt, uint64_t* tau_words, uint32_t* hit_slot,
-                      hipStream_t s) {
+                      uint64_t* ctr, hipStream_t s) {
   const bool crc = kind == CARVE_SIG_CRC64_ISO;
   if (hit_slot) {
     if (crc) launch_k_scan_tau_sig<kSigCrc64, true>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
-                                                     hit_slot, s);
+                                                     hit_slot, ctr, s);
     else launch_k_scan_tau_sig<kSigDjb2, true>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
-                                                hit_slot, s);
+                                                hit_slot, ctr, s);
   } else {
     if (crc) launch_k_scan_tau_sig<kSigCrc64, false>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
-                                                      nullptr, s);
+                                                      nullptr, ctr, s);
     else launch_k_scan_tau_sig<kSigDjb2, false>(layout, d, words_per_pos, chunk, per_cu_cap, ix, wt, tau_words,
-                                                 nullptr, s);
+                                                 nullptr, ctr, s);
   }
   HIP_TRY(hipGetLastError());
   return CARVE_OK;
@@ -1193,7 +1209,8 @@ int launch_scan(carve_scan* sc, const Src& src) {
     const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
     CARVE_TRY(launch_k_scan_tau(idx->sig_kind, idx->layout, one, cdiv(n_words, kPositions), chunk,
                                 per_cu, idx->view(), idx->weights, sc->tau_words.as<uint64_t>(),
-                                sc->hit_slot.as<uint32_t>(), s));
+                                sc->hit_slot.as<uint32_t>(), tau_counters(sc->tau_words.as<uint64_t>(), n_words),
+                                s));
   } else {
     const uint32_t chunk = idx->cfg.tiles_per_chunk ? idx->cfg.tiles_per_chunk : 1;
     CARVE_TRY(launch_k_scan<kFlags>(idx->sig_kind, src, n_words, chunk, per_cu, idx->view(),
@@ -1251,7 +1268,7 @@ int reserve_scan(carve_scan* sc) {
   const bool split = !sc->batch && !sc->fragments && sc->idx && use_split(sc->idx, sc->desc[0].any_tau);
   const uint64_t tau_tiles = cdiv(n_words, kPositions);
   CARVE_TRY(sc->hit_slot.reserve((split ? tau_tiles * kPositions : n_words) * kTileSectors * 4));
-  if (split) CARVE_TRY(sc->tau_words.reserve(kPositions * tau_tiles * 8));
+  if (split) CARVE_TRY(sc->tau_words.reserve((tau_counter_offset(n_words) + kTauCounters) * 8));
   CARVE_TRY(sc->count.reserve(64));
   if (sc->batch) {
     CARVE_TRY(sc->img_of.reserve(n_words * kTileSectors * 4));
@@ -1900,7 +1917,7 @@ extern "C" int scan_image_noalloc(const carve_index* idx, const void* image, uin
   const uint64_t nb = cdiv(n_words, kItemsPerBlock);
   if (use_split(idx, src.d.any_tau)) {   // as scan_image: the position-split scan
     CARVE_TRY(launch_k_scan_tau(idx->sig_kind, idx->layout, src.d, cdiv(n_words, kPositions), chunk, per_cu,
-                                idx->view(), idx->weights, tau_words, nullptr, s));
+                                idx->view(), idx->weights, tau_words, nullptr, offs + kNoAllocMaxChunks, s));
     k_reduce<<<nb, kBlockThreads, 0, s>>>(TauMergeItems{tau_words, cdiv(n_words, kPositions), bitmap, n_words,
                                                         tau0, (uint32_t)(n_sectors % kTileSectors)},
                                           Count{n_words, nullptr}, sums);

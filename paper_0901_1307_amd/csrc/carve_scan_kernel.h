@@ -155,9 +155,10 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4)
 // ------------------------------------------------- position-split scan
 // One image, per-cluster rule, split by cluster position. Workgroups are
 // dispatched to the chip's 8 XCDs in turn (block b runs on XCD b mod 8), so
-// block b scans only the sectors at position p = b mod 8 and probes only
-// position p's slice of the Bloom filter: each XCD's L2 holds one eighth of
-// the filter instead of all of it. Tile k of position p is the sectors
+// block b scans the sectors at position p = b mod 8 and probes position p's
+// slice of the Bloom filter: each XCD's L2 holds one eighth of the filter
+// instead of all of it (until the last tiles, which go to whichever waves are
+// free; see the work sharing below). Tile k of position p is the sectors
 // j = 8(64k + i) + r (i = 0..63, r = (p - tau0) mod 8), 512 B each, one
 // cluster apart; its 64 hit bits go to tau_words[p * words_per_pos + k]
 // (lane i = bit i), to be merged into the ordinary bitmap afterwards.
@@ -167,54 +168,139 @@ __device__ __forceinline__ uint64_t position_count(uint64_t n_sectors, uint32_t 
   return n_sectors > r ? (n_sectors - r + kPositions - 1) / kPositions : 0;
 }
 
+// Work sharing of the position-split scan. A position's tiles go in runs of
+// `chunk`. The first 7/8 of them are fixed: in round k, wave q of the
+// position (of W) takes run kW + q. The rest are handed out by the
+// position's counter (32 bits at the start of the p-th 256-byte line of ctr,
+// zero at launch): a claim that returns c takes run KW + c (K = the fixed
+// rounds). A wave whose position has no run left claims from the next
+// positions in turn, so an XCD that finishes early takes over tiles of one
+// that lags. On the 64 GiB large image with fixed shares only, the waves'
+// finishing times spread over about 1 ms (even XCDs about 0.45 ms behind odd
+// ones, and 0.65 ms within an XCD) and the kernel ended with the last; this
+// scheme took it from 10.58-10.84 to 10.40-10.42 ms with runs of 2 tiles (the
+// same scheme with every run claimed: 10.9-12.0 ms, because adds on one
+// counter serialize at about 22 per microsecond; 3/4 or 15/16 fixed: no better).
+constexpr uint32_t kCtrStride = 32;
+constexpr uint32_t kTauCounters = kPositions * kCtrStride;
+
+struct TauPos {
+  uint32_t p;         // cluster position (its slice of the filter, its hit words)
+  uint32_t r;         // its first sector: j = 8k + r
+  uint64_t count;     // its sectors
+  uint64_t n_tiles;
+  uint64_t n_static;  // rounds of fixed runs (one run per wave of the position each)
+};
+
+__device__ __forceinline__ TauPos tau_pos(uint32_t p, uint64_t n_sectors, uint32_t tau0, uint64_t round_tiles) {
+  TauPos t;
+  t.p = p;
+  t.r = (p - tau0) & (kPositions - 1);
+  t.count = position_count(n_sectors, t.r);
+  t.n_tiles = (t.count + kTileSectors - 1) / kTileSectors;
+  t.n_static = t.n_tiles * 7 / (8 * round_tiles);   // 7/8 of the tiles in fixed runs
+  return t;
+}
+
+// Lane 0 increments position p's counter (32 bits at the start of its line);
+// the result is read later with tau_claim_read, so the atomic's latency hides
+// behind the tile in flight. An increment, not an add: the compiler turns an
+// add into a wave-wide atomic whose result it broadcasts, and waits for, at
+// once.
+__device__ __forceinline__ uint32_t tau_claim_issue(unsigned int* ctr, uint32_t p, uint32_t l) {
+  uint32_t v = 0;
+  if (l == 0) v = atomicInc(ctr + p * (2 * kCtrStride), 0xFFFFFFFFu);
+  return v;
+}
+__device__ __forceinline__ uint64_t tau_claim_read(uint32_t v) {   // lane 0's value, to every lane
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
 // kSlots = false: no slot records (hit_slot unused).
 template <int kSig, int kLayout = kLayoutBucketed, bool kSlots = true>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_scan_tau(
     const uint8_t* __restrict__ image, uint64_t n_sectors, uint32_t tau0, uint64_t words_per_pos, uint32_t chunk,
-    IndexView ix, uint64_t wt, uint64_t* __restrict__ tau_words, uint32_t* __restrict__ hit_slot) {
+    IndexView ix, uint64_t wt, uint64_t* __restrict__ tau_words, uint32_t* __restrict__ hit_slot,
+    unsigned int* __restrict__ ctr) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[kScanWaves * kTileLds];
   // the wave's index, uniform (so tile addresses stay in scalar registers)
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const uint32_t l = lane_id();
   uint8_t* my = lds + w * kTileLds;
-  const uint32_t p = blockIdx.x % kPositions;
-  const uint32_t r = (p - tau0) & (kPositions - 1);
-  const uint64_t count = position_count(n_sectors, r);
-  const uint64_t n_tiles = (count + kTileSectors - 1) / kTileSectors;
-  // this position's slice of the filter
-  const uint64_t* bloom = ix.bloom_tau ? ix.bloom_tau + ((uint64_t)p << ix.log2_bloom_tau) : ix.bloom;
-  const uint32_t log2_bloom = ix.bloom_tau ? ix.log2_bloom_tau : ix.log2_bloom_words;
-  const uint64_t n_waves = (uint64_t)(gridDim.x / kPositions) * kScanWaves;
-  uint64_t g = ((uint64_t)(blockIdx.x / kPositions) * kScanWaves + w) * chunk;
-  if (g >= n_tiles) return;
-  auto next_of = [&](uint64_t t) {
-    return ((t + 1) % chunk != 0) ? t + 1 : t + 1 + (n_waves - 1) * chunk;
-  };
-  auto rows_of = [&](uint64_t k) {
-    const uint64_t first = k * kTileSectors;   // its first cluster among this position's
-    const uint64_t rem = count - first;
-    return ClusterStrideRows{image + (first * kPositions + r) * kSectorBytes,
+  const uint64_t n_waves = (uint64_t)(gridDim.x / kPositions) * kScanWaves;   // per position
+  const uint64_t q = (uint64_t)(blockIdx.x / kPositions) * kScanWaves + w;
+  auto rows_of = [&](const TauPos& t, uint64_t k) {
+    const uint64_t first = k * kTileSectors;   // its first cluster among the position's
+    const uint64_t rem = t.count - first;
+    return ClusterStrideRows{image + (first * kPositions + t.r) * kSectorBytes,
                              rem >= kTileSectors ? kTileSectors : (uint32_t)rem};
   };
-  ClusterStrideRows tr = rows_of(g);
+  // A run claimed from position t's counter (c) or, once t has none left,
+  // from the next positions; false when every position is done.
+  const uint64_t round_tiles = n_waves * chunk;
+  uint32_t visited = 1;
+  auto claim_from = [&](TauPos& t, uint64_t c, uint64_t& g, uint64_t& end) {
+    while (true) {
+      g = (t.n_static * n_waves + c) * chunk;
+      end = g + chunk;
+      if (g < t.n_tiles) return true;
+      if (visited == kPositions) return false;
+      t = tau_pos((t.p + 1) & (kPositions - 1), n_sectors, tau0, round_tiles);
+      ++visited;
+      c = tau_claim_read(tau_claim_issue(ctr, t.p, l));
+    }
+  };
+  TauPos cur = tau_pos(blockIdx.x % kPositions, n_sectors, tau0, round_tiles);
+  uint64_t k = 0;          // the wave's fixed run of its own position
+  bool fixed = cur.n_static > 0;
+  uint64_t g = q * chunk, end = g + chunk;
+  if (!fixed && !claim_from(cur, tau_claim_read(tau_claim_issue(ctr, cur.p, l)), g, end)) return;
+  ClusterStrideRows tr = rows_of(cur, g);
   PhaseRegs A, B;
   load_phase<true>(tr, 0, A);
   while (true) {
-    const uint64_t gn = next_of(g);
-    const bool more = gn < n_tiles;
-    const ClusterStrideRows tn = more ? rows_of(gn) : tr;
-    auto prefetch = [&](PhaseRegs& R) { load_phase<true>(tn, 0, R); };   // unconditionally, as in k_scan
+    // the next tile: the rest of this run, else the wave's next fixed run,
+    // else a claim issued now and read when the next tile's first loads are due
+    const bool in_run = g + 1 < end && g + 1 < cur.n_tiles;
+    const bool next_fixed = !in_run && fixed && k + 1 < cur.n_static;
+    const bool claim = !in_run && !next_fixed;
+    const uint32_t pending = claim ? tau_claim_issue(ctr, cur.p, l) : 0u;
+    TauPos nxt = cur;
+    uint64_t gn = g + 1, end_n = end;
+    bool more = true;
+    ClusterStrideRows tn = tr;
+    auto prefetch = [&](PhaseRegs& R) {   // unconditionally, as in k_scan
+      if (next_fixed) {
+        gn = ((k + 1) * n_waves + q) * chunk;
+        end_n = gn + chunk;
+      } else if (claim) {
+        // an empty asm that takes the claim's register here, so the compiler
+        // waits for the atomic at this point and not where it was issued
+        uint32_t c = pending;
+        asm volatile("" : "+v"(c));
+        more = claim_from(nxt, tau_claim_read(c), gn, end_n);
+      }
+      if (more) tn = rows_of(nxt, gn);
+      load_phase<true>(tn, 0, R);
+    };
     uint64_t h;
     if constexpr (kSig == kSigCrc64)
       h = tile_crc_pipelined<true>(tr, my, A, B, prefetch);
     else
       h = tile_signature_pipelined<true>(tr, my, wt, A, B, prefetch);
+    // this position's slice of the filter
+    const uint64_t* bloom = ix.bloom_tau ? ix.bloom_tau + ((uint64_t)cur.p << ix.log2_bloom_tau) : ix.bloom;
+    const uint32_t log2_bloom = ix.bloom_tau ? ix.log2_bloom_tau : ix.log2_bloom_words;
     uint64_t hits = tile_probe<kLayout, kPositions, kSlots>(
-        ix, h, p, false, kSlots ? hit_slot + (g * kTileSectors * kPositions + r) : nullptr, bloom, log2_bloom);
+        ix, h, cur.p, false, kSlots ? hit_slot + (g * kTileSectors * kPositions + cur.r) : nullptr, bloom, log2_bloom);
     if (tr.n_valid < kTileSectors) hits &= (1ull << tr.n_valid) - 1ull;
-    if (l == 0) tau_words[p * words_per_pos + g] = hits;
+    if (l == 0) tau_words[cur.p * words_per_pos + g] = hits;
     if (!more) break;
+    if (next_fixed) ++k;
+    if (claim) fixed = false;
+    cur = nxt;
     g = gn;
+    end = end_n;
     tr = tn;
   }
 }
