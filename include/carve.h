@@ -350,7 +350,7 @@ void ingest_free(carve_ingest* in);   /* NULL is a no-op; waits for transfers an
  * scan_image_noalloc -- scan_image followed by flagged_sectors into device
  * memory, for callers that cannot allocate (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc). It allocates nothing:
- * its work buffers are one fixed device array of the library, 32 MiB + 32 KiB,
+ * its work buffers are one fixed device array of the library, 32 MiB + 34 KiB,
  * that every GPU running the library holds until the process ends. It records
  * no confirmation data (there is no scan object for confirm_matches).
  *   idx, image, n_bytes, tau0, tau_mode, stream   as scan_image; at most 2^27
