@@ -108,7 +108,8 @@ typedef struct {
 
 typedef struct {
   uint32_t blocks_per_cu;   /* work-groups of the persistent scan grid per compute unit; 0 = as many as fit */
-  uint32_t tiles_per_chunk; /* consecutive 64-sector tiles a wave takes before striding; 0 = 1 */
+  uint32_t tiles_per_chunk; /* consecutive 64-sector tiles a wave takes before striding (the split walk also
+                               hands out the last eighth of each position's tiles in runs of this length); 0 = 1 */
   uint32_t split;           /* carve_split_mode: how scans of one image under the per-cluster rule walk it */
   uint32_t reserved;        /* must be zero */
 } carve_scan_config;
